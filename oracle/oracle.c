@@ -1,0 +1,158 @@
+/*
+ * oracle.c -- plain FP64 CPU reference for the batched dense contraction
+ * and its degenerate case, dense GEMM.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark do.  It shares no code, header, table or helper with the
+ * GPU path.
+ *
+ * What it computes (Klöckner, "Loo.py: transformation-based code generation
+ * for GPUs and CPUs", ARRAY'14):
+ *
+ *   - the reduction  sum(j, D[k,i,j] * u[e,j])  written in the paper's
+ *     reduction syntax (sec. 2.1, "Reductions are allowed"), i.e. the
+ *     element-local operator application behind Table 1's "dG FEM volume"
+ *     row:   out[k,e,i] = sum_j D[k][i][j] * u[e][j];
+ *   - its degenerate case C[m,n] = sum_k A[m,k]*B[k,n], the paper's own
+ *     reduction example sum(k, a[i,k]*b[k,j]) and Table 1's "sgemm" row.
+ *
+ * Every transformation the method offers (tiling, prefetch, unrolling,
+ * data-layout change) preserves this result up to summation order, because
+ * the programming model is unordered (sec. 2.3): a program must give a
+ * valid result for any traversal order.  So the oracle is the definition
+ * itself: a plain loop, FP64 accumulation, j in increasing order.
+ *
+ * Precision modes.  The paper generates code for the runtime type of the
+ * arguments (sec. 2.1/2.2: one variant per type combination) and leaves
+ * semantics-changing choices to the user.  Reduced-precision products are
+ * such a user choice; the oracle emulates them by rounding the operands
+ * the same way before the exact FP64 product:
+ *   PREC_FP32   : D * u
+ *   PREC_BF16   : bf16(D) * bf16(u)
+ *   PREC_BF16X3 : hi_D*hi_u + hi_D*lo_u + lo_D*hi_u,
+ *                 hi = bf16(x), lo = bf16(x - hi)   (lo*lo dropped)
+ * bf16() is round-to-nearest-even on the FP32 bit pattern.
+ *
+ * Layouts (sec. 2.4.3, array-axis implementation tags):
+ *   LAYOUT_EM (element-major): u[e*Np + j],  out[(k*E + e)*Np + i]
+ *   LAYOUT_DM (DOF-major)    : u[j*E + e],   out[(k*Np + i)*E + e]
+ * The oracle's output is always the chunk ref[k][e - e0][i] (FP64) for
+ * e in [e0, e0 + ne), whatever the input layout, so a caller can compare
+ * a huge GPU output chunk by chunk or at sampled elements.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define PREC_FP32 0
+#define PREC_BF16 1
+#define PREC_BF16X3 2
+#define LAYOUT_EM 0
+#define LAYOUT_DM 1
+
+int oracle_version(void) { return 1; }
+
+int oracle_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/* Round an FP32 value to the nearest bfloat16 (ties to even), returned as
+ * the FP32 value it represents.  bfloat16 keeps the sign, the 8 exponent
+ * bits and the top 7 mantissa bits of an IEEE binary32, so rounding is done
+ * on the low 16 bits of the pattern.  NaN stays NaN (made quiet). */
+float oracle_bf16_rne(float x) {
+    uint32_t b;
+    memcpy(&b, &x, sizeof b);
+    if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu) != 0) {
+        b = (b | 0x00400000u) & 0xffff0000u;  /* quiet NaN, top payload */
+    } else {
+        uint32_t low = b & 0xffffu;
+        uint32_t keep = b & 0xffff0000u;
+        uint32_t lsb = (keep >> 16) & 1u;
+        if (low > 0x8000u || (low == 0x8000u && lsb)) keep += 0x10000u;
+        b = keep;                     /* a carry into the exponent is right */
+    }
+    float r;
+    memcpy(&r, &b, sizeof r);
+    return r;
+}
+
+/* hi = bf16(x); lo = bf16(x - hi).  x - hi is exact in FP32 (hi shares
+ * x's exponent range and the difference fits in the mantissa). */
+void oracle_split_bf16(const float* x, float* hi, float* lo, long n) {
+    for (long t = 0; t < n; ++t) {
+        float h = oracle_bf16_rne(x[t]);
+        hi[t] = h;
+        lo[t] = oracle_bf16_rne(x[t] - h);
+    }
+}
+
+/* The product a*b under a precision mode, evaluated exactly in FP64
+ * (a product of two FP32 values has at most 48 significant bits). */
+static double prod(float a, float b, int precision) {
+    if (precision == PREC_FP32) return (double)a * (double)b;
+    if (precision == PREC_BF16)
+        return (double)oracle_bf16_rne(a) * (double)oracle_bf16_rne(b);
+    float ah = oracle_bf16_rne(a), bh = oracle_bf16_rne(b);
+    float al = oracle_bf16_rne(a - ah), bl = oracle_bf16_rne(b - bh);
+    return (double)ah * (double)bh + (double)ah * (double)bl +
+           (double)al * (double)bh;
+}
+
+/* ref[k][e - e0][i] = sum_{j=0}^{Np-1} D[k][i][j] * u(e, j), FP64. */
+void oracle_contract(int K, int Np, long E, int layout, int precision,
+                     const float* D, const float* u, long e0, long ne,
+                     double* ref) {
+    if (K <= 0 || Np <= 0 || ne <= 0) return;
+#pragma omp parallel for schedule(static)
+    for (long de = 0; de < ne; ++de) {
+        long e = e0 + de;
+        for (int k = 0; k < K; ++k) {
+            const float* Dk = D + (long)k * Np * Np;
+            for (int i = 0; i < Np; ++i) {
+                double acc = 0.0;
+                for (int j = 0; j < Np; ++j) {
+                    float uej = (layout == LAYOUT_EM) ? u[e * Np + j]
+                                                      : u[(long)j * E + e];
+                    acc += prod(Dk[(long)i * Np + j], uej, precision);
+                }
+                ref[((long)k * ne + de) * Np + i] = acc;
+            }
+        }
+    }
+}
+
+/* C[m - m0][n] = sum_{k=0}^{Kd-1} A[m][k] * B[k][n], A (M x Kd) and
+ * B (Kd x N) row-major, FP64, for m in [m0, m0 + nm). */
+void oracle_gemm(long M, long N, long Kd, int precision, const float* A,
+                 const float* B, long m0, long nm, double* C) {
+    (void)M;
+    if (nm <= 0 || N <= 0) return;
+#pragma omp parallel for schedule(static)
+    for (long dm = 0; dm < nm; ++dm) {
+        long m = m0 + dm;
+        double* Crow = C + dm * N;
+        for (long n = 0; n < N; ++n) Crow[n] = 0.0;
+        for (long k = 0; k < Kd; ++k) {
+            float a = A[m * Kd + k];
+            const float* Brow = B + k * N;
+            for (long n = 0; n < N; ++n) Crow[n] += prod(a, Brow[n], precision);
+        }
+    }
+}

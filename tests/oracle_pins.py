@@ -1,0 +1,255 @@
+"""Pins of the FP64 oracle against facts fixed by the mathematics and by
+independent library routines, not by the oracle itself.
+
+Each pin takes an ``oracle.Oracle`` handle, so the same checks run against
+the real oracle (must pass) and against deliberately mutated builds of it
+(each mutant must fail at least one pin).  The contraction is the reduction
+sum(j, D[k,i,j]*u[e,j]) of the paper's sec. 2.1; GEMM is its sum(k,
+a[i,k]*b[k,j]) example.
+"""
+from fractions import Fraction
+
+import numpy as np
+import torch
+
+from paper_1405_7470_amd import inputs
+
+
+def _bf16_lib(x):
+    """bfloat16 rounding by torch (round-to-nearest-even), an independent
+    library routine, returned as float32."""
+    t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32))
+    return t.to(torch.bfloat16).to(torch.float32).numpy()
+
+
+def _operands(x, precision):
+    """Operand pieces per precision mode, rounded by the library routine."""
+    x = np.asarray(x, dtype=np.float32)
+    if precision == "fp32":
+        return x, None
+    hi = _bf16_lib(x)
+    if precision == "bf16":
+        return hi, None
+    lo = _bf16_lib((x - hi).astype(np.float32))  # exact FP32 subtraction
+    return hi, lo
+
+
+def _exact_contract(D, u, layout, precision):
+    """Exact rational value of the contraction under a precision mode."""
+    K, Np, _ = D.shape
+    E = u.shape[0] if layout == "em" else u.shape[1]
+    ue = u if layout == "em" else u.T
+    Dh, Dl = _operands(D, precision)
+    uh, ul = _operands(ue, precision)
+    out = np.empty((K, E, Np), dtype=object)
+    for k in range(K):
+        for e in range(E):
+            for i in range(Np):
+                s = Fraction(0)
+                for j in range(Np):
+                    s += Fraction(float(Dh[k, i, j])) * Fraction(float(uh[e, j]))
+                    if precision == "bf16x3":
+                        s += Fraction(float(Dh[k, i, j])) * Fraction(float(ul[e, j]))
+                        s += Fraction(float(Dl[k, i, j])) * Fraction(float(uh[e, j]))
+                out[k, e, i] = s
+    return out
+
+
+def _assert_close_exact(ref, exact, Np):
+    """FP64 accumulation of exact products: error <= Np * 2^-52 * sum|terms|,
+    bounded here by Np * 2^-52 * (max|exact| + slack) using term magnitudes."""
+    diff = max(abs(Fraction(float(r)) - x) for r, x in zip(ref.ravel(), exact.ravel()))
+    scale = max(abs(x) for x in exact.ravel()) + 1
+    assert diff <= Fraction(Np * 4) * Fraction(2) ** -52 * scale * 16, float(diff)
+
+
+def pin_contract_bruteforce(o):
+    """Tiny random shapes, every precision and layout, against exact rational
+    sums (FP32 products are exact in FP64, so only FP64 rounding remains)."""
+    rng = np.random.default_rng(11)
+    for (K, Np, E) in [(1, 1, 1), (2, 3, 5), (3, 5, 7), (2, 4, 3)]:
+        D = rng.normal(0, 1, (K, Np, Np)).astype(np.float32)
+        u = rng.uniform(-1, 1, (E, Np)).astype(np.float32)
+        for precision in ("fp32", "bf16", "bf16x3"):
+            exact = _exact_contract(D, u, "em", precision)
+            for layout in ("em", "dm"):
+                uu = u if layout == "em" else np.ascontiguousarray(u.T)
+                ref = o.contract(D, uu, layout, precision)
+                _assert_close_exact(ref, exact, Np)
+
+
+def pin_contract_identity(o):
+    """D_k = I gives out = u exactly (both layouts)."""
+    K, Np, E = 3, 7, 33
+    _, u = inputs.contraction_inputs(K, Np, E, seed=3)
+    D = np.stack([np.eye(Np, dtype=np.float32)] * K)
+    for layout in ("em", "dm"):
+        uu = u if layout == "em" else np.ascontiguousarray(u.T)
+        ref = o.contract(D, uu, layout, "fp32")
+        for k in range(K):
+            assert np.array_equal(ref[k], u.astype(np.float64))
+
+
+def pin_contract_ones(o):
+    """All-ones D gives every output row the sum of the element's values;
+    a permuted identity picks out one column."""
+    K, Np, E = 2, 6, 19
+    rng = np.random.default_rng(5)
+    u = rng.integers(-50, 51, (E, Np)).astype(np.float32)
+    D = np.ones((K, Np, Np), dtype=np.float32)
+    ref = o.contract(D, u, "em", "fp32")
+    rows = u.astype(np.float64).sum(axis=1)
+    for k in range(K):
+        for i in range(Np):
+            assert np.array_equal(ref[k, :, i], rows)
+    perm = rng.permutation(Np)
+    P = np.zeros((1, Np, Np), dtype=np.float32)
+    P[0, np.arange(Np), perm] = 1.0          # row i picks column perm[i]
+    ref = o.contract(P, u, "em", "fp32")
+    assert np.array_equal(ref[0], u[:, perm].astype(np.float64))
+
+
+def pin_contract_rank1(o):
+    """u(e, j) = a_e b_j gives out(k, e, i) = a_e (D_k b)_i (integers, exact)."""
+    rng = np.random.default_rng(9)
+    K, Np, E = 2, 9, 12
+    a = rng.integers(-6, 7, E).astype(np.float64)
+    b = rng.integers(-6, 7, Np).astype(np.float64)
+    D = rng.integers(-5, 6, (K, Np, Np)).astype(np.float32)
+    u = np.outer(a, b).astype(np.float32)
+    ref = o.contract(D, u, "em", "fp32")
+    for k in range(K):
+        Db = np.array([sum(float(D[k, i, j]) * b[j] for j in range(Np)) for i in range(Np)])
+        assert np.array_equal(ref[k], np.outer(a, Db))
+
+
+def pin_contract_zero_and_linearity(o):
+    K, Np, E = 2, 8, 21
+    rng = np.random.default_rng(13)
+    D = rng.integers(-7, 8, (K, Np, Np)).astype(np.float32)
+    u = rng.integers(-7, 8, (E, Np)).astype(np.float32)
+    v = rng.integers(-7, 8, (E, Np)).astype(np.float32)
+    assert not np.any(o.contract(np.zeros_like(D), u, "em", "fp32"))
+    lhs = o.contract(D, (3 * u - 2 * v).astype(np.float32), "em", "fp32")
+    rhs = 3 * o.contract(D, u, "em", "fp32") - 2 * o.contract(D, v, "em", "fp32")
+    assert np.array_equal(lhs, rhs)
+
+
+def pin_contract_layouts_and_chunks(o):
+    """Element-major and DOF-major storage of the same values give the same
+    result; chunked evaluation equals the whole."""
+    K, Np, E = 3, 11, 40
+    D, u = inputs.contraction_inputs(K, Np, E, seed=21)
+    a = o.contract(D, u, "em", "fp32")
+    b = o.contract(D, np.ascontiguousarray(u.T), "dm", "fp32")
+    assert np.array_equal(a, b)
+    parts = [o.contract(D, u, "em", "fp32", e0, n) for e0, n in ((0, 13), (13, 1), (14, 26))]
+    assert np.array_equal(np.concatenate(parts, axis=1), a)
+
+
+def pin_contract_integer_all_precisions(o):
+    """Integer operands |x| <= 8 are exact in bf16, so every precision mode
+    gives the exact integer result (lo parts vanish)."""
+    K, Np, E = 3, 10, 25
+    D, u = inputs.integer_contraction_inputs(K, Np, E, seed=4)
+    exact = np.einsum("kij,ej->kei", D.astype(np.int64), u.astype(np.int64))
+    for precision in ("fp32", "bf16", "bf16x3"):
+        assert np.array_equal(o.contract(D, u, "em", precision), exact.astype(np.float64))
+
+
+def pin_bf16_rounding(o):
+    """bf16 rounding agrees with torch's round-to-nearest-even conversion on
+    random values over many binades and on special values."""
+    rng = np.random.default_rng(17)
+    x = (rng.standard_normal(200000) * np.exp2(rng.integers(-130, 120, 200000))).astype(np.float32)
+    base = np.float32(1.0)
+    ulp = np.float32(2.0 ** -7)
+    specials = np.array([0.0, -0.0, 1.0, -1.0, 3.0e38, -3.0e38, 3.3895314e38, 1e-40, -1e-40,
+                         np.inf, -np.inf,
+                         base + ulp / 2, base + 3 * ulp / 2, base + ulp / 2 + 2.0 ** -20,
+                         -(base + ulp / 2), 2.0 ** -126, 2.0 ** -133 * 3],
+                        dtype=np.float32)
+    for arr in (x, specials):
+        mine = o.bf16_rne(arr)
+        lib = _bf16_lib(arr)
+        assert np.array_equal(mine.view(np.uint32), lib.view(np.uint32))
+    nan = o.bf16_rne(np.array([np.nan], dtype=np.float32))
+    assert np.isnan(nan[0])
+    # ties go to even: 1 + 2^-8 -> 1 ; 1 + 3*2^-8 -> 1 + 2^-6
+    t = o.bf16_rne(np.array([1 + 2 ** -8, 1 + 3 * 2 ** -8], dtype=np.float32))
+    assert t[0] == 1.0 and t[1] == 1 + 2 ** -6
+
+
+def pin_split_bf16(o):
+    """hi and lo are bf16 values; x - hi is exact in FP32 and hi + lo
+    approximates x to 2^-16 relative."""
+    rng = np.random.default_rng(19)
+    x = rng.standard_normal(100000).astype(np.float32)
+    hi, lo = o.split_bf16(x)
+    assert not np.any(hi.view(np.uint32) & 0xFFFF)
+    assert not np.any(lo.view(np.uint32) & 0xFFFF)
+    assert np.array_equal(hi, _bf16_lib(x))
+    assert np.array_equal(lo, _bf16_lib((x - hi).astype(np.float32)))
+    err = np.abs(x.astype(np.float64) - hi - lo)
+    assert np.all(err <= 2.0 ** -16 * np.abs(x))
+
+
+def pin_precision_error_bands(o):
+    """Reduced-precision modes sit in their error bands against the exact
+    FP32-operand sum: bf16 ~1e-3 (8-bit operands), bf16x3 ~1e-6..1e-5."""
+    K, Np, E = 3, 56, 3000
+    D, u = inputs.contraction_inputs(K, Np, E, seed=23)
+    r32 = o.contract(D, u, "em", "fp32")
+    den = np.max(np.abs(r32))
+    e1 = np.max(np.abs(o.contract(D, u, "em", "bf16") - r32)) / den
+    e3 = np.max(np.abs(o.contract(D, u, "em", "bf16x3") - r32)) / den
+    assert 1e-4 < e1 < 2e-2, e1
+    assert 1e-7 < e3 < 1e-5, e3
+
+
+def pin_gemm(o):
+    rng = np.random.default_rng(29)
+    # tiny: exact rational sums
+    A = rng.normal(0, 1, (3, 5)).astype(np.float32)
+    B = rng.normal(0, 1, (5, 4)).astype(np.float32)
+    C = o.gemm(A, B)
+    for m in range(3):
+        for n in range(4):
+            ex = sum(Fraction(float(A[m, k])) * Fraction(float(B[k, n])) for k in range(5))
+            assert abs(Fraction(float(C[m, n])) - ex) <= Fraction(2) ** -48 * (abs(ex) + 1)
+    # numpy float64 matmul (library routine) on a non-square case
+    A, B = inputs.gemm_inputs(37, 53, 71, seed=2)
+    C = o.gemm(A, B)
+    ref = A.astype(np.float64) @ B.astype(np.float64)
+    assert np.max(np.abs(C - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # identity and integer exactness
+    I = np.eye(53, dtype=np.float32)
+    Bs = np.ascontiguousarray(B[:53])
+    assert np.array_equal(o.gemm(I, Bs), Bs.astype(np.float64))
+    Ai, Bi = inputs.integer_gemm_inputs(19, 23, 31, seed=6)
+    exact = Ai.astype(np.int64) @ Bi.astype(np.int64)
+    for precision in ("fp32", "bf16", "bf16x3"):
+        assert np.array_equal(o.gemm(Ai, Bi, precision), exact.astype(np.float64))
+    # row chunks
+    full = o.gemm(A, B)
+    assert np.array_equal(np.concatenate([o.gemm(A, B, "fp32", 0, 10), o.gemm(A, B, "fp32", 10, 27)]), full)
+    # bf16x3 error band on a GEMM
+    A, B = inputs.gemm_inputs(64, 64, 512, seed=8)
+    r = o.gemm(A, B)
+    e3 = np.max(np.abs(o.gemm(A, B, "bf16x3") - r)) / np.max(np.abs(r))
+    assert 1e-8 < e3 < 1e-5, e3
+
+
+ALL_PINS = [
+    pin_contract_bruteforce,
+    pin_contract_identity,
+    pin_contract_ones,
+    pin_contract_rank1,
+    pin_contract_zero_and_linearity,
+    pin_contract_layouts_and_chunks,
+    pin_contract_integer_all_precisions,
+    pin_bf16_rounding,
+    pin_split_bf16,
+    pin_precision_error_bands,
+    pin_gemm,
+]
