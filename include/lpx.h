@@ -1,0 +1,210 @@
+/*
+ * lpx.h -- C ABI of liblpx: code variants of the batched dense contraction
+ *
+ *     out[k,e,i] = sum_j D[k][i][j] * u[e][j]
+ *
+ * and of its degenerate case, dense GEMM, on AMD Instinct MI355X (gfx950).
+ *
+ * Background (Klöckner, "Loo.py: transformation-based code generation for
+ * GPUs and CPUs", ARRAY'14):
+ *   - the computation is a reduction in the paper's sense (sec. 2.1,
+ *     sum(j, D[k,i,j]*u[e,j])); Table 1's "dG FEM volume" and "sgemm" rows
+ *     are the workloads it stands for;
+ *   - the paper's point is that the instructions, the loop bounds and the
+ *     explicitly invoked transformations together fix the generated code
+ *     (sec. 1).  Here the transformations are an explicit, immutable value,
+ *     the transformation record (lpx_record), passed with every call; each
+ *     legal record selects one precompiled gfx950 kernel instance;
+ *   - size parameters are plain arguments, as the paper's kernel
+ *     parameters are (sec. 2.1), and every call is enqueued on a stream and
+ *     returns before the work finishes, as a kernel call on an OpenCL queue
+ *     does (sec. 2.2);
+ *   - kernels are compiled ahead of time and callable from any host program
+ *     (sec. 1): this header has no dependency beyond <stdint.h>/<stddef.h>.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named as "device" are HIP device pointers (global memory of
+ *     the current device); "host" pointers are ordinary host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - The caller owns every buffer it passes and keeps it alive until the
+ *     stream has passed the enqueued work.
+ *   - Arguments are validated before any HIP call; on error nothing is
+ *     enqueued, no output is written, and lpx_last_error() describes the
+ *     failure.  No function aborts or throws.
+ *   - A problem with a zero size (K, Np or E equal to 0) is a successful
+ *     no-op, like a loop whose upper bound lies below its lower bound
+ *     (sec. 2.2's generated loop runs zero times for n = 0).
+ */
+#ifndef LPX_H
+#define LPX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+typedef int32_t lpx_status;
+#define LPX_OK 0
+#define LPX_ERR_INVALID_ARG 1 /* NULL/misaligned pointer, negative or     */
+                              /* overflowing size, malformed record       */
+#define LPX_ERR_UNSUPPORTED 2 /* legal record not built for this shape    */
+                              /* (e.g. LDS staging does not fit, Np > 128) */
+#define LPX_ERR_ASSUMPTION 3  /* a record's assumption is false for shape */
+#define LPX_ERR_ALIAS 4       /* output overlaps an input                 */
+#define LPX_ERR_HIP 5         /* HIP runtime/launch error (text kept)     */
+#define LPX_ERR_MODEL 6       /* picker model missing/corrupt/version     */
+#define LPX_ERR_NOT_TUNED 7   /* no tuning result cached for the shape    */
+#define LPX_ERR_INTERNAL 8
+
+/* ------------------------------------------------------------- enums */
+/* Arithmetic of the products (a semantics-changing choice the caller opts
+ * into; the paper leaves such choices to the user, sec. 1). Accumulation is
+ * always FP32.
+ *   FP32   : FP32 operands, FP32 MFMA.
+ *   BF16   : operands rounded to bfloat16 (nearest-even), BF16 MFMA.
+ *   BF16X3 : x = hi + lo with hi = bf16(x), lo = bf16(x - hi); each product
+ *            as hi*hi + hi*lo + lo*hi (lo*lo dropped), BF16 MFMA.        */
+#define LPX_FP32 0
+#define LPX_BF16 1
+#define LPX_BF16X3 2
+
+/* Storage of u and out (sec. 2.4.3, array-axis implementation tags; the
+ * structure-of-arrays / array-of-structures switch):
+ *   ELEMENT_MAJOR: u[e*Np + j],  out[(k*E + e)*Np + i]
+ *   DOF_MAJOR    : u[j*E + e],   out[(k*Np + i)*E + e]
+ * D is always D[(k*Np + i)*Np + j].                                     */
+#define LPX_ELEMENT_MAJOR 0
+#define LPX_DOF_MAJOR 1
+
+/* ------------------------------------------------ transformation record */
+#define LPX_RECORD_VERSION 1u
+
+/* One code variant.  Every field is one transformation of sec. 2.4:
+ *   tile_e   : split_iname(e, tile_e) with the outer index mapped to the
+ *              work-group grid axis (sec. 2.4.1 eq. (1), sec. 2.4.2);
+ *              16, 32 or 64 elements per work-group tile.  Inside a tile,
+ *              e is split again by 16 (the MFMA column block) and i by 16
+ *              (the MFMA row block); the (k, i-block) pairs of a 16-element
+ *              block are spread over the work-group's four wavefronts.
+ *   prefetch : 0 = MFMA operands are loaded from global memory straight
+ *              into registers; 1 = add_prefetch (sec. 2.4.4): the u tile
+ *              and all of D are staged in LDS (converted to the operand
+ *              precision on the way) before the reduction, with the
+ *              work-group barrier the paper's precompute inserts.
+ *   unroll   : 1, 2 or 4; the reduction loop over MFMA k-steps is split by
+ *              `unroll` and the inner part unrolled (tag "unr", sec. 2.4.2).
+ *   precision: LPX_FP32 / LPX_BF16 / LPX_BF16X3.
+ *   assume_tile_divides: 1 asserts E % tile_e == 0 (an assumption in the
+ *              sense of sec. 2.1); a call whose E violates it fails with
+ *              LPX_ERR_ASSUMPTION instead of computing.
+ *   gemm_tm, gemm_tn, gemm_tk: GEMM macro tile (rows of C, columns of C,
+ *              reduction depth staged per step); 0 = library default.
+ * Records are plain values (the paper's kernels are immutable, sec. 2.4):
+ * the library never modifies one it is given.                          */
+typedef struct lpx_record {
+    uint32_t version;
+    uint8_t precision;
+    uint8_t tile_e;
+    uint8_t prefetch;
+    uint8_t unroll;
+    uint8_t assume_tile_divides;
+    uint8_t reserved0[3];
+    uint16_t gemm_tm;
+    uint16_t gemm_tn;
+    uint16_t gemm_tk;
+    uint16_t reserved1;
+} lpx_record;
+
+/* The problem a record is chosen for. */
+typedef struct lpx_problem {
+    int32_t K;
+    int32_t Np;
+    int64_t E;
+    int32_t layout;    /* LPX_ELEMENT_MAJOR / LPX_DOF_MAJOR */
+    int32_t precision; /* the caller's accuracy class      */
+} lpx_problem;
+
+/* -------------------------------------------------------- contraction */
+typedef struct lpx_contract_desc {
+    int32_t K;        /* number of operators, >= 0                      */
+    int32_t Np;       /* operator order (nodes per element), 0..128     */
+    int64_t E;        /* number of elements, >= 0                       */
+    int32_t layout;   /* LPX_ELEMENT_MAJOR / LPX_DOF_MAJOR              */
+    int32_t reserved; /* must be 0                                      */
+    const float* D;   /* device, K*Np*Np floats, 16-byte aligned        */
+    const float* u;   /* device, E*Np floats, 16-byte aligned           */
+    float* out;       /* device, K*E*Np floats, 16-byte aligned; must   */
+                      /* not overlap D or u                             */
+} lpx_contract_desc;
+
+/* ------------------------------------------------------ support calls */
+/* Library version string, e.g. "lpx 0.1.0 gfx950". */
+const char* lpx_version(void);
+
+/* Static text for a status code. */
+const char* lpx_status_string(lpx_status s);
+
+/* Text of the last failure on the calling thread ("" if none).  Valid until
+ * the next lpx call on this thread. */
+const char* lpx_last_error(void);
+
+/* The untuned default record for a precision: tile_e = 16, prefetch = 0,
+ * unroll = 1 (one 16x16 output block per MFMA chain, operands straight from
+ * global memory), GEMM tiles 0 (library default).  `out` is host memory. */
+lpx_status lpx_record_default(int32_t precision, lpx_record* out);
+
+/* Checks a record's fields (version, ranges); LPX_OK if well formed. */
+lpx_status lpx_record_validate(const lpx_record* rec);
+
+/* Human-readable one-line description of a record, NUL-terminated, into
+ * the host buffer `buf` of `len` bytes (truncated if short). */
+lpx_status lpx_record_describe(const lpx_record* rec, char* buf, size_t len);
+
+/* The candidate records of a problem in canonical order: precision fixed to
+ * p->precision, then tile_e in {16,32,64} (outer), prefetch in {0,1},
+ * unroll in {1,2,4} (inner): 18 records.  Writes min(cap, 18) records to
+ * the host array `recs` and the total count to *n. */
+lpx_status lpx_record_enumerate(const lpx_problem* p, lpx_record* recs,
+                                int32_t cap, int32_t* n);
+
+/* Dynamic LDS bytes one work-group of the record's kernel uses for the
+ * problem (0 when prefetch = 0); LPX_ERR_UNSUPPORTED if it exceeds the
+ * gfx950 limit, which is what lpx_contract would return. */
+lpx_status lpx_contract_lds_bytes(const lpx_problem* p, const lpx_record* rec,
+                                  int64_t* bytes);
+
+/* ------------------------------------------------------- entry points */
+/* Batched dense contraction  out[k,e,i] = sum_j D[k][i][j] u[e][j]
+ * (the reduction of sec. 2.1 applied per element; Table 1 "dG FEM
+ * volume"), enqueued on `stream`.  `rec` selects the code variant; NULL
+ * means the untuned default of precision FP32.  Every output element is
+ * written exactly once; nothing outside `out` is written.  Summation order
+ * is the variant's own (the programming model is unordered, sec. 2.3), so
+ * results of different records agree to rounding, and bit for bit when all
+ * partial sums are exact. */
+lpx_status lpx_contract(const lpx_contract_desc* c, const lpx_record* rec,
+                        void* stream);
+
+/* Runs every check lpx_contract makes before enqueueing (arguments,
+ * record, assumption, aliasing, LDS budget) and returns the status
+ * lpx_contract would return for them, without any HIP call and without
+ * reading through the pointers.  Device-dependent failures (LPX_ERR_HIP)
+ * can still occur in lpx_contract after this returns LPX_OK. */
+lpx_status lpx_contract_validate(const lpx_contract_desc* c, const lpx_record* rec);
+
+/* Split-precision conversion: hi[t] = bf16(x[t]), lo[t] = bf16(x[t] -
+ * float(hi[t])), round-to-nearest-even, as raw bfloat16 bit patterns.
+ * x, hi, lo are device pointers of n elements (x 4-byte, hi/lo 2-byte
+ * aligned); hi and lo must not overlap x or each other.  This is the
+ * operand transformation behind LPX_BF16 (hi only) and LPX_BF16X3. */
+lpx_status lpx_split_bf16(const float* x, uint16_t* hi, uint16_t* lo,
+                          int64_t n, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LPX_H */

@@ -1,0 +1,314 @@
+// Host side of the C ABI: validation, records, error reporting, dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "lpx_internal.h"
+
+namespace lpx {
+
+namespace {
+thread_local char g_last_error[512] = "";
+}
+
+lpx_status set_error(lpx_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+void clear_error() { g_last_error[0] = '\0'; }
+
+const char* last_error_text() { return g_last_error; }
+
+lpx_record default_record(int precision) {
+    lpx_record r;
+    std::memset(&r, 0, sizeof r);
+    r.version = LPX_RECORD_VERSION;
+    r.precision = (uint8_t)precision;
+    r.tile_e = 16;
+    r.prefetch = 0;
+    r.unroll = 1;
+    return r;
+}
+
+lpx_status check_record(const lpx_record* rec) {
+    if (!rec) return set_error(LPX_ERR_INVALID_ARG, "record is NULL");
+    if (rec->version != LPX_RECORD_VERSION)
+        return set_error(LPX_ERR_INVALID_ARG, "record version %u, expected %u",
+                         rec->version, LPX_RECORD_VERSION);
+    if (rec->precision > LPX_BF16X3)
+        return set_error(LPX_ERR_INVALID_ARG, "unknown precision %u", rec->precision);
+    if (rec->tile_e != 16 && rec->tile_e != 32 && rec->tile_e != 64)
+        return set_error(LPX_ERR_INVALID_ARG, "tile_e %u not in {16,32,64}", rec->tile_e);
+    if (rec->prefetch > 1)
+        return set_error(LPX_ERR_INVALID_ARG, "prefetch %u not in {0,1}", rec->prefetch);
+    if (rec->unroll != 1 && rec->unroll != 2 && rec->unroll != 4)
+        return set_error(LPX_ERR_INVALID_ARG, "unroll %u not in {1,2,4}", rec->unroll);
+    if (rec->assume_tile_divides > 1)
+        return set_error(LPX_ERR_INVALID_ARG, "assume_tile_divides %u not in {0,1}",
+                         rec->assume_tile_divides);
+    for (uint8_t b : rec->reserved0)
+        if (b) return set_error(LPX_ERR_INVALID_ARG, "reserved record bytes must be 0");
+    if (rec->reserved1) return set_error(LPX_ERR_INVALID_ARG, "reserved record bytes must be 0");
+    return LPX_OK;
+}
+
+lpx_status contract_geometry(int K, int Np, int64_t E, int layout,
+                             const lpx_record& r, ContractGeom* g) {
+    g->prec = r.precision;
+    g->layout = layout;
+    g->tile_e = r.tile_e;
+    g->prefetch = r.prefetch;
+    g->unroll = r.unroll;
+    g->kstep = (r.precision == LPX_FP32) ? 4 : 32;
+    g->nt = (int)ceil_div(Np, 16);
+    g->ntmax = g->nt <= 2 ? 2 : (g->nt <= 4 ? 4 : 8);
+    g->nsteps = (int)ceil_div(Np, g->kstep);
+    g->ntiles = ceil_div(E, r.tile_e);
+    g->nfrag = (int64_t)K * g->nt * g->nsteps * 64;
+    if (r.precision == LPX_FP32) {
+        // row stride = 2 (mod 4) floats: the 16 rows x 4 k-slots an MFMA
+        // operand read touches fall in distinct LDS banks.
+        g->ldu = (int)round_up(Np, 4) + 2;
+    } else {
+        // row stride = 16 (mod 64) bytes: 16-byte operand reads of
+        // consecutive rows start in distinct bank groups.
+        g->ldu = (int)round_up(Np, 32) + 8;
+    }
+    g->lds_bytes = 0;
+    if (r.prefetch) {
+        int64_t frag_bytes = r.precision == LPX_FP32 ? 4 : (r.precision == LPX_BF16 ? 16 : 32);
+        int64_t u_bytes = (int64_t)r.tile_e * g->ldu *
+                          (r.precision == LPX_FP32 ? 4 : (r.precision == LPX_BF16 ? 2 : 4));
+        g->lds_bytes = g->nfrag * frag_bytes + u_bytes;
+        if (g->lds_bytes > kMaxLdsPerWorkgroup)
+            return set_error(LPX_ERR_UNSUPPORTED,
+                             "prefetch=1 needs %lld bytes of LDS per work-group for K=%d "
+                             "Np=%d (limit %lld); use prefetch=0",
+                             (long long)g->lds_bytes, K, Np, (long long)kMaxLdsPerWorkgroup);
+    }
+    return LPX_OK;
+}
+
+lpx_status current_device_info(DeviceInfo* out) {
+    static std::mutex mu;
+    static std::vector<DeviceInfo> cache;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return set_error(LPX_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)cache.size() <= dev) cache.resize(dev + 1);
+    DeviceInfo& d = cache[dev];
+    if (d.device < 0) {
+        int ncu = 0, lds = 0;
+        e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e != hipSuccess)
+            return set_error(LPX_ERR_HIP, "hipDeviceGetAttribute: %s", hipGetErrorString(e));
+        d.device = dev;
+        d.num_cu = ncu;
+        d.max_lds_per_block = lds;
+    }
+    *out = d;
+    return LPX_OK;
+}
+
+}  // namespace lpx
+
+using namespace lpx;
+
+namespace {
+
+bool overlaps(const void* a, int64_t abytes, const void* b, int64_t bbytes) {
+    auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+    return abytes > 0 && bbytes > 0 && pa < pb + (uintptr_t)bbytes &&
+           pb < pa + (uintptr_t)abytes;
+}
+
+bool mul_overflows(int64_t a, int64_t b, int64_t* r) {
+    return __builtin_mul_overflow(a, b, r);
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Every check of lpx_contract that needs no HIP call.  On LPX_OK, g holds
+// the launch geometry; g->ntiles == 0 marks a zero-size no-op.
+lpx_status validate_contract(const lpx_contract_desc* c, const lpx_record* rec,
+                             ContractGeom* g) {
+    g->ntiles = 0;
+    if (!c) return set_error(LPX_ERR_INVALID_ARG, "descriptor is NULL");
+    lpx_record r = rec ? *rec : default_record(LPX_FP32);
+    lpx_status s = check_record(&r);
+    if (s != LPX_OK) return s;
+    if (c->K < 0 || c->Np < 0 || c->E < 0)
+        return set_error(LPX_ERR_INVALID_ARG, "negative size K=%d Np=%d E=%lld", c->K, c->Np,
+                         (long long)c->E);
+    if (c->layout != LPX_ELEMENT_MAJOR && c->layout != LPX_DOF_MAJOR)
+        return set_error(LPX_ERR_INVALID_ARG, "unknown layout %d", c->layout);
+    if (c->reserved != 0) return set_error(LPX_ERR_INVALID_ARG, "reserved must be 0");
+    int64_t uelems, oelems, delems;
+    if (mul_overflows(c->E, c->Np, &uelems) || mul_overflows(uelems, c->K, &oelems) ||
+        mul_overflows((int64_t)c->Np * c->Np, c->K, &delems) || oelems > INT64_MAX / 4)
+        return set_error(LPX_ERR_INVALID_ARG, "size product overflows int64");
+    if (c->Np > kMaxNp)
+        return set_error(LPX_ERR_UNSUPPORTED, "Np=%d above the supported %d", c->Np, kMaxNp);
+    if (r.assume_tile_divides && c->E % r.tile_e != 0)
+        return set_error(LPX_ERR_ASSUMPTION, "record assumes E %% %u == 0 but E = %lld",
+                         r.tile_e, (long long)c->E);
+    if (c->K == 0 || c->Np == 0 || c->E == 0) return LPX_OK;  // zero-trip loop
+    if (!c->D || !c->u || !c->out) return set_error(LPX_ERR_INVALID_ARG, "NULL D, u or out");
+    if (!aligned16(c->D) || !aligned16(c->u) || !aligned16(c->out))
+        return set_error(LPX_ERR_INVALID_ARG, "D, u and out must be 16-byte aligned");
+    if (overlaps(c->out, oelems * 4, c->u, uelems * 4) ||
+        overlaps(c->out, oelems * 4, c->D, delems * 4))
+        return set_error(LPX_ERR_ALIAS, "out overlaps D or u");
+    return contract_geometry(c->K, c->Np, c->E, c->layout, r, g);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lpx_version(void) { return "lpx 0.1.0 gfx950"; }
+
+const char* lpx_status_string(lpx_status s) {
+    switch (s) {
+        case LPX_OK: return "LPX_OK";
+        case LPX_ERR_INVALID_ARG: return "LPX_ERR_INVALID_ARG";
+        case LPX_ERR_UNSUPPORTED: return "LPX_ERR_UNSUPPORTED";
+        case LPX_ERR_ASSUMPTION: return "LPX_ERR_ASSUMPTION";
+        case LPX_ERR_ALIAS: return "LPX_ERR_ALIAS";
+        case LPX_ERR_HIP: return "LPX_ERR_HIP";
+        case LPX_ERR_MODEL: return "LPX_ERR_MODEL";
+        case LPX_ERR_NOT_TUNED: return "LPX_ERR_NOT_TUNED";
+        case LPX_ERR_INTERNAL: return "LPX_ERR_INTERNAL";
+        default: return "LPX_ERR_UNKNOWN";
+    }
+}
+
+const char* lpx_last_error(void) { return last_error_text(); }
+
+lpx_status lpx_record_default(int32_t precision, lpx_record* out) {
+    clear_error();
+    if (!out) return set_error(LPX_ERR_INVALID_ARG, "out is NULL");
+    if (precision < LPX_FP32 || precision > LPX_BF16X3)
+        return set_error(LPX_ERR_INVALID_ARG, "unknown precision %d", precision);
+    *out = default_record(precision);
+    return LPX_OK;
+}
+
+lpx_status lpx_record_validate(const lpx_record* rec) {
+    clear_error();
+    return check_record(rec);
+}
+
+lpx_status lpx_record_describe(const lpx_record* rec, char* buf, size_t len) {
+    clear_error();
+    if (!buf || len == 0) return set_error(LPX_ERR_INVALID_ARG, "buffer is NULL or empty");
+    lpx_status s = check_record(rec);
+    if (s != LPX_OK) {
+        buf[0] = '\0';
+        return s;
+    }
+    static const char* prec[] = {"fp32", "bf16", "bf16x3"};
+    snprintf(buf, len, "%s tile_e=%u prefetch=%u unroll=%u%s gemm=%ux%ux%u",
+             prec[rec->precision], rec->tile_e, rec->prefetch, rec->unroll,
+             rec->assume_tile_divides ? " assume(E%tile_e==0)" : "", rec->gemm_tm,
+             rec->gemm_tn, rec->gemm_tk);
+    return LPX_OK;
+}
+
+lpx_status lpx_record_enumerate(const lpx_problem* p, lpx_record* recs, int32_t cap,
+                                int32_t* n) {
+    clear_error();
+    if (!p || !n) return set_error(LPX_ERR_INVALID_ARG, "problem or n is NULL");
+    if (cap < 0 || (cap > 0 && !recs))
+        return set_error(LPX_ERR_INVALID_ARG, "bad output array (cap %d)", cap);
+    if (p->precision < LPX_FP32 || p->precision > LPX_BF16X3)
+        return set_error(LPX_ERR_INVALID_ARG, "unknown precision %d", p->precision);
+    static const uint8_t tiles[] = {16, 32, 64};
+    static const uint8_t unrolls[] = {1, 2, 4};
+    int32_t count = 0;
+    for (uint8_t t : tiles)
+        for (uint8_t pf = 0; pf < 2; ++pf)
+            for (uint8_t un : unrolls) {
+                if (count < cap) {
+                    lpx_record r = default_record(p->precision);
+                    r.tile_e = t;
+                    r.prefetch = pf;
+                    r.unroll = un;
+                    recs[count] = r;
+                }
+                ++count;
+            }
+    *n = count;
+    return LPX_OK;
+}
+
+lpx_status lpx_contract_lds_bytes(const lpx_problem* p, const lpx_record* rec,
+                                  int64_t* bytes) {
+    clear_error();
+    if (!p || !bytes) return set_error(LPX_ERR_INVALID_ARG, "problem or bytes is NULL");
+    lpx_status s = check_record(rec);
+    if (s != LPX_OK) return s;
+    if (p->K < 0 || p->Np < 0 || p->E < 0)
+        return set_error(LPX_ERR_INVALID_ARG, "negative size");
+    if (p->Np > kMaxNp)
+        return set_error(LPX_ERR_UNSUPPORTED, "Np=%d above %d", p->Np, kMaxNp);
+    ContractGeom g;
+    s = contract_geometry(p->K, p->Np, p->E, p->layout, *rec, &g);
+    *bytes = g.lds_bytes;
+    return s;
+}
+
+lpx_status lpx_contract_validate(const lpx_contract_desc* c, const lpx_record* rec) {
+    clear_error();
+    try {
+        ContractGeom g;
+        return validate_contract(c, rec, &g);
+    } catch (...) {
+        return set_error(LPX_ERR_INTERNAL, "unexpected C++ exception");
+    }
+}
+
+lpx_status lpx_contract(const lpx_contract_desc* c, const lpx_record* rec, void* stream) {
+    clear_error();
+    try {
+        ContractGeom g;
+        lpx_status s = validate_contract(c, rec, &g);
+        if (s != LPX_OK || g.ntiles == 0) return s;
+        return launch_contract(*c, g, stream);
+    } catch (...) {
+        return set_error(LPX_ERR_INTERNAL, "unexpected C++ exception");
+    }
+}
+
+lpx_status lpx_split_bf16(const float* x, uint16_t* hi, uint16_t* lo, int64_t n,
+                          void* stream) {
+    clear_error();
+    try {
+        if (n < 0) return set_error(LPX_ERR_INVALID_ARG, "negative n");
+        if (n == 0) return LPX_OK;
+        if (!x || !hi || !lo) return set_error(LPX_ERR_INVALID_ARG, "NULL pointer");
+        if ((reinterpret_cast<uintptr_t>(x) & 3u) || (reinterpret_cast<uintptr_t>(hi) & 1u) ||
+            (reinterpret_cast<uintptr_t>(lo) & 1u))
+            return set_error(LPX_ERR_INVALID_ARG, "misaligned pointer");
+        if (n > INT64_MAX / 4) return set_error(LPX_ERR_INVALID_ARG, "n too large");
+        if (overlaps(hi, n * 2, x, n * 4) || overlaps(lo, n * 2, x, n * 4) ||
+            overlaps(hi, n * 2, lo, n * 2))
+            return set_error(LPX_ERR_ALIAS, "hi/lo overlap x or each other");
+        return launch_split_bf16(x, hi, lo, n, stream);
+    } catch (...) {
+        return set_error(LPX_ERR_INTERNAL, "unexpected C++ exception");
+    }
+}
+
+}  // extern "C"

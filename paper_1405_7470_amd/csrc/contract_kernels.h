@@ -1,0 +1,434 @@
+// Contraction kernel family  out[k,e,i] = sum_j D[k][i][j] u[e][j]  for gfx950.
+//
+// One template, instantiated once per transformation record:
+//
+//   PREC      FP32 (v_mfma_f32_16x16x4_f32), BF16 or BF16X3
+//             (v_mfma_f32_16x16x32_bf16; bf16x3 = three products per step)
+//   LAYOUT    element-major or DOF-major storage of u and out (the paper's
+//             array-axis tags, sec. 2.4.3)
+//   NTMAX     compiled bound on the number of 16-row i-blocks (2, 4, 8)
+//   TILE_E    split_iname(e, TILE_E), outer index -> work-group (sec. 2.4.1)
+//   PREFETCH  add_prefetch of the u tile and of D into LDS (sec. 2.4.4)
+//   UNROLL    split of the MFMA k-step loop with the inner part unrolled
+//             (tag "unr", sec. 2.4.2)
+//
+// Work decomposition.  A work-group (4 wave64s) walks the element tiles
+// tile = blockIdx.x, blockIdx.x + gridDim.x, ... (grid sized to the
+// resident capacity, so LDS-staged D is loaded once per work-group).  A tile
+// of TILE_E elements is split into 16-element blocks; each block's K*nt
+// (operator, i-block) pairs are spread over 64/TILE_E waves.  A wave owns a
+// set of pairs and, for one 16-element block, accumulates
+//     C_pair[16 x 16] += A[16 x kstep] * B[kstep x 16]
+// over the k-steps of j.  The two operands are a D fragment (16 rows of
+// D[k] for the pair's i-block) and a u fragment (the 16 elements of the
+// block).  Element-major puts i on the MFMA row axis, so each lane ends
+// with 4 consecutive i of one element (one 16-byte store); DOF-major puts
+// e on the row axis, so each lane ends with 4 consecutive e of one i.
+//
+// MFMA operand layout (16x16xKSTEP, both A and B): lane l supplies row (or
+// column) l % 16 and the k-slots (l / 16) * KPL ... + KPL - 1 of the step,
+// KPL = 1 (fp32) or 8 (bf16).  The product pairs A and B values of the same
+// lane-group/slot, so any mapping of j onto (step, group, slot) is correct
+// as long as both operands use it; here j = step*KSTEP + group*KPL + slot.
+// The 16x16 result: lane l, register r holds row 4*(l/16) + r, column l%16.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lpx_internal.h"
+
+namespace lpx {
+namespace kern {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+struct ContractArgs {
+    const float* __restrict__ D;
+    const float* __restrict__ u;
+    float* __restrict__ out;
+    int64_t E;
+    int64_t ntiles;
+    int K, Np, nt, nsteps, ldu;
+    int np_vec;  // Np % 4 == 0: 16-byte row accesses are aligned
+    int e_vec;   // E % 4 == 0
+};
+
+template <int PREC>
+struct Frag;
+template <>
+struct Frag<LPX_FP32> {
+    float a;
+};
+template <>
+struct Frag<LPX_BF16> {
+    bf16x8 h;
+};
+template <>
+struct Frag<LPX_BF16X3> {
+    bf16x8 h, l;
+};
+
+template <int PREC>
+struct Traits {
+    static constexpr int KSTEP = 32;  // reduction length of one MFMA
+    static constexpr int KPL = 8;     // k-slots per lane
+};
+template <>
+struct Traits<LPX_FP32> {
+    static constexpr int KSTEP = 4;
+    static constexpr int KPL = 1;
+};
+
+// ------------------------------------------------------------ conversions
+__device__ __forceinline__ Frag<LPX_FP32> make_frag_fp32(float v) { return {v}; }
+
+template <int PREC>
+__device__ __forceinline__ Frag<PREC> make_frag8(const float (&v)[8]);
+
+template <>
+__device__ __forceinline__ Frag<LPX_BF16> make_frag8<LPX_BF16>(const float (&v)[8]) {
+    Frag<LPX_BF16> f;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) f.h[t] = (__bf16)v[t];  // round to nearest even
+    return f;
+}
+
+template <>
+__device__ __forceinline__ Frag<LPX_BF16X3> make_frag8<LPX_BF16X3>(const float (&v)[8]) {
+    Frag<LPX_BF16X3> f;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        __bf16 h = (__bf16)v[t];
+        f.h[t] = h;
+        f.l[t] = (__bf16)(v[t] - (float)h);  // the difference is exact in fp32
+    }
+    return f;
+}
+
+// ------------------------------------------------------------------ MFMA
+__device__ __forceinline__ f4 mma(const Frag<LPX_FP32>& a, const Frag<LPX_FP32>& b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a.a, b.a, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mma(const Frag<LPX_BF16>& a, const Frag<LPX_BF16>& b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, c, 0, 0, 0);
+}
+// bf16x3: the two correction products first, then hi*hi.
+__device__ __forceinline__ f4 mma(const Frag<LPX_BF16X3>& a, const Frag<LPX_BF16X3>& b,
+                                  f4 c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l, b.h, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.l, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, c, 0, 0, 0);
+}
+
+// ------------------------------------------------------- global fragments
+// Eight consecutive values of a row, zero past `n`; 16-byte loads when the
+// row start is aligned and the eight values are all in range.
+__device__ __forceinline__ void load_row8(const float* __restrict__ row, int j0, int n,
+                                          bool vec, float (&v)[8]) {
+    if (vec && j0 + 8 <= n) {
+        f4 a = *reinterpret_cast<const f4*>(row + j0);
+        f4 b = *reinterpret_cast<const f4*>(row + j0 + 4);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            v[t] = a[t];
+            v[t + 4] = b[t];
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = (j0 + t < n) ? row[j0 + t] : 0.0f;
+    }
+}
+
+// D fragment of pair (k, t), step s, read from global memory.
+template <int PREC>
+__device__ __forceinline__ Frag<PREC> d_frag_global(const ContractArgs& a, int k, int t,
+                                                    int s, int lane) {
+    const int i = 16 * t + (lane & 15);
+    const int j0 = s * Traits<PREC>::KSTEP + (lane >> 4) * Traits<PREC>::KPL;
+    const float* row = a.D + ((int64_t)k * a.Np + i) * a.Np;
+    if constexpr (PREC == LPX_FP32) {
+        return make_frag_fp32((i < a.Np && j0 < a.Np) ? row[j0] : 0.0f);
+    } else {
+        float v[8];
+        if (i < a.Np) {
+            load_row8(row, j0, a.Np, a.np_vec, v);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = 0.0f;
+        }
+        return make_frag8<PREC>(v);
+    }
+}
+
+// u fragment of the 16-element block starting at eb0, step s, from global.
+template <int PREC, int LAYOUT>
+__device__ __forceinline__ Frag<PREC> u_frag_global(const ContractArgs& a, int64_t eb0,
+                                                    int s, int lane) {
+    const int64_t e = eb0 + (lane & 15);
+    const int j0 = s * Traits<PREC>::KSTEP + (lane >> 4) * Traits<PREC>::KPL;
+    const bool ev = e < a.E;
+    if constexpr (PREC == LPX_FP32) {
+        float v = 0.0f;
+        if (ev && j0 < a.Np)
+            v = (LAYOUT == LPX_ELEMENT_MAJOR) ? a.u[e * a.Np + j0] : a.u[(int64_t)j0 * a.E + e];
+        return make_frag_fp32(v);
+    } else {
+        float v[8];
+        if (LAYOUT == LPX_ELEMENT_MAJOR && ev) {
+            load_row8(a.u + e * a.Np, j0, a.Np, a.np_vec, v);
+        } else {
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                v[t] = (ev && j0 + t < a.Np) ? a.u[(int64_t)(j0 + t) * a.E + e] : 0.0f;
+        }
+        return make_frag8<PREC>(v);
+    }
+}
+
+// ------------------------------------------------------------ LDS layout
+// [D fragments, operand order: ((k*nt + t)*nsteps + s)*64 + lane]
+//   fp32: float; bf16: 16-byte hi plane; bf16x3: hi plane then lo plane
+// [u tile, TILE_E rows of ldu elements]
+//   fp32: float; bf16: bf16 hi; bf16x3: hi rows then lo rows
+template <int PREC>
+struct Lds {
+    static constexpr int DFRAG_BYTES = PREC == LPX_FP32 ? 4 : 16;  // per plane
+    static constexpr int PLANES = PREC == LPX_BF16X3 ? 2 : 1;
+    static constexpr int UELEM_BYTES = PREC == LPX_FP32 ? 4 : 2;
+};
+
+template <int PREC>
+__device__ __forceinline__ Frag<PREC> d_frag_lds(const unsigned char* lds, int64_t nfrag,
+                                                 int idx) {
+    if constexpr (PREC == LPX_FP32) {
+        return {reinterpret_cast<const float*>(lds)[idx]};
+    } else if constexpr (PREC == LPX_BF16) {
+        return {reinterpret_cast<const bf16x8*>(lds)[idx]};
+    } else {
+        const bf16x8* p = reinterpret_cast<const bf16x8*>(lds);
+        return {p[idx], p[nfrag + idx]};
+    }
+}
+
+template <int PREC>
+__device__ __forceinline__ void d_frag_store_lds(unsigned char* lds, int64_t nfrag, int idx,
+                                                 const Frag<PREC>& f) {
+    if constexpr (PREC == LPX_FP32) {
+        reinterpret_cast<float*>(lds)[idx] = f.a;
+    } else if constexpr (PREC == LPX_BF16) {
+        reinterpret_cast<bf16x8*>(lds)[idx] = f.h;
+    } else {
+        bf16x8* p = reinterpret_cast<bf16x8*>(lds);
+        p[idx] = f.h;
+        p[nfrag + idx] = f.l;
+    }
+}
+
+// Writes one u value (element row r of the tile, column j) in the staged
+// precision.
+template <int PREC, int TILE_E>
+__device__ __forceinline__ void u_put_lds(unsigned char* ut, int ldu, int r, int j, float v) {
+    if constexpr (PREC == LPX_FP32) {
+        reinterpret_cast<float*>(ut)[r * ldu + j] = v;
+    } else {
+        __bf16* p = reinterpret_cast<__bf16*>(ut);
+        __bf16 h = (__bf16)v;
+        p[r * ldu + j] = h;
+        if constexpr (PREC == LPX_BF16X3) p[TILE_E * ldu + r * ldu + j] = (__bf16)(v - (float)h);
+    }
+}
+
+template <int PREC, int TILE_E>
+__device__ __forceinline__ Frag<PREC> u_frag_lds(const unsigned char* ut, int ldu, int row0,
+                                                 int s, int lane) {
+    const int r = row0 + (lane & 15);
+    const int j0 = s * Traits<PREC>::KSTEP + (lane >> 4) * Traits<PREC>::KPL;
+    if constexpr (PREC == LPX_FP32) {
+        return {reinterpret_cast<const float*>(ut)[r * ldu + j0]};
+    } else if constexpr (PREC == LPX_BF16) {
+        return {*reinterpret_cast<const bf16x8*>(reinterpret_cast<const __bf16*>(ut) +
+                                                 r * ldu + j0)};
+    } else {
+        const __bf16* p = reinterpret_cast<const __bf16*>(ut);
+        return {*reinterpret_cast<const bf16x8*>(p + r * ldu + j0),
+                *reinterpret_cast<const bf16x8*>(p + TILE_E * ldu + r * ldu + j0)};
+    }
+}
+
+// Stage the u tile [e0, e0 + nvalid) into LDS rows 0..nvalid-1, columns
+// 0..Np-1 (the zero columns Np..ldu-1 are written once at kernel start).
+template <int PREC, int LAYOUT, int TILE_E>
+__device__ __forceinline__ void stage_u_tile(const ContractArgs& a, unsigned char* ut,
+                                             int64_t e0, int nvalid, int tid) {
+    const int Np = a.Np;
+    if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
+        // The tile is one contiguous run of nvalid*Np floats.
+        const float* src = a.u + e0 * Np;
+        const int nflat = nvalid * Np;
+        const float inv = 1.0f / (float)Np;
+        if (a.np_vec) {
+            // 16-byte chunks never straddle a row when Np % 4 == 0.
+            for (int c = tid; c < nflat / 4; c += kThreads) {
+                f4 v = reinterpret_cast<const f4*>(src)[c];
+                const int f = 4 * c;
+                const int r = (int)(((float)f + 0.5f) * inv);  // exact: f < 2^13
+                const int j = f - r * Np;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) u_put_lds<PREC, TILE_E>(ut, a.ldu, r, j + q, v[q]);
+            }
+        } else {
+            for (int f = tid; f < nflat; f += kThreads) {
+                const int r = (int)(((float)f + 0.5f) * inv);
+                u_put_lds<PREC, TILE_E>(ut, a.ldu, r, f - r * Np, src[f]);
+            }
+        }
+    } else {
+        // Np rows of nvalid contiguous floats, row stride E.
+        if (a.e_vec) {
+            constexpr int CPR = TILE_E / 4;  // 16-byte chunks per row
+            for (int c = tid; c < Np * CPR; c += kThreads) {
+                const int j = c / CPR;
+                const int r = 4 * (c % CPR);
+                if (r < nvalid) {  // E % 4 == 0 and e0 % 4 == 0: all 4 valid
+                    f4 v = *reinterpret_cast<const f4*>(a.u + (int64_t)j * a.E + e0 + r);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) u_put_lds<PREC, TILE_E>(ut, a.ldu, r + q, j, v[q]);
+                }
+            }
+        } else {
+            for (int f = tid; f < Np * TILE_E; f += kThreads) {
+                const int j = f / TILE_E;
+                const int r = f % TILE_E;
+                if (r < nvalid) u_put_lds<PREC, TILE_E>(ut, a.ldu, r, j, a.u[(int64_t)j * a.E + e0 + r]);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ the kernel
+template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PREFETCH, int UNROLL>
+__global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    constexpr int WPE = 64 / TILE_E;                // waves per 16-element block
+    constexpr int PMAX = (3 * NTMAX + WPE - 1) / WPE;  // pairs held per wave
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int eblk = wave / WPE;  // which 16-element block of the tile
+    const int part = wave % WPE;  // which share of that block's pairs
+    const int npairs = a.K * a.nt;
+    const int64_t nfrag = (int64_t)npairs * a.nsteps * 64;
+    unsigned char* ut = lds + nfrag * Lds<PREC>::DFRAG_BYTES * Lds<PREC>::PLANES;
+
+    if constexpr (PREFETCH) {
+        // D in operand order, converted once per work-group.
+        for (int64_t idx = tid; idx < nfrag; idx += kThreads) {
+            const int l = (int)(idx & 63);
+            const int rest = (int)(idx >> 6);
+            const int s = rest % a.nsteps;
+            const int p = rest / a.nsteps;
+            const int k = p / a.nt;
+            const int t = p - k * a.nt;
+            d_frag_store_lds<PREC>(lds, nfrag, (int)idx, d_frag_global<PREC>(a, k, t, s, l));
+        }
+        // Zero the padding columns [Np, ldu) of every tile row once; tile
+        // staging never writes them.
+        const int padw = a.ldu - a.Np;
+        for (int f = tid; f < TILE_E * padw; f += kThreads)
+            u_put_lds<PREC, TILE_E>(ut, a.ldu, f / padw, a.Np + f % padw, 0.0f);
+        __syncthreads();
+    }
+
+    for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        const int64_t e0 = tile * TILE_E;
+        const int nvalid = (int)((a.E - e0) < TILE_E ? (a.E - e0) : TILE_E);
+        if constexpr (PREFETCH) {
+            __syncthreads();  // previous tile's operand reads are done
+            stage_u_tile<PREC, LAYOUT, TILE_E>(a, ut, e0, nvalid, tid);
+            __syncthreads();
+        }
+        const int64_t eb0 = e0 + 16 * eblk;
+        if (16 * eblk >= nvalid) continue;  // uniform per wave; no barrier below
+
+        for (int pc = part; pc < npairs; pc += WPE * PMAX) {
+            f4 acc[PMAX];
+            int pk[PMAX], pt[PMAX];
+#pragma unroll
+            for (int q = 0; q < PMAX; ++q) {
+                acc[q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+                const int p = pc + q * WPE;
+                pk[q] = p / a.nt;
+                pt[q] = p - pk[q] * a.nt;
+            }
+            auto step = [&](int s) {
+                Frag<PREC> uf;
+                if constexpr (PREFETCH)
+                    uf = u_frag_lds<PREC, TILE_E>(ut, a.ldu, 16 * eblk, s, lane);
+                else
+                    uf = u_frag_global<PREC, LAYOUT>(a, eb0, s, lane);
+#pragma unroll
+                for (int q = 0; q < PMAX; ++q) {
+                    const int p = pc + q * WPE;
+                    if (p < npairs) {
+                        Frag<PREC> df;
+                        if constexpr (PREFETCH)
+                            df = d_frag_lds<PREC>(lds, nfrag, (p * a.nsteps + s) * 64 + lane);
+                        else
+                            df = d_frag_global<PREC>(a, pk[q], pt[q], s, lane);
+                        if constexpr (LAYOUT == LPX_ELEMENT_MAJOR)
+                            acc[q] = mma(df, uf, acc[q]);  // rows i, columns e
+                        else
+                            acc[q] = mma(uf, df, acc[q]);  // rows e, columns i
+                    }
+                }
+            };
+            int s = 0;
+            for (; s + UNROLL <= a.nsteps; s += UNROLL) {
+#pragma unroll
+                for (int uu = 0; uu < UNROLL; ++uu) step(s + uu);
+            }
+            for (; s < a.nsteps; ++s) step(s);
+
+#pragma unroll
+            for (int q = 0; q < PMAX; ++q) {
+                const int p = pc + q * WPE;
+                if (p >= npairs) continue;
+                const int k = pk[q], t = pt[q];
+                if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
+                    const int64_t e = eb0 + (lane & 15);
+                    const int i0 = 16 * t + 4 * (lane >> 4);
+                    if (e < a.E && i0 < a.Np) {
+                        float* dst = a.out + ((int64_t)k * a.E + e) * a.Np + i0;
+                        if (a.np_vec) {
+                            *reinterpret_cast<f4*>(dst) = acc[q];
+                        } else {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                if (i0 + r < a.Np) dst[r] = acc[q][r];
+                        }
+                    }
+                } else {
+                    const int i = 16 * t + (lane & 15);
+                    const int64_t e = eb0 + 4 * (lane >> 4);
+                    if (i < a.Np && e < a.E) {
+                        float* dst = a.out + ((int64_t)k * a.Np + i) * a.E + e;
+                        if (a.e_vec) {
+                            *reinterpret_cast<f4*>(dst) = acc[q];
+                        } else {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                if (e + r < a.E) dst[r] = acc[q][r];
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+}  // namespace kern
+}  // namespace lpx

@@ -1,0 +1,98 @@
+// Launch of the contraction kernel family: record -> kernel instance, grid.
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "contract_kernels.h"
+
+namespace lpx {
+
+using ContractFn = void (*)(kern::ContractArgs);
+ContractFn contract_kernel_fp32(int layout, int ntmax, int tile, int pf, int un);
+ContractFn contract_kernel_bf16(int layout, int ntmax, int tile, int pf, int un);
+ContractFn contract_kernel_bf16x3(int layout, int ntmax, int tile, int pf, int un);
+
+namespace {
+
+ContractFn select(const ContractGeom& g) {
+    switch (g.prec) {
+        case LPX_FP32: return contract_kernel_fp32(g.layout, g.ntmax, g.tile_e, g.prefetch, g.unroll);
+        case LPX_BF16: return contract_kernel_bf16(g.layout, g.ntmax, g.tile_e, g.prefetch, g.unroll);
+        default: return contract_kernel_bf16x3(g.layout, g.ntmax, g.tile_e, g.prefetch, g.unroll);
+    }
+}
+
+// Resident work-groups per CU for (kernel, dynamic LDS), cached per device.
+lpx_status blocks_per_cu(const void* fn, int64_t lds, int device, int* out) {
+    static std::mutex mu;
+    static std::map<std::pair<std::pair<const void*, int64_t>, int>, int> cache;
+    static std::map<std::pair<const void*, int>, bool> lds_attr_set;
+    std::lock_guard<std::mutex> lock(mu);
+    auto key = std::make_pair(std::make_pair(fn, lds), device);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        *out = it->second;
+        return LPX_OK;
+    }
+    if (lds > 64 * 1024 && !lds_attr_set[{fn, device}]) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)kMaxLdsPerWorkgroup);
+        if (e != hipSuccess)
+            return set_error(LPX_ERR_HIP, "hipFuncSetAttribute: %s", hipGetErrorString(e));
+        lds_attr_set[{fn, device}] = true;
+    }
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kThreads, (size_t)lds);
+    if (e != hipSuccess)
+        return set_error(LPX_ERR_HIP, "hipOccupancyMaxActiveBlocksPerMultiprocessor: %s",
+                         hipGetErrorString(e));
+    cache[key] = nb;
+    *out = nb;
+    return LPX_OK;
+}
+
+}  // namespace
+
+lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g, void* stream) {
+    DeviceInfo dev;
+    lpx_status s = current_device_info(&dev);
+    if (s != LPX_OK) return s;
+    if (g.lds_bytes > dev.max_lds_per_block)
+        return set_error(LPX_ERR_UNSUPPORTED, "needs %lld bytes of LDS, device allows %d",
+                         (long long)g.lds_bytes, dev.max_lds_per_block);
+    ContractFn fn = select(g);
+    int nb = 0;
+    s = blocks_per_cu(reinterpret_cast<const void*>(fn), g.lds_bytes, dev.device, &nb);
+    if (s != LPX_OK) return s;
+    if (nb <= 0)
+        return set_error(LPX_ERR_UNSUPPORTED, "kernel cannot be resident (LDS %lld bytes)",
+                         (long long)g.lds_bytes);
+    int64_t grid = (int64_t)nb * dev.num_cu;
+    if (grid > g.ntiles) grid = g.ntiles;
+
+    kern::ContractArgs a;
+    a.D = c.D;
+    a.u = c.u;
+    a.out = c.out;
+    a.E = c.E;
+    a.ntiles = g.ntiles;
+    a.K = c.K;
+    a.Np = c.Np;
+    a.nt = g.nt;
+    a.nsteps = g.nsteps;
+    a.ldu = g.ldu;
+    a.np_vec = (c.Np % 4) == 0;
+    a.e_vec = (c.E % 4) == 0;
+    void* args[] = {&a};
+    hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)grid),
+                                   dim3(kThreads), args, (size_t)g.lds_bytes,
+                                   reinterpret_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess)
+        return set_error(LPX_ERR_HIP, "contraction launch: %s", hipGetErrorString(e));
+    return LPX_OK;
+}
+
+}  // namespace lpx

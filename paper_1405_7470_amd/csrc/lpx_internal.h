@@ -1,0 +1,67 @@
+// Internal declarations shared by the liblpx translation units.
+#pragma once
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/lpx.h"
+
+namespace lpx {
+
+// gfx950 limits used by host-side validation (no HIP call needed).
+constexpr int64_t kMaxLdsPerWorkgroup = 160 * 1024;
+constexpr int kMaxNp = 128;
+constexpr int kThreads = 256;  // every contraction work-group: 4 wave64s
+
+// Thread-local last-error text; set_error returns its status so call sites
+// can `return set_error(...)`.
+lpx_status set_error(lpx_status s, const char* fmt, ...)
+    __attribute__((format(printf, 2, 3)));
+void clear_error();
+const char* last_error_text();
+
+// Record defaults and checks.
+lpx_record default_record(int precision);
+lpx_status check_record(const lpx_record* rec);
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+inline int64_t ceil_div(int64_t x, int64_t m) { return (x + m - 1) / m; }
+
+// Geometry of one contraction launch, derived from (problem, record) on the
+// host.  Every quantity the kernel's indexing assumes is computed here.
+struct ContractGeom {
+    int prec = 0, layout = 0;
+    int tile_e = 16, prefetch = 0, unroll = 1;
+    int kstep = 4;     // reduction length of one MFMA (4 fp32, 32 bf16)
+    int nt = 0;        // i-blocks of 16 rows: ceil(Np / 16)
+    int ntmax = 2;     // compiled bound on nt: 2, 4 or 8
+    int nsteps = 0;    // MFMA k-steps: ceil(Np / kstep)
+    int ldu = 0;       // LDS row stride of the staged u tile (elements)
+    int64_t ntiles = 0;
+    int64_t nfrag = 0;     // staged D fragments: K*nt*nsteps*64 lanes
+    int64_t lds_bytes = 0; // dynamic LDS per work-group (0 if no prefetch)
+};
+
+// Fills g; returns LPX_OK or LPX_ERR_UNSUPPORTED (with error text) when the
+// shape is outside what the record's kernels are built for.
+lpx_status contract_geometry(int K, int Np, int64_t E, int layout,
+                             const lpx_record& r, ContractGeom* g);
+
+// Launches the contraction kernel for a validated problem.
+lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g,
+                           void* stream);
+
+// Elementwise bf16 split kernel launch (n > 0, pointers validated).
+lpx_status launch_split_bf16(const float* x, uint16_t* hi, uint16_t* lo,
+                             int64_t n, void* stream);
+
+// Device properties of the current device, cached per device.
+struct DeviceInfo {
+    int device = -1;
+    int num_cu = 0;
+    int max_lds_per_block = 0;
+};
+lpx_status current_device_info(DeviceInfo* out);
+
+}  // namespace lpx

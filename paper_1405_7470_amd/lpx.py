@@ -1,0 +1,276 @@
+"""ctypes binding of liblpx (the C ABI in include/lpx.h).
+
+Argument marshalling only: every step of the contraction runs in the HIP
+kernels of liblpx.  PyTorch supplies device memory and streams.  There is no
+fallback: if liblpx.so is missing or a call fails, an exception is raised.
+
+torch is imported before liblpx.so is loaded, so that the library binds to the
+HIP runtime torch already has in the process (one runtime, shared streams).
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblpx.so")
+
+# status codes (include/lpx.h)
+OK = 0
+ERR_INVALID_ARG = 1
+ERR_UNSUPPORTED = 2
+ERR_ASSUMPTION = 3
+ERR_ALIAS = 4
+ERR_HIP = 5
+ERR_MODEL = 6
+ERR_NOT_TUNED = 7
+ERR_INTERNAL = 8
+
+PRECISION = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+PRECISION_NAME = {v: k for k, v in PRECISION.items()}
+LAYOUT = {"em": 0, "dm": 1}
+RECORD_VERSION = 1
+
+
+class LpxError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{_status_name(status)}: {message}")
+        self.status = status
+
+
+class Record(ctypes.Structure):
+    """Transformation record (struct lpx_record)."""
+    _fields_ = [
+        ("version", ctypes.c_uint32),
+        ("precision", ctypes.c_uint8),
+        ("tile_e", ctypes.c_uint8),
+        ("prefetch", ctypes.c_uint8),
+        ("unroll", ctypes.c_uint8),
+        ("assume_tile_divides", ctypes.c_uint8),
+        ("reserved0", ctypes.c_uint8 * 3),
+        ("gemm_tm", ctypes.c_uint16),
+        ("gemm_tn", ctypes.c_uint16),
+        ("gemm_tk", ctypes.c_uint16),
+        ("reserved1", ctypes.c_uint16),
+    ]
+
+    def key(self):
+        return (self.precision, self.tile_e, self.prefetch, self.unroll,
+                self.assume_tile_divides, self.gemm_tm, self.gemm_tn, self.gemm_tk)
+
+    def __eq__(self, other):
+        return isinstance(other, Record) and self.key() == other.key()
+
+    def __hash__(self):
+        return hash(self.key())
+
+    def __repr__(self):
+        return f"Record({describe(self)})"
+
+    def as_dict(self):
+        return {"precision": PRECISION_NAME[self.precision], "tile_e": self.tile_e,
+                "prefetch": self.prefetch, "unroll": self.unroll,
+                "assume_tile_divides": self.assume_tile_divides,
+                "gemm": [self.gemm_tm, self.gemm_tn, self.gemm_tk]}
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("Np", ctypes.c_int32), ("E", ctypes.c_int64),
+                ("layout", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class ContractDesc(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("Np", ctypes.c_int32), ("E", ctypes.c_int64),
+                ("layout", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("D", ctypes.c_void_p), ("u", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded liblpx.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_1405_7470_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        st = ctypes.c_int32
+        vp = ctypes.c_void_p
+        L.lpx_version.restype = ctypes.c_char_p
+        L.lpx_status_string.restype = ctypes.c_char_p
+        L.lpx_status_string.argtypes = [st]
+        L.lpx_last_error.restype = ctypes.c_char_p
+        L.lpx_record_default.argtypes = [ctypes.c_int32, ctypes.POINTER(Record)]
+        L.lpx_record_validate.argtypes = [ctypes.POINTER(Record)]
+        L.lpx_record_describe.argtypes = [ctypes.POINTER(Record), ctypes.c_char_p, ctypes.c_size_t]
+        L.lpx_record_enumerate.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Record),
+                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        L.lpx_contract_lds_bytes.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Record),
+                                             ctypes.POINTER(ctypes.c_int64)]
+        L.lpx_contract_validate.argtypes = [ctypes.POINTER(ContractDesc), ctypes.POINTER(Record)]
+        L.lpx_contract.argtypes = [ctypes.POINTER(ContractDesc), ctypes.POINTER(Record), vp]
+        L.lpx_split_bf16.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
+        for name in ("lpx_record_default", "lpx_record_validate", "lpx_record_describe",
+                     "lpx_record_enumerate", "lpx_contract_lds_bytes", "lpx_contract_validate",
+                     "lpx_contract", "lpx_split_bf16"):
+            getattr(L, name).restype = st
+        _lib = L
+    return _lib
+
+
+def _status_name(s):
+    try:
+        return lib().lpx_status_string(s).decode()
+    except Exception:  # library not loadable: still report the number
+        return f"status {s}"
+
+
+def _check(status):
+    if status != OK:
+        raise LpxError(status, lib().lpx_last_error().decode())
+
+
+def version() -> str:
+    return lib().lpx_version().decode()
+
+
+def last_error() -> str:
+    return lib().lpx_last_error().decode()
+
+
+# ------------------------------------------------------------------ records
+def default_record(precision="fp32") -> Record:
+    r = Record()
+    _check(lib().lpx_record_default(PRECISION[precision], ctypes.byref(r)))
+    return r
+
+
+def record(precision="fp32", tile_e=16, prefetch=0, unroll=1, assume_tile_divides=0,
+           gemm=(0, 0, 0)) -> Record:
+    r = default_record(precision)
+    r.tile_e, r.prefetch, r.unroll = tile_e, prefetch, unroll
+    r.assume_tile_divides = assume_tile_divides
+    r.gemm_tm, r.gemm_tn, r.gemm_tk = gemm
+    return r
+
+
+def validate_record(rec) -> int:
+    return lib().lpx_record_validate(ctypes.byref(rec))
+
+
+def describe(rec) -> str:
+    buf = ctypes.create_string_buffer(160)
+    s = lib().lpx_record_describe(ctypes.byref(rec), buf, len(buf))
+    if s != OK:
+        return f"<invalid record: {last_error()}>"
+    return buf.value.decode()
+
+
+def problem(K, Np, E, layout="em", precision="fp32") -> Problem:
+    return Problem(K, Np, E, LAYOUT[layout], PRECISION[precision])
+
+
+def enumerate_records(K, Np, E, layout="em", precision="fp32"):
+    """Candidate records of a problem, in the library's canonical order."""
+    p = problem(K, Np, E, layout, precision)
+    n = ctypes.c_int32()
+    _check(lib().lpx_record_enumerate(ctypes.byref(p), None, 0, ctypes.byref(n)))
+    arr = (Record * n.value)()
+    _check(lib().lpx_record_enumerate(ctypes.byref(p), arr, n.value, ctypes.byref(n)))
+    return list(arr)
+
+
+def lds_bytes(K, Np, E, layout, rec):
+    """(status, bytes) of dynamic LDS per work-group for the record."""
+    p = problem(K, Np, E, layout, PRECISION_NAME[rec.precision])
+    b = ctypes.c_int64()
+    s = lib().lpx_contract_lds_bytes(ctypes.byref(p), ctypes.byref(rec), ctypes.byref(b))
+    return s, b.value
+
+
+# -------------------------------------------------------------- contraction
+def _stream_handle(stream):
+    """hipStream_t of a torch stream (None = torch's current stream; 0 = the
+    null stream)."""
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream or None)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def contract_shapes(D, u, layout):
+    K, Np, Np2 = D.shape
+    if Np != Np2:
+        raise ValueError(f"D must be (K, Np, Np), got {tuple(D.shape)}")
+    if u.dim() != 2:
+        raise ValueError("u must be 2-D")
+    if layout == "em":
+        E = u.shape[0]
+        if u.shape[1] != Np:
+            raise ValueError(f"element-major u must be (E, {Np}), got {tuple(u.shape)}")
+    elif layout == "dm":
+        E = u.shape[1]
+        if u.shape[0] != Np:
+            raise ValueError(f"DOF-major u must be ({Np}, E), got {tuple(u.shape)}")
+    else:
+        raise ValueError(f"unknown layout {layout!r}")
+    return K, Np, E
+
+
+def make_desc(D, u, out, layout):
+    K, Np, E = contract_shapes(D, u, layout)
+    for name, t in (("D", D), ("u", u), ("out", out)):
+        if t.dtype != torch.float32:
+            raise TypeError(f"{name} must be float32")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+    if out.numel() != K * E * Np:
+        raise ValueError(f"out must hold K*E*Np = {K * E * Np} floats")
+    return ContractDesc(K, Np, E, LAYOUT[layout], 0, D.data_ptr() if D.numel() else None,
+                        u.data_ptr() if u.numel() else None,
+                        out.data_ptr() if out.numel() else None)
+
+
+def out_shape(K, Np, E, layout):
+    return (K, E, Np) if layout == "em" else (K, Np, E)
+
+
+def contract(D, u, out=None, layout="em", record=None, stream=None):
+    """out[k,e,i] = sum_j D[k][i][j] u[e][j] on the GPU through lpx_contract.
+
+    D: (K, Np, Np) float32 CUDA tensor.  u: (E, Np) for layout "em", (Np, E)
+    for "dm".  out (allocated if None): (K, E, Np) for "em", (K, Np, E) for
+    "dm".  record: a Record (None = the untuned FP32 default).
+    """
+    K, Np, E = contract_shapes(D, u, layout)
+    if out is None:
+        out = torch.empty(out_shape(K, Np, E, layout), dtype=torch.float32, device=u.device)
+    desc = make_desc(D, u, out, layout)
+    recp = ctypes.byref(record) if record is not None else None
+    _check(lib().lpx_contract(ctypes.byref(desc), recp, _stream_handle(stream)))
+    return out
+
+
+def contract_validate(desc, rec=None) -> int:
+    """Status lpx_contract would return for (desc, rec) before any launch."""
+    recp = ctypes.byref(rec) if rec is not None else None
+    return lib().lpx_contract_validate(ctypes.byref(desc), recp)
+
+
+def split_bf16(x, hi=None, lo=None, stream=None):
+    """(hi, lo) raw bfloat16 bit patterns (int16 tensors) of an fp32 tensor."""
+    if x.dtype != torch.float32 or not x.is_contiguous():
+        raise TypeError("x must be a contiguous float32 tensor")
+    if hi is None:
+        hi = torch.empty(x.shape, dtype=torch.int16, device=x.device)
+    if lo is None:
+        lo = torch.empty(x.shape, dtype=torch.int16, device=x.device)
+    n = x.numel()
+    _check(lib().lpx_split_bf16(ctypes.c_void_p(x.data_ptr() if n else None),
+                                ctypes.c_void_p(hi.data_ptr() if n else None),
+                                ctypes.c_void_p(lo.data_ptr() if n else None), n,
+                                _stream_handle(stream)))
+    return hi, lo

@@ -1,0 +1,151 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, and rejects every malformed call before any HIP call.
+
+Calls that could launch work are only made with NULL pointers or zero
+sizes; descriptors with stand-in addresses go to lpx_contract_validate,
+which never launches or dereferences.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1405_7470_amd import lpx
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                      "include", "lpx.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lpx_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert "lpx_contract" in names and "lpx_split_bf16" in names
+    L = lpx.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_version_and_status_strings():
+    assert "gfx950" in lpx.version()
+    L = lpx.lib()
+    assert L.lpx_status_string(0) == b"LPX_OK"
+    assert L.lpx_status_string(lpx.ERR_ALIAS) == b"LPX_ERR_ALIAS"
+    assert L.lpx_status_string(99) == b"LPX_ERR_UNKNOWN"
+
+
+def test_default_record_is_the_untuned_variant():
+    for prec in ("fp32", "bf16", "bf16x3"):
+        r = lpx.default_record(prec)
+        assert (r.version, r.tile_e, r.prefetch, r.unroll) == (1, 16, 0, 1)
+        assert lpx.PRECISION_NAME[r.precision] == prec
+        assert lpx.validate_record(r) == lpx.OK
+    bad = lpx.Record()
+    assert lpx.lib().lpx_record_default(7, ctypes.byref(bad)) == lpx.ERR_INVALID_ARG
+
+
+def test_enumeration_canonical_order_and_truncation():
+    recs = lpx.enumerate_records(3, 56, 1 << 20, "em", "bf16x3")
+    assert len(recs) == 18
+    keys = [(r.tile_e, r.prefetch, r.unroll) for r in recs]
+    assert keys == [(t, p, u) for t in (16, 32, 64) for p in (0, 1) for u in (1, 2, 4)]
+    assert all(lpx.PRECISION_NAME[r.precision] == "bf16x3" for r in recs)
+    p = lpx.problem(3, 56, 1 << 20, "em", "fp32")
+    arr = (lpx.Record * 4)()
+    n = ctypes.c_int32()
+    assert lpx.lib().lpx_record_enumerate(ctypes.byref(p), arr, 4, ctypes.byref(n)) == 0
+    assert n.value == 18 and arr[3].unroll == 1 and arr[3].prefetch == 1
+
+
+def test_describe():
+    r = lpx.record("bf16", 64, 1, 4)
+    assert lpx.describe(r) == "bf16 tile_e=64 prefetch=1 unroll=4 gemm=0x0x0"
+
+
+@pytest.mark.parametrize("field,value", [
+    ("version", 2), ("precision", 3), ("tile_e", 8), ("tile_e", 128), ("prefetch", 2),
+    ("unroll", 3), ("assume_tile_divides", 2), ("reserved1", 1)])
+def test_malformed_records_rejected(field, value):
+    r = lpx.default_record()
+    setattr(r, field, value)
+    assert lpx.validate_record(r) == lpx.ERR_INVALID_ARG
+    assert lpx.last_error()
+
+
+A = 1 << 32  # stand-in, 16-byte aligned addresses (never dereferenced)
+
+
+def desc(K=3, Np=56, E=1000, layout=0, D=A, u=A + (1 << 24), out=A + (1 << 28), reserved=0):
+    return lpx.ContractDesc(K, Np, E, layout, reserved, D, u, out)
+
+
+def status(d, rec=None):
+    return lpx.contract_validate(d, rec)
+
+
+def test_validate_accepts_well_formed():
+    assert status(desc()) == lpx.OK
+    for r in lpx.enumerate_records(3, 56, 1000, "dm", "bf16x3"):
+        assert status(desc(layout=1), r) == lpx.OK
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(K=-1), lpx.ERR_INVALID_ARG),
+    (dict(Np=-2), lpx.ERR_INVALID_ARG),
+    (dict(E=-5), lpx.ERR_INVALID_ARG),
+    (dict(layout=2), lpx.ERR_INVALID_ARG),
+    (dict(reserved=1), lpx.ERR_INVALID_ARG),
+    (dict(E=1 << 62), lpx.ERR_INVALID_ARG),          # K*E*Np overflows
+    (dict(Np=129), lpx.ERR_UNSUPPORTED),
+    (dict(D=None), lpx.ERR_INVALID_ARG),
+    (dict(u=None), lpx.ERR_INVALID_ARG),
+    (dict(out=None), lpx.ERR_INVALID_ARG),
+    (dict(u=A + 8), lpx.ERR_INVALID_ARG),             # misaligned
+    (dict(out=A + (1 << 24) + 4096), lpx.ERR_ALIAS),  # out overlaps u
+    (dict(out=A), lpx.ERR_ALIAS),                      # out overlaps D
+])
+def test_validate_rejects(kw, code):
+    assert status(desc(**kw)) == code
+    assert lpx.last_error()
+
+
+def test_zero_sizes_are_noops_even_with_null_pointers():
+    for kw in (dict(E=0), dict(K=0), dict(Np=0)):
+        d = desc(D=None, u=None, out=None, **kw)
+        assert status(d) == lpx.OK
+        # lpx_contract returns before any HIP call for a zero-size problem
+        assert lpx.lib().lpx_contract(ctypes.byref(d), None, None) == lpx.OK
+
+
+def test_assumption_checked():
+    r = lpx.record("fp32", 32, 0, 1, assume_tile_divides=1)
+    assert status(desc(E=1024), r) == lpx.OK
+    assert status(desc(E=1000), r) == lpx.ERR_ASSUMPTION
+    assert "assumes" in lpx.last_error()
+
+
+def test_lds_budget():
+    # prefetch=1 stages all of D in LDS: Np = 128, K = 3 in FP32 needs
+    # 3*8*32*64*4 bytes of D fragments, above the 160 KiB per work-group
+    r = lpx.record("fp32", 64, 1, 1)
+    assert status(desc(Np=128), r) == lpx.ERR_UNSUPPORTED
+    s, b = lpx.lds_bytes(3, 128, 4096, "em", r)
+    assert s == lpx.ERR_UNSUPPORTED and b == 3 * 8 * 32 * 64 * 4 + 64 * 130 * 4
+    # the config-scale shape fits: D 3*4*14*64*4 bytes + u tile 64*58*4
+    s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", r)
+    assert s == lpx.OK and b == 3 * 4 * 14 * 64 * 4 + 64 * 58 * 4
+    s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", lpx.record("fp32", 64, 0, 1))
+    assert s == lpx.OK and b == 0
+
+
+def test_null_descriptor_and_split_args():
+    L = lpx.lib()
+    assert L.lpx_contract(None, None, None) == lpx.ERR_INVALID_ARG
+    assert L.lpx_split_bf16(None, None, None, 0, None) == lpx.OK
+    assert L.lpx_split_bf16(None, None, None, -1, None) == lpx.ERR_INVALID_ARG
+    assert L.lpx_split_bf16(None, None, None, 10, None) == lpx.ERR_INVALID_ARG
