@@ -89,11 +89,14 @@ typedef int32_t lpx_status;
  *              e is split again by 16 (the MFMA column block) and i by 16
  *              (the MFMA row block); the (k, i-block) pairs of a 16-element
  *              block are spread over the work-group's four wavefronts.
- *   prefetch : 0 = MFMA operands are loaded from global memory straight
- *              into registers; 1 = add_prefetch (sec. 2.4.4): the u tile
- *              and all of D are staged in LDS (converted to the operand
- *              precision on the way) before the reduction, with the
- *              work-group barrier the paper's precompute inserts.
+ *   prefetch : add_prefetch (sec. 2.4.4), one bit per array, 0..3.
+ *              bit 0: all of D is staged in LDS once per work-group, in
+ *              MFMA operand order and converted to the operand precision;
+ *              bit 1: each u tile is staged in LDS (converted on the way)
+ *              before its reduction, with the work-group barriers the
+ *              paper's precompute inserts.  A clear bit means that array's
+ *              MFMA operands are loaded from global memory straight into
+ *              registers.
  *   unroll   : 1, 2 or 4; the reduction loop over MFMA k-steps is split by
  *              `unroll` and the inner part unrolled (tag "unr", sec. 2.4.2).
  *   precision: LPX_FP32 / LPX_BF16 / LPX_BF16X3.
@@ -164,8 +167,8 @@ lpx_status lpx_record_validate(const lpx_record* rec);
 lpx_status lpx_record_describe(const lpx_record* rec, char* buf, size_t len);
 
 /* The candidate records of a problem in canonical order: precision fixed to
- * p->precision, then tile_e in {16,32,64} (outer), prefetch in {0,1},
- * unroll in {1,2,4} (inner): 18 records.  Writes min(cap, 18) records to
+ * p->precision, then tile_e in {16,32,64} (outer), prefetch in {0,1,2,3},
+ * unroll in {1,2,4} (inner): 36 records.  Writes min(cap, 36) records to
  * the host array `recs` and the total count to *n. */
 lpx_status lpx_record_enumerate(const lpx_problem* p, lpx_record* recs,
                                 int32_t cap, int32_t* n);
@@ -202,6 +205,38 @@ lpx_status lpx_contract_validate(const lpx_contract_desc* c, const lpx_record* r
  * operand transformation behind LPX_BF16 (hi only) and LPX_BF16X3. */
 lpx_status lpx_split_bf16(const float* x, uint16_t* hi, uint16_t* lo,
                           int64_t n, void* stream);
+
+/* ------------------------------------------------ variant selection */
+/* Exhaustive autotuner: times every candidate record of the problem
+ * (lpx_record_enumerate order) on the caller's buffers -- `warmup` untimed
+ * launches, then `reps` launches each bracketed by HIP events on `stream`,
+ * median kept -- and returns the fastest in *best (ties: lowest index).
+ * Blocks the calling thread until the timing launches finish.  Overwrites
+ * c->out.  Candidates that lpx_contract_validate rejects (e.g. LDS budget)
+ * are skipped and reported as +infinity.  Writes min(cap, count) median
+ * times in microseconds to the host array times_us and the count to *n
+ * (n may be NULL).  The winner is also stored in the library's tuning
+ * cache, keyed by (device, K, Np, E, layout, precision), where
+ * LPX_PICK_EXHAUSTIVE finds it. */
+lpx_status lpx_autotune(const lpx_contract_desc* c, int32_t precision, int32_t warmup,
+                        int32_t reps, void* stream, lpx_record* best, float* times_us,
+                        int32_t cap, int32_t* n);
+
+/* Seeds the tuning cache for the current device (e.g. from a stored timing
+ * database); the record's precision must equal p->precision. */
+lpx_status lpx_tune_cache_insert(const lpx_problem* p, const lpx_record* rec);
+
+/* Empties the tuning cache. */
+lpx_status lpx_tune_cache_clear(void);
+
+/* ------------------------------------------------------ measurement */
+/* Streaming probe, the analogue of Table 1's "saxpy" row: y[r*n + t] =
+ * x[t] for r < fanout (fanout 1 = plain copy; fanout 3 = the contraction's
+ * one-read-three-writes byte mix).  x: device, n floats; y: device,
+ * fanout*n floats; n a multiple of 4, pointers 16-byte aligned, y must not
+ * overlap x.  Used to measure the achievable HBM rate and to calibrate
+ * hardware byte counters against a kernel of known traffic. */
+lpx_status lpx_stream_probe(const float* x, float* y, int64_t n, int32_t fanout, void* stream);
 
 #ifdef __cplusplus
 }

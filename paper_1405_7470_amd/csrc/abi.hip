@@ -46,8 +46,8 @@ lpx_status check_record(const lpx_record* rec) {
         return set_error(LPX_ERR_INVALID_ARG, "unknown precision %u", rec->precision);
     if (rec->tile_e != 16 && rec->tile_e != 32 && rec->tile_e != 64)
         return set_error(LPX_ERR_INVALID_ARG, "tile_e %u not in {16,32,64}", rec->tile_e);
-    if (rec->prefetch > 1)
-        return set_error(LPX_ERR_INVALID_ARG, "prefetch %u not in {0,1}", rec->prefetch);
+    if (rec->prefetch > 3)
+        return set_error(LPX_ERR_INVALID_ARG, "prefetch %u not in {0,1,2,3}", rec->prefetch);
     if (rec->unroll != 1 && rec->unroll != 2 && rec->unroll != 4)
         return set_error(LPX_ERR_INVALID_ARG, "unroll %u not in {1,2,4}", rec->unroll);
     if (rec->assume_tile_divides > 1)
@@ -86,7 +86,8 @@ lpx_status contract_geometry(int K, int Np, int64_t E, int layout,
         int64_t frag_bytes = r.precision == LPX_FP32 ? 4 : (r.precision == LPX_BF16 ? 16 : 32);
         int64_t u_bytes = (int64_t)r.tile_e * g->ldu *
                           (r.precision == LPX_FP32 ? 4 : (r.precision == LPX_BF16 ? 2 : 4));
-        g->lds_bytes = g->nfrag * frag_bytes + u_bytes;
+        g->lds_bytes = ((r.prefetch & 1) ? g->nfrag * frag_bytes : 0) +
+                       ((r.prefetch & 2) ? u_bytes : 0);
         if (g->lds_bytes > kMaxLdsPerWorkgroup)
             return set_error(LPX_ERR_UNSUPPORTED,
                              "prefetch=1 needs %lld bytes of LDS per work-group for K=%d "
@@ -238,7 +239,7 @@ lpx_status lpx_record_enumerate(const lpx_problem* p, lpx_record* recs, int32_t 
     static const uint8_t unrolls[] = {1, 2, 4};
     int32_t count = 0;
     for (uint8_t t : tiles)
-        for (uint8_t pf = 0; pf < 2; ++pf)
+        for (uint8_t pf = 0; pf < 4; ++pf)
             for (uint8_t un : unrolls) {
                 if (count < cap) {
                     lpx_record r = default_record(p->precision);

@@ -22,7 +22,12 @@ ContractFn by_unroll(int un) {
 
 template <int LAYOUT, int NTMAX, int TILE_E>
 ContractFn by_prefetch(int pf, int un) {
-    return pf ? by_unroll<LAYOUT, NTMAX, TILE_E, 1>(un) : by_unroll<LAYOUT, NTMAX, TILE_E, 0>(un);
+    switch (pf) {
+        case 0: return by_unroll<LAYOUT, NTMAX, TILE_E, 0>(un);
+        case 1: return by_unroll<LAYOUT, NTMAX, TILE_E, 1>(un);
+        case 2: return by_unroll<LAYOUT, NTMAX, TILE_E, 2>(un);
+        default: return by_unroll<LAYOUT, NTMAX, TILE_E, 3>(un);
+    }
 }
 
 template <int LAYOUT, int NTMAX>

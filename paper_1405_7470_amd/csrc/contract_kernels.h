@@ -8,13 +8,16 @@
 //             array-axis tags, sec. 2.4.3)
 //   NTMAX     compiled bound on the number of 16-row i-blocks (2, 4, 8)
 //   TILE_E    split_iname(e, TILE_E), outer index -> work-group (sec. 2.4.1)
-//   PREFETCH  add_prefetch of the u tile and of D into LDS (sec. 2.4.4)
+//   PREFETCH  add_prefetch (sec. 2.4.4), one bit per array: bit 0 stages all
+//             of D in LDS (once per work-group), bit 1 stages each u tile
 //   UNROLL    split of the MFMA k-step loop with the inner part unrolled
 //             (tag "unr", sec. 2.4.2)
 //
 // Work decomposition.  A work-group (4 wave64s) walks the element tiles
 // tile = blockIdx.x, blockIdx.x + gridDim.x, ... (grid sized to the
-// resident capacity, so LDS-staged D is loaded once per work-group).  A tile
+// resident capacity, so LDS-staged D is loaded once per work-group).
+// Without the u bit, each wave streams its u fragments from global memory
+// straight into registers and needs no work-group barrier per tile.  A tile
 // of TILE_E elements is split into 16-element blocks; each block's K*nt
 // (operator, i-block) pairs are spread over 64/TILE_E waves.  A wave owns a
 // set of pairs and, for one 16-element block, accumulates
@@ -322,9 +325,11 @@ __global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs a) {
     const int part = wave % WPE;  // which share of that block's pairs
     const int npairs = a.K * a.nt;
     const int64_t nfrag = (int64_t)npairs * a.nsteps * 64;
-    unsigned char* ut = lds + nfrag * Lds<PREC>::DFRAG_BYTES * Lds<PREC>::PLANES;
+    constexpr bool PF_D = (PREFETCH & 1) != 0;
+    constexpr bool PF_U = (PREFETCH & 2) != 0;
+    unsigned char* ut = lds + (PF_D ? nfrag * Lds<PREC>::DFRAG_BYTES * Lds<PREC>::PLANES : 0);
 
-    if constexpr (PREFETCH) {
+    if constexpr (PF_D) {
         // D in operand order, converted once per work-group.
         for (int64_t idx = tid; idx < nfrag; idx += kThreads) {
             const int l = (int)(idx & 63);
@@ -335,18 +340,20 @@ __global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs a) {
             const int t = p - k * a.nt;
             d_frag_store_lds<PREC>(lds, nfrag, (int)idx, d_frag_global<PREC>(a, k, t, s, l));
         }
+    }
+    if constexpr (PF_U) {
         // Zero the padding columns [Np, ldu) of every tile row once; tile
         // staging never writes them.
         const int padw = a.ldu - a.Np;
         for (int f = tid; f < TILE_E * padw; f += kThreads)
             u_put_lds<PREC, TILE_E>(ut, a.ldu, f / padw, a.Np + f % padw, 0.0f);
-        __syncthreads();
     }
+    if constexpr (PREFETCH != 0) __syncthreads();
 
     for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
         const int64_t e0 = tile * TILE_E;
         const int nvalid = (int)((a.E - e0) < TILE_E ? (a.E - e0) : TILE_E);
-        if constexpr (PREFETCH) {
+        if constexpr (PF_U) {
             __syncthreads();  // previous tile's operand reads are done
             stage_u_tile<PREC, LAYOUT, TILE_E>(a, ut, e0, nvalid, tid);
             __syncthreads();
@@ -366,7 +373,7 @@ __global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs a) {
             }
             auto step = [&](int s) {
                 Frag<PREC> uf;
-                if constexpr (PREFETCH)
+                if constexpr (PF_U)
                     uf = u_frag_lds<PREC, TILE_E>(ut, a.ldu, 16 * eblk, s, lane);
                 else
                     uf = u_frag_global<PREC, LAYOUT>(a, eb0, s, lane);
@@ -375,7 +382,7 @@ __global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs a) {
                     const int p = pc + q * WPE;
                     if (p < npairs) {
                         Frag<PREC> df;
-                        if constexpr (PREFETCH)
+                        if constexpr (PF_D)
                             df = d_frag_lds<PREC>(lds, nfrag, (p * a.nsteps + s) * 64 + lane);
                         else
                             df = d_frag_global<PREC>(a, pk[q], pt[q], s, lane);

@@ -112,7 +112,16 @@ def lib():
         L.lpx_contract_validate.argtypes = [ctypes.POINTER(ContractDesc), ctypes.POINTER(Record)]
         L.lpx_contract.argtypes = [ctypes.POINTER(ContractDesc), ctypes.POINTER(Record), vp]
         L.lpx_split_bf16.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
-        for name in ("lpx_record_default", "lpx_record_validate", "lpx_record_describe",
+        L.lpx_autotune.argtypes = [ctypes.POINTER(ContractDesc), ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32, vp, ctypes.POINTER(Record),
+                                   ctypes.POINTER(ctypes.c_float), ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_int32)]
+        L.lpx_tune_cache_insert.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Record)]
+        L.lpx_tune_cache_clear.argtypes = []
+        L.lpx_stream_probe.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, vp]
+        L.lpx_stream_probe.restype = st
+        for name in ("lpx_autotune", "lpx_tune_cache_insert", "lpx_tune_cache_clear",
+                     "lpx_record_default", "lpx_record_validate", "lpx_record_describe",
                      "lpx_record_enumerate", "lpx_contract_lds_bytes", "lpx_contract_validate",
                      "lpx_contract", "lpx_split_bf16"):
             getattr(L, name).restype = st
@@ -274,3 +283,39 @@ def split_bf16(x, hi=None, lo=None, stream=None):
                                 ctypes.c_void_p(lo.data_ptr() if n else None), n,
                                 _stream_handle(stream)))
     return hi, lo
+
+
+# ------------------------------------------------------------- autotuning
+def autotune(D, u, out=None, layout="em", precision="fp32", warmup=2, reps=7, stream=None):
+    """Exhaustive tuning on the given buffers; returns (best Record, list of
+    median microseconds per candidate in enumeration order; inf = skipped)."""
+    K, Np, E = contract_shapes(D, u, layout)
+    if out is None:
+        out = torch.empty(out_shape(K, Np, E, layout), dtype=torch.float32, device=u.device)
+    desc = make_desc(D, u, out, layout)
+    best = Record()
+    times = (ctypes.c_float * 32)()
+    n = ctypes.c_int32()
+    _check(lib().lpx_autotune(ctypes.byref(desc), PRECISION[precision], warmup, reps,
+                              _stream_handle(stream), ctypes.byref(best), times, 32,
+                              ctypes.byref(n)))
+    return best, [times[i] for i in range(n.value)]
+
+
+def tune_cache_insert(K, Np, E, layout, rec):
+    p = problem(K, Np, E, layout, PRECISION_NAME[rec.precision])
+    _check(lib().lpx_tune_cache_insert(ctypes.byref(p), ctypes.byref(rec)))
+
+
+def tune_cache_clear():
+    _check(lib().lpx_tune_cache_clear())
+
+
+def stream_probe(x, y, fanout=1, stream=None):
+    """y[r*n:(r+1)*n] = x for r < fanout (HBM streaming probe)."""
+    n = x.numel()
+    if y.numel() != fanout * n:
+        raise ValueError("y must hold fanout * x.numel() floats")
+    _check(lib().lpx_stream_probe(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                  n, fanout, _stream_handle(stream)))
+    return y

@@ -51,15 +51,15 @@ def test_default_record_is_the_untuned_variant():
 
 def test_enumeration_canonical_order_and_truncation():
     recs = lpx.enumerate_records(3, 56, 1 << 20, "em", "bf16x3")
-    assert len(recs) == 18
+    assert len(recs) == 36
     keys = [(r.tile_e, r.prefetch, r.unroll) for r in recs]
-    assert keys == [(t, p, u) for t in (16, 32, 64) for p in (0, 1) for u in (1, 2, 4)]
+    assert keys == [(t, p, u) for t in (16, 32, 64) for p in (0, 1, 2, 3) for u in (1, 2, 4)]
     assert all(lpx.PRECISION_NAME[r.precision] == "bf16x3" for r in recs)
     p = lpx.problem(3, 56, 1 << 20, "em", "fp32")
     arr = (lpx.Record * 4)()
     n = ctypes.c_int32()
     assert lpx.lib().lpx_record_enumerate(ctypes.byref(p), arr, 4, ctypes.byref(n)) == 0
-    assert n.value == 18 and arr[3].unroll == 1 and arr[3].prefetch == 1
+    assert n.value == 36 and arr[3].unroll == 1 and arr[3].prefetch == 1
 
 
 def test_describe():
@@ -68,7 +68,7 @@ def test_describe():
 
 
 @pytest.mark.parametrize("field,value", [
-    ("version", 2), ("precision", 3), ("tile_e", 8), ("tile_e", 128), ("prefetch", 2),
+    ("version", 2), ("precision", 3), ("tile_e", 8), ("tile_e", 128), ("prefetch", 4),
     ("unroll", 3), ("assume_tile_divides", 2), ("reserved1", 1)])
 def test_malformed_records_rejected(field, value):
     r = lpx.default_record()
@@ -130,15 +130,22 @@ def test_assumption_checked():
 
 
 def test_lds_budget():
-    # prefetch=1 stages all of D in LDS: Np = 128, K = 3 in FP32 needs
+    # prefetch bit 0 stages all of D in LDS: Np = 128, K = 3 in FP32 needs
     # 3*8*32*64*4 bytes of D fragments, above the 160 KiB per work-group
     r = lpx.record("fp32", 64, 1, 1)
     assert status(desc(Np=128), r) == lpx.ERR_UNSUPPORTED
     s, b = lpx.lds_bytes(3, 128, 4096, "em", r)
-    assert s == lpx.ERR_UNSUPPORTED and b == 3 * 8 * 32 * 64 * 4 + 64 * 130 * 4
-    # the config-scale shape fits: D 3*4*14*64*4 bytes + u tile 64*58*4
-    s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", r)
+    assert s == lpx.ERR_UNSUPPORTED and b == 3 * 8 * 32 * 64 * 4
+    # bit 1 alone stages only the u tile: 64 rows of 130 floats
+    s, b = lpx.lds_bytes(3, 128, 4096, "em", lpx.record("fp32", 64, 2, 1))
+    assert s == lpx.OK and b == 64 * 130 * 4
+    # the full-scale shape fits both: D 3*4*14*64*4 bytes + u tile 64*58*4
+    s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", lpx.record("fp32", 64, 3, 1))
     assert s == lpx.OK and b == 3 * 4 * 14 * 64 * 4 + 64 * 58 * 4
+    # bf16x3: two bf16 planes of D fragments (16 B per lane each), u rows
+    # padded to 64 + 8 bf16 in two planes
+    s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", lpx.record("bf16x3", 32, 3, 1))
+    assert s == lpx.OK and b == 3 * 4 * 2 * 64 * 32 + 32 * 72 * 4
     s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", lpx.record("fp32", 64, 0, 1))
     assert s == lpx.OK and b == 0
 

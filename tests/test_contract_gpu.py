@@ -50,7 +50,7 @@ def test_edge_shapes(precision, layout):
     shapes = [(1, 1), (1, 17), (10, 15), (16, 16), (17, 65), (64, 64), (84, 129),
               (120, 31), (128, 70)]
     recs = [lpx.record(precision, t, p, un) for (t, p, un) in
-            ((16, 0, 1), (64, 0, 4), (32, 1, 2), (64, 1, 1))]
+            ((16, 0, 1), (64, 0, 4), (32, 1, 2), (64, 3, 1), (16, 2, 4))]
     for Np, E in shapes:
         D, u = inputs.contraction_inputs(2, Np, E, seed=E, layout=layout)
         for rec in recs:
@@ -160,3 +160,28 @@ def test_errors_raise_and_alias_detected():
     with pytest.raises(lpx.LpxError) as ei:
         lpx.contract(D, u2, out=out)
     assert ei.value.status == lpx.ERR_ALIAS
+
+
+def test_autotune_picks_the_fastest_and_caches_it():
+    K, Np, E = 3, 20, 20000
+    D, u = inputs.contraction_inputs(K, Np, E, seed=14)
+    Dd, ud = to_dev(D), to_dev(u)
+    lpx.tune_cache_clear()
+    best, times = lpx.autotune(Dd, ud, layout="em", precision="bf16x3", warmup=1, reps=3)
+    recs = lpx.enumerate_records(K, Np, E, "em", "bf16x3")
+    assert len(times) == len(recs)
+    finite = [t for t in times if np.isfinite(t)]
+    assert finite and min(finite) == times[recs.index(best)]
+    # the tuner overwrote out with a valid result of the last candidate
+    out = lpx.contract(Dd, ud, record=best)
+    torch.cuda.synchronize()
+    check_against_oracle(D, u, as_em(out, "em"), "em", "bf16x3")
+
+
+def test_stream_probe():
+    x = torch.arange(1 << 16, dtype=torch.float32, device=dev())
+    for fanout in (1, 3):
+        y = torch.empty(fanout * x.numel(), device=dev())
+        lpx.stream_probe(x, y, fanout)
+        torch.cuda.synchronize()
+        assert torch.equal(y.view(fanout, -1), x.expand(fanout, -1))
