@@ -87,8 +87,9 @@ typedef int32_t lpx_status;
  *              work-group grid axis (sec. 2.4.1 eq. (1), sec. 2.4.2);
  *              16, 32 or 64 elements per work-group tile.  Inside a tile,
  *              e is split again by 16 (the MFMA column block) and i by 16
- *              (the MFMA row block); the (k, i-block) pairs of a 16-element
- *              block are spread over the work-group's four wavefronts.
+ *              (the MFMA row block); each 16-element block has four wave64s
+ *              that split its (k, i-block) pairs, so a work-group has
+ *              4 * tile_e / 16 wavefronts.
  *   prefetch : add_prefetch (sec. 2.4.4), one bit per array, 0..3.
  *              bit 0: all of D is staged in LDS once per work-group, in
  *              MFMA operand order and converted to the operand precision;
@@ -142,6 +143,18 @@ typedef struct lpx_contract_desc {
     float* out;       /* device, K*E*Np floats, 16-byte aligned; must   */
                       /* not overlap D or u                             */
 } lpx_contract_desc;
+
+/* -------------------------------------------------------------- GEMM */
+/* C = A B, row-major FP32 (the degenerate case of the contraction). */
+typedef struct lpx_gemm_desc {
+    int64_t M, N, K;  /* C is M x N, A is M x K, B is K x N; each >= 0       */
+    const float* A;   /* device; row m at A + m*lda; 16-byte aligned        */
+    int64_t lda;      /* >= K (rows 16-byte aligned when a multiple of 4)   */
+    const float* B;   /* device; row k at B + k*ldb; 16-byte aligned        */
+    int64_t ldb;      /* >= N                                               */
+    float* C;         /* device; row m at C + m*ldc; 16-byte aligned; must  */
+    int64_t ldc;      /* not overlap A or B; ldc >= N                       */
+} lpx_gemm_desc;
 
 /* ------------------------------------------------------ support calls */
 /* Library version string, e.g. "lpx 0.1.0 gfx950". */
@@ -198,6 +211,21 @@ lpx_status lpx_contract(const lpx_contract_desc* c, const lpx_record* rec,
  * can still occur in lpx_contract after this returns LPX_OK. */
 lpx_status lpx_contract_validate(const lpx_contract_desc* c, const lpx_record* rec);
 
+/* Dense GEMM  C[m][n] = sum_k A[m][k] B[k][n]  (the paper's sec. 2.1
+ * reduction example sum(k, a[i,k]*b[k,j]); Table 1 "sgemm"), enqueued on
+ * `stream`.  The record supplies the precision (as for lpx_contract; the
+ * products follow the same FP32 / BF16 / BF16X3 rules, FP32 accumulation)
+ * and the tiling: gemm_tm x gemm_tn tile of C per work-group, gemm_tk-deep
+ * k slabs staged in LDS (0 = 128 x 128 x 32).  Built tilings: 64x64x32,
+ * 64x64x64, 128x128x32, 128x128x64, 128x64x32, 64x128x32, and for FP32/BF16
+ * also 256x128x32, 128x256x32, 256x256x32; others return
+ * LPX_ERR_UNSUPPORTED.  C is overwritten (no alpha/beta).  rec = NULL means
+ * FP32 with the default tiling.  Errors as for lpx_contract. */
+lpx_status lpx_gemm(const lpx_gemm_desc* g, const lpx_record* rec, void* stream);
+
+/* Every pre-launch check of lpx_gemm, without any HIP call. */
+lpx_status lpx_gemm_validate(const lpx_gemm_desc* g, const lpx_record* rec);
+
 /* Split-precision conversion: hi[t] = bf16(x[t]), lo[t] = bf16(x[t] -
  * float(hi[t])), round-to-nearest-even, as raw bfloat16 bit patterns.
  * x, hi, lo are device pointers of n elements (x 4-byte, hi/lo 2-byte
@@ -205,6 +233,40 @@ lpx_status lpx_contract_validate(const lpx_contract_desc* c, const lpx_record* r
  * operand transformation behind LPX_BF16 (hi only) and LPX_BF16X3. */
 lpx_status lpx_split_bf16(const float* x, uint16_t* hi, uint16_t* lo,
                           int64_t n, void* stream);
+
+/* ------------------------------------------------------- ragged batch */
+/* Many contractions of uneven sizes in one persistent launch, captured
+ * once into a HIP graph and replayed.  Opaque, library-owned handle. */
+typedef struct lpx_batch lpx_batch;
+
+/* items[0..n-1]: contraction descriptors (validated as by lpx_contract; no
+ * zero sizes); all must share one layout.  recs: one record per item (all
+ * of one precision), or NULL to take each item's FP32 winner from the
+ * tuning cache, else the FP32 default.
+ *   *h == NULL: builds the batch -- instances ordered largest first (cost
+ *     K*Np^2*E), cut into 16-element tiles that persistent work-groups pull
+ *     from an atomic counter; a record's D-prefetch bit is honoured when
+ *     its staged D fits 48 KiB of LDS (else D is read from global memory);
+ *     the tile is fixed at 16 elements and u is streamed from global memory
+ *     -- captures [counter reset, persistent kernel] into a graph, launches
+ *     it on `stream`, and returns the handle in *h.
+ *   *h != NULL: items must have the batch's n and per-item K, Np, E and
+ *     layout (pointers may change); copies the updated descriptor table and
+ *     replays the graph on `stream`.
+ * Outputs are bit-identical to lpx_contract with the same precision (every
+ * record of a precision sums each output in the same order).  The caller
+ * keeps all buffers alive until `stream` passes the work. */
+lpx_status lpx_batch_submit(const lpx_contract_desc* items, const lpx_record* recs,
+                            int32_t n, lpx_batch** h, void* stream);
+
+/* Tiles in the batch, persistent grid size and dynamic LDS per work-group
+ * (any output pointer may be NULL). */
+lpx_status lpx_batch_info(const lpx_batch* b, int64_t* total_tiles, int32_t* grid,
+                          int64_t* lds_bytes);
+
+/* Frees the batch; the caller must first make sure no submitted replay is
+ * still running.  NULL is a no-op. */
+lpx_status lpx_batch_destroy(lpx_batch* b);
 
 /* ------------------------------------------------ variant selection */
 /* Exhaustive autotuner: times every candidate record of the problem

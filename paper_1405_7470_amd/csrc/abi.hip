@@ -66,6 +66,7 @@ lpx_status contract_geometry(int K, int Np, int64_t E, int layout,
     g->tile_e = r.tile_e;
     g->prefetch = r.prefetch;
     g->unroll = r.unroll;
+    g->threads = 64 * 4 * (r.tile_e / 16);
     g->kstep = (r.precision == LPX_FP32) ? 4 : 32;
     g->nt = (int)ceil_div(Np, 16);
     g->ntmax = g->nt <= 2 ? 2 : (g->nt <= 4 ? 4 : 8);
@@ -126,7 +127,7 @@ lpx_status current_device_info(DeviceInfo* out) {
 
 using namespace lpx;
 
-namespace {
+namespace lpx {
 
 bool overlaps(const void* a, int64_t abytes, const void* b, int64_t bbytes) {
     auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
@@ -174,7 +175,38 @@ lpx_status validate_contract(const lpx_contract_desc* c, const lpx_record* rec,
     return contract_geometry(c->K, c->Np, c->E, c->layout, r, g);
 }
 
-}  // namespace
+
+lpx_status validate_gemm(const lpx_gemm_desc* g, const lpx_record* rec, bool* noop) {
+    *noop = true;
+    if (!g) return set_error(LPX_ERR_INVALID_ARG, "descriptor is NULL");
+    lpx_record r = rec ? *rec : default_record(LPX_FP32);
+    lpx_status s = check_record(&r);
+    if (s != LPX_OK) return s;
+    if (g->M < 0 || g->N < 0 || g->K < 0)
+        return set_error(LPX_ERR_INVALID_ARG, "negative size");
+    int tm, tn, tk;
+    s = gemm_tiles(r, &tm, &tn, &tk);
+    if (s != LPX_OK) return s;
+    if (g->M == 0 || g->N == 0) return LPX_OK;  // nothing to write
+    if (!g->A && g->K > 0) return set_error(LPX_ERR_INVALID_ARG, "NULL A");
+    if (!g->B && g->K > 0) return set_error(LPX_ERR_INVALID_ARG, "NULL B");
+    if (!g->C) return set_error(LPX_ERR_INVALID_ARG, "NULL C");
+    if (g->lda < g->K || g->ldb < g->N || g->ldc < g->N)
+        return set_error(LPX_ERR_INVALID_ARG, "leading dimension below the row length");
+    if ((g->K > 0 && (!aligned16(g->A) || !aligned16(g->B))) || !aligned16(g->C))
+        return set_error(LPX_ERR_INVALID_ARG, "A, B and C must be 16-byte aligned");
+    int64_t abytes, bbytes, cbytes;
+    if (mul_overflows(g->M, g->lda, &abytes) || mul_overflows(g->K, g->ldb, &bbytes) ||
+        mul_overflows(g->M, g->ldc, &cbytes) || abytes > INT64_MAX / 4 ||
+        bbytes > INT64_MAX / 4 || cbytes > INT64_MAX / 4)
+        return set_error(LPX_ERR_INVALID_ARG, "size product overflows int64");
+    if (overlaps(g->C, cbytes * 4, g->A, abytes * 4) || overlaps(g->C, cbytes * 4, g->B, bbytes * 4))
+        return set_error(LPX_ERR_ALIAS, "C overlaps A or B");
+    *noop = false;
+    return LPX_OK;
+}
+
+}  // namespace lpx
 
 extern "C" {
 
@@ -287,6 +319,28 @@ lpx_status lpx_contract(const lpx_contract_desc* c, const lpx_record* rec, void*
         lpx_status s = validate_contract(c, rec, &g);
         if (s != LPX_OK || g.ntiles == 0) return s;
         return launch_contract(*c, g, stream);
+    } catch (...) {
+        return set_error(LPX_ERR_INTERNAL, "unexpected C++ exception");
+    }
+}
+
+lpx_status lpx_gemm_validate(const lpx_gemm_desc* g, const lpx_record* rec) {
+    clear_error();
+    try {
+        bool noop;
+        return validate_gemm(g, rec, &noop);
+    } catch (...) {
+        return set_error(LPX_ERR_INTERNAL, "unexpected C++ exception");
+    }
+}
+
+lpx_status lpx_gemm(const lpx_gemm_desc* g, const lpx_record* rec, void* stream) {
+    clear_error();
+    try {
+        bool noop;
+        lpx_status s = validate_gemm(g, rec, &noop);
+        if (s != LPX_OK || noop) return s;
+        return launch_gemm(*g, rec ? *rec : default_record(LPX_FP32), stream);
     } catch (...) {
         return set_error(LPX_ERR_INTERNAL, "unexpected C++ exception");
     }

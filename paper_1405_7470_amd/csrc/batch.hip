@@ -1,0 +1,357 @@
+// Ragged batch of contractions in one persistent, graph-captured launch.
+//
+// Each instance i (its own K, Np, E, pointers, record) is cut into 16-element
+// tiles; the tiles of all instances form one list, largest instances first
+// (longest-processing-time order, cost K*Np^2*E).  Persistent work-groups of
+// four waves pull chunks of tiles from one atomic counter, find each tile's
+// instance by binary search over the instances' first-tile indices, and run
+// the same per-block routine as lpx_contract (four waves split the block's
+// (k, i-block) pairs).  D is staged in LDS when the instance's record asks
+// for it and it fits the batch's LDS budget; otherwise D fragments are read
+// from global memory.  Every output's summation order depends only on the
+// precision, so the batch is bit-identical to separate lpx_contract calls.
+//
+// The counter reset (a one-thread kernel, not a memset node) and the batch
+// kernel are captured once into a HIP graph on a library-owned stream;
+// lpx_batch_submit replays it on the caller's stream after copying the
+// (possibly updated) descriptor table.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "contract_kernels.h"
+
+namespace lpx {
+namespace batchk {
+
+constexpr int kThreadsB = 256;
+constexpr int kChunk = 8;                         // tiles per counter fetch
+constexpr int64_t kLdsBudget = 48 * 1024;         // D staging budget per work-group
+
+struct Item {
+    kern::ContractArgs a;
+    int64_t tile_begin;  // first global tile index of this instance
+    int d_lds;           // stage D in LDS for this instance
+    int pad;
+};
+
+struct BatchArgs {
+    const Item* __restrict__ items;
+    unsigned long long* counter;
+    int64_t total_tiles;
+    int n;
+};
+
+__global__ void reset_counter(unsigned long long* c) { *c = 0ull; }
+
+template <int PREC, int LAYOUT, int NTMAX>
+__global__ __launch_bounds__(kThreadsB) void batch_kernel(BatchArgs b) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ long long s_t0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int cur = -1;
+    for (;;) {
+        if (tid == 0) s_t0 = (long long)atomicAdd(b.counter, (unsigned long long)kChunk);
+        __syncthreads();
+        const long long tv = s_t0;  // the same value in every lane: make it scalar
+        const int64_t t0 = ((int64_t)__builtin_amdgcn_readfirstlane((int)(tv >> 32)) << 32) |
+                           (uint32_t)__builtin_amdgcn_readfirstlane((int)(tv & 0xffffffff));
+        __syncthreads();  // every thread has read s_t0 before it is rewritten
+        if (t0 >= b.total_tiles) break;  // uniform: all waves leave together
+        const int64_t t1 = t0 + kChunk < b.total_tiles ? t0 + kChunk : b.total_tiles;
+        for (int64_t t = t0; t < t1; ++t) {
+            int lo = 0, hi = b.n - 1;  // last instance with tile_begin <= t
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (b.items[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+            }
+            const kern::ContractArgs a = b.items[lo].a;
+            const bool dl = b.items[lo].d_lds != 0;
+            if (lo != cur) {
+                cur = lo;
+                if (dl) {
+                    __syncthreads();  // the previous instance's D is no longer read
+                    kern::stage_d<PREC, kThreadsB>(a, lds, tid);
+                    __syncthreads();
+                }
+            }
+            const int64_t eb0 = (t - b.items[lo].tile_begin) * 16;
+            if (dl)
+                kern::block_compute<PREC, LAYOUT, NTMAX, true, false, 16, 2>(a, lds, nullptr, 0,
+                                                                             eb0, wave, lane);
+            else
+                kern::block_compute<PREC, LAYOUT, NTMAX, false, false, 16, 2>(a, lds, nullptr, 0,
+                                                                              eb0, wave, lane);
+        }
+    }
+}
+
+using BatchFn = void (*)(BatchArgs);
+
+template <int PREC>
+BatchFn pick(int layout, int ntmax) {
+    if (layout == LPX_ELEMENT_MAJOR) {
+        if (ntmax == 2) return &batch_kernel<PREC, LPX_ELEMENT_MAJOR, 2>;
+        if (ntmax == 4) return &batch_kernel<PREC, LPX_ELEMENT_MAJOR, 4>;
+        return &batch_kernel<PREC, LPX_ELEMENT_MAJOR, 8>;
+    }
+    if (ntmax == 2) return &batch_kernel<PREC, LPX_DOF_MAJOR, 2>;
+    if (ntmax == 4) return &batch_kernel<PREC, LPX_DOF_MAJOR, 4>;
+    return &batch_kernel<PREC, LPX_DOF_MAJOR, 8>;
+}
+
+}  // namespace batchk
+
+}  // namespace lpx
+
+using namespace lpx;
+using namespace lpx::batchk;
+
+struct lpx_batch {
+    int32_t n = 0;
+    int precision = 0, layout = 0, ntmax = 2;
+    std::vector<int32_t> K, Np;
+    std::vector<int64_t> E;
+    std::vector<int32_t> order;       // instance index of each table slot
+    Item* host_items = nullptr;       // pinned host copy of the table
+    Item* dev_items = nullptr;
+    unsigned long long* counter = nullptr;
+    int64_t total_tiles = 0, lds = 0;
+    int grid = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t copied = nullptr;      // the table copy of the last submit is done
+    int device = -1;
+};
+
+namespace {
+
+lpx_status hip_err(hipError_t e, const char* what) {
+    return set_error(LPX_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+void free_batch(lpx_batch* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->copied) (void)hipEventDestroy(b->copied);
+    if (b->dev_items) (void)hipFree(b->dev_items);
+    if (b->counter) (void)hipFree(b->counter);
+    if (b->host_items) (void)hipHostFree(b->host_items);
+    delete b;
+}
+
+// Fills the pinned table from the descriptors (shapes already validated).
+lpx_status fill_table(lpx_batch* b, const lpx_contract_desc* items, const lpx_record* recs) {
+    int64_t tile = 0;
+    for (int32_t slot = 0; slot < b->n; ++slot) {
+        const int32_t i = b->order[slot];
+        const lpx_contract_desc& c = items[i];
+        lpx_record r = recs ? recs[i] : default_record(b->precision);
+        ContractGeom g;
+        lpx_status s = contract_geometry(c.K, c.Np, c.E, c.layout, r, &g);
+        if (s != LPX_OK) return s;
+        Item& it = b->host_items[slot];
+        std::memset(&it, 0, sizeof it);
+        it.a.D = c.D;
+        it.a.u = c.u;
+        it.a.out = c.out;
+        it.a.E = c.E;
+        it.a.ntiles = ceil_div(c.E, 16);
+        it.a.K = c.K;
+        it.a.Np = c.Np;
+        it.a.nt = g.nt;
+        it.a.nsteps = g.nsteps;
+        it.a.ldu = g.ldu;
+        it.a.np_vec = (c.Np % 4) == 0;
+        it.a.e_vec = (c.E % 4) == 0;
+        it.tile_begin = tile;
+        const int64_t frag_bytes = b->precision == LPX_FP32 ? 4 : (b->precision == LPX_BF16 ? 16 : 32);
+        const int64_t dbytes = g.nfrag * frag_bytes;
+        it.d_lds = (r.prefetch & 1) && dbytes <= kLdsBudget;
+        if (it.d_lds) b->lds = std::max(b->lds, dbytes);
+        tile += it.a.ntiles;
+    }
+    b->total_tiles = tile;
+    return LPX_OK;
+}
+
+lpx_status check_items(const lpx_contract_desc* items, const lpx_record* recs, int32_t n,
+                       int* precision, int* layout, int* ntmax) {
+    if (!items || n <= 0) return set_error(LPX_ERR_INVALID_ARG, "need n > 0 descriptors");
+    *precision = recs ? recs[0].precision : LPX_FP32;
+    *layout = items[0].layout;
+    *ntmax = 2;
+    for (int32_t i = 0; i < n; ++i) {
+        const lpx_record* r = recs ? &recs[i] : nullptr;
+        ContractGeom g;
+        lpx_status s = validate_contract(&items[i], r, &g);
+        if (s != LPX_OK) {
+            std::string why = last_error_text();  // set_error overwrites it
+            return set_error(s, "instance %d: %s", i, why.c_str());
+        }
+        if ((r ? r->precision : LPX_FP32) != *precision || items[i].layout != *layout)
+            return set_error(LPX_ERR_UNSUPPORTED,
+                             "instance %d: a batch needs one precision and one layout", i);
+        if (items[i].K == 0 || items[i].Np == 0 || items[i].E == 0)
+            return set_error(LPX_ERR_INVALID_ARG, "instance %d has a zero size", i);
+        *ntmax = std::max(*ntmax, g.ntmax);
+    }
+    return LPX_OK;
+}
+
+lpx_status create(const lpx_contract_desc* items, const lpx_record* recs, int32_t n,
+                  lpx_batch** out) {
+    int precision, layout, ntmax;
+    lpx_status s = check_items(items, recs, n, &precision, &layout, &ntmax);
+    if (s != LPX_OK) return s;
+    lpx_batch* b = new lpx_batch;
+    b->n = n;
+    b->precision = precision;
+    b->layout = layout;
+    b->ntmax = ntmax;
+    for (int32_t i = 0; i < n; ++i) {
+        b->K.push_back(items[i].K);
+        b->Np.push_back(items[i].Np);
+        b->E.push_back(items[i].E);
+    }
+    b->order.resize(n);
+    std::iota(b->order.begin(), b->order.end(), 0);
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int32_t x, int32_t y) {
+        auto cost = [&](int32_t i) { return (double)items[i].K * items[i].Np * items[i].Np * items[i].E; };
+        return cost(x) > cost(y);
+    });
+    hipError_t e = hipGetDevice(&b->device);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b->host_items, sizeof(Item) * n, hipHostMallocDefault);
+    if (e != hipSuccess) { free_batch(b); return hip_err(e, "batch host table"); }
+    if ((s = fill_table(b, items, recs)) != LPX_OK) { free_batch(b); return s; }
+    if ((e = hipMalloc((void**)&b->dev_items, sizeof(Item) * n)) != hipSuccess ||
+        (e = hipMalloc((void**)&b->counter, sizeof(unsigned long long))) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&b->copied, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
+        free_batch(b);
+        return hip_err(e, "batch allocation");
+    }
+    BatchFn fn = precision == LPX_FP32 ? pick<LPX_FP32>(layout, ntmax)
+               : precision == LPX_BF16 ? pick<LPX_BF16>(layout, ntmax)
+                                       : pick<LPX_BF16X3>(layout, ntmax);
+    DeviceInfo dev;
+    if ((s = current_device_info(&dev)) != LPX_OK) { free_batch(b); return s; }
+    int nb = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(fn),
+                                                     kThreadsB, (size_t)b->lds);
+    if (e != hipSuccess) { free_batch(b); return hip_err(e, "batch occupancy"); }
+    if (nb <= 0) { free_batch(b); return set_error(LPX_ERR_UNSUPPORTED, "batch kernel cannot be resident"); }
+    int64_t grid = (int64_t)nb * dev.num_cu;
+    const int64_t need = ceil_div(b->total_tiles, kChunk);
+    b->grid = (int)std::max<int64_t>(1, std::min(grid, need));
+
+    // Capture [reset counter, batch kernel] once.
+    BatchArgs args{b->dev_items, b->counter, b->total_tiles, n};
+    e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, b->cap_stream, b->counter);
+        void* kargs[] = {&args};
+        hipError_t le = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(b->grid),
+                                        dim3(kThreadsB), kargs, (size_t)b->lds, b->cap_stream);
+        e = hipStreamEndCapture(b->cap_stream, &b->graph);
+        if (e == hipSuccess && le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) { free_batch(b); return hip_err(e, "batch graph capture"); }
+    *out = b;
+    return LPX_OK;
+}
+
+lpx_status replay(lpx_batch* b, void* stream) {
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(b->dev_items, b->host_items, sizeof(Item) * b->n,
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(b->copied, st);
+    if (e == hipSuccess) e = hipGraphLaunch(b->exec, st);
+    if (e != hipSuccess) return hip_err(e, "batch replay");
+    return LPX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lpx_status lpx_batch_submit(const lpx_contract_desc* items, const lpx_record* recs, int32_t n,
+                            lpx_batch** h, void* stream) {
+    clear_error();
+    try {
+        if (!h) return set_error(LPX_ERR_INVALID_ARG, "handle pointer is NULL");
+        if (*h == nullptr) {
+            // Records: the caller's, else the tuning cache's, else the default.
+            std::vector<lpx_record> rv;
+            if (!recs && items && n > 0) {
+                rv.resize(n);
+                for (int32_t i = 0; i < n; ++i) {
+                    lpx_problem p{items[i].K, items[i].Np, items[i].E, items[i].layout, LPX_FP32};
+                    if (tuned_lookup(p, &rv[i]) != LPX_OK) rv[i] = default_record(LPX_FP32);
+                }
+                clear_error();
+                recs = rv.data();
+            }
+            lpx_batch* b = nullptr;
+            lpx_status s = create(items, recs, n, &b);
+            if (s != LPX_OK) return s;
+            s = replay(b, stream);
+            if (s != LPX_OK) { free_batch(b); return s; }
+            *h = b;
+            return LPX_OK;
+        }
+        lpx_batch* b = *h;
+        if (!items || n != b->n)
+            return set_error(LPX_ERR_INVALID_ARG, "update needs the batch's %d descriptors", b->n);
+        for (int32_t i = 0; i < n; ++i) {
+            if (items[i].K != b->K[i] || items[i].Np != b->Np[i] || items[i].E != b->E[i] ||
+                items[i].layout != b->layout)
+                return set_error(LPX_ERR_INVALID_ARG, "instance %d changed shape; create a new batch", i);
+            lpx_record r = default_record(b->precision);
+            ContractGeom g;
+            lpx_status s = validate_contract(&items[i], &r, &g);
+            if (s != LPX_OK) {
+                std::string why = last_error_text();
+                return set_error(s, "instance %d: %s", i, why.c_str());
+            }
+        }
+        // The previous table copy must have finished before it is rewritten.
+        hipError_t e = hipEventSynchronize(b->copied);
+        if (e != hipSuccess) return hip_err(e, "batch update");
+        for (int32_t slot = 0; slot < b->n; ++slot) {
+            const lpx_contract_desc& c = items[b->order[slot]];
+            b->host_items[slot].a.D = c.D;
+            b->host_items[slot].a.u = c.u;
+            b->host_items[slot].a.out = c.out;
+        }
+        return replay(b, stream);
+    } catch (...) {
+        return set_error(LPX_ERR_INTERNAL, "unexpected C++ exception");
+    }
+}
+
+lpx_status lpx_batch_info(const lpx_batch* b, int64_t* total_tiles, int32_t* grid,
+                          int64_t* lds_bytes) {
+    clear_error();
+    if (!b) return set_error(LPX_ERR_INVALID_ARG, "batch is NULL");
+    if (total_tiles) *total_tiles = b->total_tiles;
+    if (grid) *grid = b->grid;
+    if (lds_bytes) *lds_bytes = b->lds;
+    return LPX_OK;
+}
+
+lpx_status lpx_batch_destroy(lpx_batch* b) {
+    clear_error();
+    free_batch(b);
+    return LPX_OK;
+}
+
+}  // extern "C"

@@ -13,13 +13,14 @@
 //   UNROLL    split of the MFMA k-step loop with the inner part unrolled
 //             (tag "unr", sec. 2.4.2)
 //
-// Work decomposition.  A work-group (4 wave64s) walks the element tiles
+// Work decomposition.  A work-group (4 wave64s per 16 elements of the
+// tile) walks the element tiles
 // tile = blockIdx.x, blockIdx.x + gridDim.x, ... (grid sized to the
 // resident capacity, so LDS-staged D is loaded once per work-group).
 // Without the u bit, each wave streams its u fragments from global memory
 // straight into registers and needs no work-group barrier per tile.  A tile
 // of TILE_E elements is split into 16-element blocks; each block's K*nt
-// (operator, i-block) pairs are spread over 64/TILE_E waves.  A wave owns a
+// (operator, i-block) pairs are spread over its 4 waves.  A wave owns a
 // set of pairs and, for one 16-element block, accumulates
 //     C_pair[16 x 16] += A[16 x kstep] * B[kstep x 16]
 // over the k-steps of j.  The two operands are a D fragment (16 rows of
@@ -263,7 +264,7 @@ __device__ __forceinline__ Frag<PREC> u_frag_lds(const unsigned char* ut, int ld
 
 // Stage the u tile [e0, e0 + nvalid) into LDS rows 0..nvalid-1, columns
 // 0..Np-1 (the zero columns Np..ldu-1 are written once at kernel start).
-template <int PREC, int LAYOUT, int TILE_E>
+template <int PREC, int LAYOUT, int TILE_E, int NTHREADS>
 __device__ __forceinline__ void stage_u_tile(const ContractArgs& a, unsigned char* ut,
                                              int64_t e0, int nvalid, int tid) {
     const int Np = a.Np;
@@ -274,7 +275,7 @@ __device__ __forceinline__ void stage_u_tile(const ContractArgs& a, unsigned cha
         const float inv = 1.0f / (float)Np;
         if (a.np_vec) {
             // 16-byte chunks never straddle a row when Np % 4 == 0.
-            for (int c = tid; c < nflat / 4; c += kThreads) {
+            for (int c = tid; c < nflat / 4; c += NTHREADS) {
                 f4 v = reinterpret_cast<const f4*>(src)[c];
                 const int f = 4 * c;
                 const int r = (int)(((float)f + 0.5f) * inv);  // exact: f < 2^13
@@ -283,7 +284,7 @@ __device__ __forceinline__ void stage_u_tile(const ContractArgs& a, unsigned cha
                 for (int q = 0; q < 4; ++q) u_put_lds<PREC, TILE_E>(ut, a.ldu, r, j + q, v[q]);
             }
         } else {
-            for (int f = tid; f < nflat; f += kThreads) {
+            for (int f = tid; f < nflat; f += NTHREADS) {
                 const int r = (int)(((float)f + 0.5f) * inv);
                 u_put_lds<PREC, TILE_E>(ut, a.ldu, r, f - r * Np, src[f]);
             }
@@ -292,7 +293,7 @@ __device__ __forceinline__ void stage_u_tile(const ContractArgs& a, unsigned cha
         // Np rows of nvalid contiguous floats, row stride E.
         if (a.e_vec) {
             constexpr int CPR = TILE_E / 4;  // 16-byte chunks per row
-            for (int c = tid; c < Np * CPR; c += kThreads) {
+            for (int c = tid; c < Np * CPR; c += NTHREADS) {
                 const int j = c / CPR;
                 const int r = 4 * (c % CPR);
                 if (r < nvalid) {  // E % 4 == 0 and e0 % 4 == 0: all 4 valid
@@ -302,7 +303,7 @@ __device__ __forceinline__ void stage_u_tile(const ContractArgs& a, unsigned cha
                 }
             }
         } else {
-            for (int f = tid; f < Np * TILE_E; f += kThreads) {
+            for (int f = tid; f < Np * TILE_E; f += NTHREADS) {
                 const int j = f / TILE_E;
                 const int r = f % TILE_E;
                 if (r < nvalid) u_put_lds<PREC, TILE_E>(ut, a.ldu, r, j, a.u[(int64_t)j * a.E + e0 + r]);
@@ -311,41 +312,139 @@ __device__ __forceinline__ void stage_u_tile(const ContractArgs& a, unsigned cha
     }
 }
 
-// ------------------------------------------------------------ the kernel
-template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PREFETCH, int UNROLL>
-__global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs a) {
-    extern __shared__ __align__(16) unsigned char lds[];
-    constexpr int WPE = 64 / TILE_E;                // waves per 16-element block
+// ------------------------------------------------------ building blocks
+// D in MFMA operand order, converted to the operand precision, written to
+// LDS by the NTHREADS threads of a work-group (caller adds the barrier).
+template <int PREC, int NTHREADS>
+__device__ __forceinline__ void stage_d(const ContractArgs& a, unsigned char* lds, int tid) {
+    const int64_t nfrag = (int64_t)a.K * a.nt * a.nsteps * 64;
+    for (int64_t idx = tid; idx < nfrag; idx += NTHREADS) {
+        const int l = (int)(idx & 63);
+        const int rest = (int)(idx >> 6);
+        const int s = rest % a.nsteps;
+        const int p = rest / a.nsteps;
+        const int k = p / a.nt;
+        const int t = p - k * a.nt;
+        d_frag_store_lds<PREC>(lds, nfrag, (int)idx, d_frag_global<PREC>(a, k, t, s, l));
+    }
+}
+
+// One wave's share of a 16-element block starting at element eb0: the
+// (k, i-block) pairs p = part, part + 4, ... ; for each, the MFMA chain over
+// the k-steps of j, then the write-back.  D fragments come from LDS (PF_D)
+// or global memory; u fragments from the staged tile `ut` at row `row0`
+// (PF_U) or global memory.  The summation order of every output depends
+// only on PREC: all records of a precision give bit-identical results.
+template <int PREC, int LAYOUT, int NTMAX, bool PF_D, bool PF_U, int TILE_E, int UNROLL>
+__device__ __forceinline__ void block_compute(const ContractArgs& a, const unsigned char* lds,
+                                              const unsigned char* ut, int row0, int64_t eb0,
+                                              int part, int lane) {
+    constexpr int WPE = 4;                             // waves per 16-element block
     constexpr int PMAX = (3 * NTMAX + WPE - 1) / WPE;  // pairs held per wave
+    const int npairs = a.K * a.nt;
+    const int64_t nfrag = (int64_t)npairs * a.nsteps * 64;
+    for (int pc = part; pc < npairs; pc += WPE * PMAX) {
+        f4 acc[PMAX];
+        int pk[PMAX], pt[PMAX];
+#pragma unroll
+        for (int q = 0; q < PMAX; ++q) {
+            acc[q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            const int p = pc + q * WPE;
+            pk[q] = p / a.nt;
+            pt[q] = p - pk[q] * a.nt;
+        }
+        auto step = [&](int s) {
+            Frag<PREC> uf;
+            if constexpr (PF_U)
+                uf = u_frag_lds<PREC, TILE_E>(ut, a.ldu, row0, s, lane);
+            else
+                uf = u_frag_global<PREC, LAYOUT>(a, eb0, s, lane);
+#pragma unroll
+            for (int q = 0; q < PMAX; ++q) {
+                const int p = pc + q * WPE;
+                if (p < npairs) {
+                    Frag<PREC> df;
+                    if constexpr (PF_D)
+                        df = d_frag_lds<PREC>(lds, nfrag, (p * a.nsteps + s) * 64 + lane);
+                    else
+                        df = d_frag_global<PREC>(a, pk[q], pt[q], s, lane);
+                    if constexpr (LAYOUT == LPX_ELEMENT_MAJOR)
+                        acc[q] = mma(df, uf, acc[q]);  // rows i, columns e
+                    else
+                        acc[q] = mma(uf, df, acc[q]);  // rows e, columns i
+                }
+            }
+        };
+        int s = 0;
+        for (; s + UNROLL <= a.nsteps; s += UNROLL) {
+#pragma unroll
+            for (int uu = 0; uu < UNROLL; ++uu) step(s + uu);
+        }
+        for (; s < a.nsteps; ++s) step(s);
+
+#pragma unroll
+        for (int q = 0; q < PMAX; ++q) {
+            const int p = pc + q * WPE;
+            if (p >= npairs) continue;
+            const int k = pk[q], t = pt[q];
+            if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
+                const int64_t e = eb0 + (lane & 15);
+                const int i0 = 16 * t + 4 * (lane >> 4);
+                if (e < a.E && i0 < a.Np) {
+                    float* dst = a.out + ((int64_t)k * a.E + e) * a.Np + i0;
+                    if (a.np_vec) {
+                        *reinterpret_cast<f4*>(dst) = acc[q];
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (i0 + r < a.Np) dst[r] = acc[q][r];
+                    }
+                }
+            } else {
+                const int i = 16 * t + (lane & 15);
+                const int64_t e = eb0 + 4 * (lane >> 4);
+                if (i < a.Np && e < a.E) {
+                    float* dst = a.out + ((int64_t)k * a.Np + i) * a.E + e;
+                    if (a.e_vec) {
+                        *reinterpret_cast<f4*>(dst) = acc[q];
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (e + r < a.E) dst[r] = acc[q][r];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ the kernel
+// Work-group size of a TILE_E-element tile: four waves per 16-element
+// block, which split that block's (k, i-block) pairs between them.
+template <int TILE_E>
+constexpr int contract_threads() { return 64 * 4 * (TILE_E / 16); }
+
+template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PREFETCH, int UNROLL>
+__global__ __launch_bounds__(contract_threads<TILE_E>()) void contract_kernel(ContractArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    constexpr int NTHREADS = contract_threads<TILE_E>();
+    constexpr bool PF_D = (PREFETCH & 1) != 0;
+    constexpr bool PF_U = (PREFETCH & 2) != 0;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int eblk = wave / WPE;  // which 16-element block of the tile
-    const int part = wave % WPE;  // which share of that block's pairs
-    const int npairs = a.K * a.nt;
-    const int64_t nfrag = (int64_t)npairs * a.nsteps * 64;
-    constexpr bool PF_D = (PREFETCH & 1) != 0;
-    constexpr bool PF_U = (PREFETCH & 2) != 0;
+    const int eblk = wave / 4;  // which 16-element block of the tile
+    const int part = wave % 4;  // which share of that block's pairs
+    const int64_t nfrag = (int64_t)a.K * a.nt * a.nsteps * 64;
     unsigned char* ut = lds + (PF_D ? nfrag * Lds<PREC>::DFRAG_BYTES * Lds<PREC>::PLANES : 0);
 
-    if constexpr (PF_D) {
-        // D in operand order, converted once per work-group.
-        for (int64_t idx = tid; idx < nfrag; idx += kThreads) {
-            const int l = (int)(idx & 63);
-            const int rest = (int)(idx >> 6);
-            const int s = rest % a.nsteps;
-            const int p = rest / a.nsteps;
-            const int k = p / a.nt;
-            const int t = p - k * a.nt;
-            d_frag_store_lds<PREC>(lds, nfrag, (int)idx, d_frag_global<PREC>(a, k, t, s, l));
-        }
-    }
+    if constexpr (PF_D) stage_d<PREC, NTHREADS>(a, lds, tid);
     if constexpr (PF_U) {
         // Zero the padding columns [Np, ldu) of every tile row once; tile
         // staging never writes them.
         const int padw = a.ldu - a.Np;
-        for (int f = tid; f < TILE_E * padw; f += kThreads)
+        for (int f = tid; f < TILE_E * padw; f += NTHREADS)
             u_put_lds<PREC, TILE_E>(ut, a.ldu, f / padw, a.Np + f % padw, 0.0f);
     }
     if constexpr (PREFETCH != 0) __syncthreads();
@@ -355,85 +454,12 @@ __global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs a) {
         const int nvalid = (int)((a.E - e0) < TILE_E ? (a.E - e0) : TILE_E);
         if constexpr (PF_U) {
             __syncthreads();  // previous tile's operand reads are done
-            stage_u_tile<PREC, LAYOUT, TILE_E>(a, ut, e0, nvalid, tid);
+            stage_u_tile<PREC, LAYOUT, TILE_E, NTHREADS>(a, ut, e0, nvalid, tid);
             __syncthreads();
         }
-        const int64_t eb0 = e0 + 16 * eblk;
         if (16 * eblk >= nvalid) continue;  // uniform per wave; no barrier below
-
-        for (int pc = part; pc < npairs; pc += WPE * PMAX) {
-            f4 acc[PMAX];
-            int pk[PMAX], pt[PMAX];
-#pragma unroll
-            for (int q = 0; q < PMAX; ++q) {
-                acc[q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-                const int p = pc + q * WPE;
-                pk[q] = p / a.nt;
-                pt[q] = p - pk[q] * a.nt;
-            }
-            auto step = [&](int s) {
-                Frag<PREC> uf;
-                if constexpr (PF_U)
-                    uf = u_frag_lds<PREC, TILE_E>(ut, a.ldu, 16 * eblk, s, lane);
-                else
-                    uf = u_frag_global<PREC, LAYOUT>(a, eb0, s, lane);
-#pragma unroll
-                for (int q = 0; q < PMAX; ++q) {
-                    const int p = pc + q * WPE;
-                    if (p < npairs) {
-                        Frag<PREC> df;
-                        if constexpr (PF_D)
-                            df = d_frag_lds<PREC>(lds, nfrag, (p * a.nsteps + s) * 64 + lane);
-                        else
-                            df = d_frag_global<PREC>(a, pk[q], pt[q], s, lane);
-                        if constexpr (LAYOUT == LPX_ELEMENT_MAJOR)
-                            acc[q] = mma(df, uf, acc[q]);  // rows i, columns e
-                        else
-                            acc[q] = mma(uf, df, acc[q]);  // rows e, columns i
-                    }
-                }
-            };
-            int s = 0;
-            for (; s + UNROLL <= a.nsteps; s += UNROLL) {
-#pragma unroll
-                for (int uu = 0; uu < UNROLL; ++uu) step(s + uu);
-            }
-            for (; s < a.nsteps; ++s) step(s);
-
-#pragma unroll
-            for (int q = 0; q < PMAX; ++q) {
-                const int p = pc + q * WPE;
-                if (p >= npairs) continue;
-                const int k = pk[q], t = pt[q];
-                if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
-                    const int64_t e = eb0 + (lane & 15);
-                    const int i0 = 16 * t + 4 * (lane >> 4);
-                    if (e < a.E && i0 < a.Np) {
-                        float* dst = a.out + ((int64_t)k * a.E + e) * a.Np + i0;
-                        if (a.np_vec) {
-                            *reinterpret_cast<f4*>(dst) = acc[q];
-                        } else {
-#pragma unroll
-                            for (int r = 0; r < 4; ++r)
-                                if (i0 + r < a.Np) dst[r] = acc[q][r];
-                        }
-                    }
-                } else {
-                    const int i = 16 * t + (lane & 15);
-                    const int64_t e = eb0 + 4 * (lane >> 4);
-                    if (i < a.Np && e < a.E) {
-                        float* dst = a.out + ((int64_t)k * a.Np + i) * a.E + e;
-                        if (a.e_vec) {
-                            *reinterpret_cast<f4*>(dst) = acc[q];
-                        } else {
-#pragma unroll
-                            for (int r = 0; r < 4; ++r)
-                                if (e + r < a.E) dst[r] = acc[q][r];
-                        }
-                    }
-                }
-            }
-        }
+        block_compute<PREC, LAYOUT, NTMAX, PF_D, PF_U, TILE_E, UNROLL>(
+            a, lds, ut, 16 * eblk, e0 + 16 * eblk, part, lane);
     }
 }
 

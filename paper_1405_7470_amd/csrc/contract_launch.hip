@@ -25,7 +25,7 @@ ContractFn select(const ContractGeom& g) {
 }
 
 // Resident work-groups per CU for (kernel, dynamic LDS), cached per device.
-lpx_status blocks_per_cu(const void* fn, int64_t lds, int device, int* out) {
+lpx_status blocks_per_cu(const void* fn, int threads, int64_t lds, int device, int* out) {
     static std::mutex mu;
     static std::map<std::pair<std::pair<const void*, int64_t>, int>, int> cache;
     static std::map<std::pair<const void*, int>, bool> lds_attr_set;
@@ -44,7 +44,7 @@ lpx_status blocks_per_cu(const void* fn, int64_t lds, int device, int* out) {
         lds_attr_set[{fn, device}] = true;
     }
     int nb = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kThreads, (size_t)lds);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, (size_t)lds);
     if (e != hipSuccess)
         return set_error(LPX_ERR_HIP, "hipOccupancyMaxActiveBlocksPerMultiprocessor: %s",
                          hipGetErrorString(e));
@@ -64,7 +64,7 @@ lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g, vo
                          (long long)g.lds_bytes, dev.max_lds_per_block);
     ContractFn fn = select(g);
     int nb = 0;
-    s = blocks_per_cu(reinterpret_cast<const void*>(fn), g.lds_bytes, dev.device, &nb);
+    s = blocks_per_cu(reinterpret_cast<const void*>(fn), g.threads, g.lds_bytes, dev.device, &nb);
     if (s != LPX_OK) return s;
     if (nb <= 0)
         return set_error(LPX_ERR_UNSUPPORTED, "kernel cannot be resident (LDS %lld bytes)",
@@ -87,7 +87,7 @@ lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g, vo
     a.e_vec = (c.E % 4) == 0;
     void* args[] = {&a};
     hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)grid),
-                                   dim3(kThreads), args, (size_t)g.lds_bytes,
+                                   dim3(g.threads), args, (size_t)g.lds_bytes,
                                    reinterpret_cast<hipStream_t>(stream));
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess)

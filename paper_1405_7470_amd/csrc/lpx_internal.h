@@ -12,7 +12,6 @@ namespace lpx {
 // gfx950 limits used by host-side validation (no HIP call needed).
 constexpr int64_t kMaxLdsPerWorkgroup = 160 * 1024;
 constexpr int kMaxNp = 128;
-constexpr int kThreads = 256;  // every contraction work-group: 4 wave64s
 
 // Thread-local last-error text; set_error returns its status so call sites
 // can `return set_error(...)`.
@@ -33,6 +32,7 @@ inline int64_t ceil_div(int64_t x, int64_t m) { return (x + m - 1) / m; }
 struct ContractGeom {
     int prec = 0, layout = 0;
     int tile_e = 16, prefetch = 0, unroll = 1;
+    int threads = 256;  // work-group size: 4 wave64s per 16 elements of the tile
     int kstep = 4;     // reduction length of one MFMA (4 fp32, 32 bf16)
     int nt = 0;        // i-blocks of 16 rows: ceil(Np / 16)
     int ntmax = 2;     // compiled bound on nt: 2, 4 or 8
@@ -48,9 +48,25 @@ struct ContractGeom {
 lpx_status contract_geometry(int K, int Np, int64_t E, int layout,
                              const lpx_record& r, ContractGeom* g);
 
+// Every check of lpx_contract / lpx_gemm that needs no HIP call.
+lpx_status validate_contract(const lpx_contract_desc* c, const lpx_record* rec, ContractGeom* g);
+lpx_status validate_gemm(const lpx_gemm_desc* g, const lpx_record* rec, bool* noop);
+bool overlaps(const void* a, int64_t abytes, const void* b, int64_t bbytes);
+bool mul_overflows(int64_t a, int64_t b, int64_t* r);
+bool aligned16(const void* p);
+
+// Tuning cache (per device): lookup returns LPX_ERR_NOT_TUNED on a miss.
+lpx_status tuned_lookup(const lpx_problem& p, lpx_record* out);
+lpx_status tuned_store(const lpx_problem& p, const lpx_record& r);
+
 // Launches the contraction kernel for a validated problem.
 lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g,
                            void* stream);
+
+// GEMM tiling of a record (defaults filled in); LPX_ERR_UNSUPPORTED if that
+// tiling is not built for the record's precision.
+lpx_status gemm_tiles(const lpx_record& r, int* tm, int* tn, int* tk);
+lpx_status launch_gemm(const lpx_gemm_desc& d, const lpx_record& r, void* stream);
 
 // Elementwise bf16 split kernel launch (n > 0, pointers validated).
 lpx_status launch_split_bf16(const float* x, uint16_t* hi, uint16_t* lo,

@@ -85,6 +85,13 @@ class ContractDesc(ctypes.Structure):
                 ("D", ctypes.c_void_p), ("u", ctypes.c_void_p), ("out", ctypes.c_void_p)]
 
 
+class GemmDesc(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_int64),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64),
+                ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -118,6 +125,18 @@ def lib():
                                    ctypes.POINTER(ctypes.c_int32)]
         L.lpx_tune_cache_insert.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Record)]
         L.lpx_tune_cache_clear.argtypes = []
+        L.lpx_gemm.argtypes = [ctypes.POINTER(GemmDesc), ctypes.POINTER(Record), vp]
+        L.lpx_gemm.restype = st
+        L.lpx_gemm_validate.argtypes = [ctypes.POINTER(GemmDesc), ctypes.POINTER(Record)]
+        L.lpx_gemm_validate.restype = st
+        L.lpx_batch_submit.argtypes = [ctypes.POINTER(ContractDesc), ctypes.POINTER(Record),
+                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), vp]
+        L.lpx_batch_submit.restype = st
+        L.lpx_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
+        L.lpx_batch_info.restype = st
+        L.lpx_batch_destroy.argtypes = [vp]
+        L.lpx_batch_destroy.restype = st
         L.lpx_stream_probe.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, vp]
         L.lpx_stream_probe.restype = st
         for name in ("lpx_autotune", "lpx_tune_cache_insert", "lpx_tune_cache_clear",
@@ -294,10 +313,10 @@ def autotune(D, u, out=None, layout="em", precision="fp32", warmup=2, reps=7, st
         out = torch.empty(out_shape(K, Np, E, layout), dtype=torch.float32, device=u.device)
     desc = make_desc(D, u, out, layout)
     best = Record()
-    times = (ctypes.c_float * 32)()
+    times = (ctypes.c_float * 64)()
     n = ctypes.c_int32()
     _check(lib().lpx_autotune(ctypes.byref(desc), PRECISION[precision], warmup, reps,
-                              _stream_handle(stream), ctypes.byref(best), times, 32,
+                              _stream_handle(stream), ctypes.byref(best), times, 64,
                               ctypes.byref(n)))
     return best, [times[i] for i in range(n.value)]
 
@@ -319,3 +338,77 @@ def stream_probe(x, y, fanout=1, stream=None):
     _check(lib().lpx_stream_probe(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                   n, fanout, _stream_handle(stream)))
     return y
+
+
+# -------------------------------------------------------------------- GEMM
+def gemm(A, B, C=None, record=None, stream=None):
+    """C = A @ B (row-major float32 CUDA tensors) through lpx_gemm."""
+    if A.dim() != 2 or B.dim() != 2 or A.shape[1] != B.shape[0]:
+        raise ValueError("A (M, K) and B (K, N) expected")
+    M, K = A.shape
+    N = B.shape[1]
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    for name, t in (("A", A), ("B", B), ("C", C)):
+        if t.dtype != torch.float32 or t.stride(1) != 1:
+            raise ValueError(f"{name} must be float32 with unit column stride")
+    d = GemmDesc(M, N, K, A.data_ptr() if A.numel() else None, A.stride(0) if M else K,
+                 B.data_ptr() if B.numel() else None, B.stride(0) if K else N,
+                 C.data_ptr() if C.numel() else None, C.stride(0) if M else N)
+    recp = ctypes.byref(record) if record is not None else None
+    _check(lib().lpx_gemm(ctypes.byref(d), recp, _stream_handle(stream)))
+    return C
+
+
+def gemm_validate(desc, rec=None) -> int:
+    recp = ctypes.byref(rec) if rec is not None else None
+    return lib().lpx_gemm_validate(ctypes.byref(desc), recp)
+
+
+# ------------------------------------------------------------ ragged batch
+class Batch:
+    """A ragged batch of contractions replayed as one persistent graph launch.
+
+    items: list of (D, u, out, layout) CUDA tensors; records: list of Record
+    (one precision) or None (tuning cache / default).  submit() replays,
+    optionally with new tensors of the same shapes."""
+
+    def __init__(self, items, records=None, stream=None):
+        self.handle = ctypes.c_void_p(None)
+        self.n = len(items)
+        self._submit(items, records, stream)
+
+    def _descs(self, items):
+        arr = (ContractDesc * len(items))()
+        for i, (D, u, out, layout) in enumerate(items):
+            arr[i] = make_desc(D, u, out, layout)
+        return arr
+
+    def _submit(self, items, records, stream):
+        descs = self._descs(items)
+        recs = None
+        if records is not None:
+            recs = (Record * len(records))(*records)
+        _check(lib().lpx_batch_submit(descs, recs, len(items), ctypes.byref(self.handle),
+                                      _stream_handle(stream)))
+        self._keep = items  # the caller's tensors stay referenced until the next submit
+
+    def submit(self, items=None, stream=None):
+        self._submit(items if items is not None else self._keep, None, stream)
+
+    def info(self):
+        t, g, l = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().lpx_batch_info(self.handle, ctypes.byref(t), ctypes.byref(g), ctypes.byref(l)))
+        return {"tiles": t.value, "grid": g.value, "lds_bytes": l.value}
+
+    def destroy(self):
+        if self.handle:
+            torch.cuda.synchronize()
+            lib().lpx_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -156,3 +156,28 @@ def test_null_descriptor_and_split_args():
     assert L.lpx_split_bf16(None, None, None, 0, None) == lpx.OK
     assert L.lpx_split_bf16(None, None, None, -1, None) == lpx.ERR_INVALID_ARG
     assert L.lpx_split_bf16(None, None, None, 10, None) == lpx.ERR_INVALID_ARG
+
+
+def gdesc(M=256, N=256, K=256, A=A, lda=None, B=A + (1 << 24), ldb=None, C=A + (1 << 28), ldc=None):
+    return lpx.GemmDesc(M, N, K, A, K if lda is None else lda, B, N if ldb is None else ldb,
+                        C, N if ldc is None else ldc)
+
+
+def test_gemm_validate():
+    assert lpx.gemm_validate(gdesc()) == lpx.OK
+    for prec in ("fp32", "bf16", "bf16x3"):
+        for tiles in ((64, 64, 32), (128, 128, 64), (128, 64, 32)):
+            assert lpx.gemm_validate(gdesc(), lpx.record(prec, gemm=tiles)) == lpx.OK
+    assert lpx.gemm_validate(gdesc(), lpx.record("fp32", gemm=(256, 256, 32))) == lpx.OK
+    assert lpx.gemm_validate(gdesc(), lpx.record("bf16x3", gemm=(256, 256, 32))) == lpx.ERR_UNSUPPORTED
+    assert lpx.gemm_validate(gdesc(), lpx.record("fp32", gemm=(96, 64, 32))) == lpx.ERR_UNSUPPORTED
+    assert lpx.gemm_validate(gdesc(M=-1)) == lpx.ERR_INVALID_ARG
+    assert lpx.gemm_validate(gdesc(lda=100)) == lpx.ERR_INVALID_ARG   # below K
+    assert lpx.gemm_validate(gdesc(lda=258)) == lpx.OK                # any lda >= K
+    assert lpx.gemm_validate(gdesc(A=A + 4)) == lpx.ERR_INVALID_ARG   # misaligned
+    assert lpx.gemm_validate(gdesc(C=A + 1024)) == lpx.ERR_ALIAS      # C overlaps A
+    assert lpx.gemm_validate(gdesc(C=None)) == lpx.ERR_INVALID_ARG
+    d = gdesc(M=0, A=None, B=None, C=None)
+    assert lpx.gemm_validate(d) == lpx.OK
+    assert lpx.lib().lpx_gemm(ctypes.byref(d), None, None) == lpx.OK   # no-op, no HIP call
+    assert lpx.lib().lpx_gemm(None, None, None) == lpx.ERR_INVALID_ARG

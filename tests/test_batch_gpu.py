@@ -1,0 +1,97 @@
+"""Ragged batch in one persistent graph launch: bit-identical to separate
+lpx_contract calls, within tolerance of the oracle, replayable with new
+buffers; plus sampled instances of the 512-instance workload."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1405_7470_amd import inputs, lpx
+from tests.gpu_util import as_em, check_against_oracle, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def make_items(shapes, seed, layout="em", K=3):
+    host = inputs.ragged_batch_inputs(shapes, K=K, seed=seed)
+    items = []
+    for D, u in host:
+        uu = u if layout == "em" else np.ascontiguousarray(u.T)
+        Dd, ud = to_dev(D), to_dev(uu)
+        out = torch.empty(lpx.out_shape(K, D.shape[1], u.shape[0], layout), device="cuda")
+        items.append((Dd, ud, out, layout))
+    return host, items
+
+
+@pytest.mark.parametrize("precision", ("fp32", "bf16x3", "bf16"))
+@pytest.mark.parametrize("layout", ("em", "dm"))
+def test_batch_bitwise_equals_separate_calls(precision, layout):
+    shapes = inputs.ragged_shapes(n=40, seed=7, lo=1, hi=3000)
+    host, items = make_items(shapes, seed=3, layout=layout)
+    rng = np.random.default_rng(1)
+    recs = [lpx.record(precision, int(rng.choice([16, 32, 64])), int(rng.integers(0, 4)),
+                       int(rng.choice([1, 2, 4]))) for _ in shapes]
+    print(f"case: batch {precision} {layout} n={len(shapes)}", flush=True)
+    b = lpx.Batch(items, recs)
+    torch.cuda.synchronize()
+    for (D, u, out, lay), rec, (Dh, uh) in zip(items, recs, host):
+        ref = lpx.contract(D, u, layout=lay, record=rec)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), lpx.describe(rec)
+        uu = uh if lay == "em" else np.ascontiguousarray(uh.T)
+        check_against_oracle(Dh, uu, as_em(out, lay), lay, precision)
+    b.destroy()
+
+
+def test_batch_replay_with_new_buffers_and_sentinel():
+    shapes = inputs.ragged_shapes(n=25, seed=11, lo=10, hi=2000)
+    host, items = make_items(shapes, seed=5)
+    b = lpx.Batch(items, None)
+    torch.cuda.synchronize()
+    info = b.info()
+    assert info["tiles"] == sum((E + 15) // 16 for _, E in shapes)
+    # new inputs and NaN-filled outputs, same shapes: replay the graph
+    host2, items2 = make_items(shapes, seed=6)
+    for (_, _, out, _) in items2:
+        out.fill_(float("nan"))
+    for _ in range(3):  # several replays, with eager work in between
+        b.submit(items2)
+        torch.cuda.synchronize()
+        _ = torch.ones(10, device="cuda").sum().item()
+        for (D, u, out, lay), (Dh, uh) in zip(items2, host2):
+            assert not torch.isnan(out).any()
+            check_against_oracle(Dh, uh, as_em(out, lay), lay, "fp32")
+    b.destroy()
+
+
+def test_batch_rejects_mixed_precision_and_changed_shapes():
+    shapes = [(20, 100), (56, 50)]
+    _, items = make_items(shapes, seed=1)
+    with pytest.raises(lpx.LpxError) as ei:
+        lpx.Batch(items, [lpx.record("fp32"), lpx.record("bf16")])
+    assert ei.value.status == lpx.ERR_UNSUPPORTED
+    b = lpx.Batch(items, None)
+    _, items_bad = make_items([(20, 100), (56, 51)], seed=1)
+    with pytest.raises(lpx.LpxError) as ei:
+        b.submit(items_bad)
+    assert ei.value.status == lpx.ERR_INVALID_ARG
+    b.destroy()
+
+
+def test_batch_512_instances_sampled():
+    """The 512-instance workload (Np over {10,...,120}, E log-uniform in
+    [1024, 65536], seed 0): a sample of instances checked bit-for-bit
+    against lpx_contract and against the oracle."""
+    shapes = inputs.ragged_shapes(n=512, seed=0)
+    host, items = make_items(shapes, seed=0)
+    b = lpx.Batch(items, None)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    for i in sorted(set(int(x) for x in rng.integers(0, 512, 12)) | {0, 511}):
+        D, u, out, lay = items[i]
+        ref = lpx.contract(D, u, layout=lay)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), i
+        Dh, uh = host[i]
+        n = min(64, uh.shape[0])
+        check_against_oracle(Dh, uh, as_em(out[:, :n, :], "em"), "em", "fp32", e0=0)
+    b.destroy()

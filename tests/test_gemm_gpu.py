@@ -1,0 +1,83 @@
+"""GEMM (the contraction's degenerate case) through lpx_gemm vs the FP64
+oracle: every built tiling and precision on ragged shapes, exact integer
+inputs, identity, and sampled rows at 4096^3 and 8192 x 1024 x 4096."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1405_7470_amd import inputs, lpx
+from tests.gpu_util import EMU_TOL, TOL, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TILES = {"fp32": [(64, 64, 32), (64, 64, 64), (128, 128, 32), (128, 128, 64), (128, 64, 32),
+                  (64, 128, 32), (256, 128, 32), (128, 256, 32), (256, 256, 32)],
+         "bf16": [(64, 64, 32), (128, 128, 32), (128, 128, 64), (256, 256, 32)],
+         "bf16x3": [(64, 64, 32), (64, 64, 64), (128, 128, 32), (128, 128, 64), (64, 128, 32)]}
+
+
+def check(C, A, B, precision, m0=0):
+    nm = C.shape[0]
+    ref = oracle.gemm(A, B, "fp32", m0, nm)
+    err = oracle.rel_err(C, ref)
+    assert err <= TOL[precision], (precision, err)
+    if precision != "fp32":
+        emu = oracle.gemm(A, B, precision, m0, nm)
+        assert oracle.rel_err(C, emu) <= EMU_TOL
+    return err
+
+
+@pytest.mark.parametrize("precision", ("fp32", "bf16", "bf16x3"))
+def test_gemm_tilings_ragged(precision):
+    for (M, N, K) in ((128, 128, 128), (100, 77, 61), (257, 130, 95), (33, 300, 1)):
+        A, B = inputs.gemm_inputs(M, N, K, seed=M + N + K)
+        Ad, Bd = to_dev(A), to_dev(B)
+        for tiles in TILES[precision]:
+            rec = lpx.record(precision, gemm=tiles)
+            print(f"case: gemm {M}x{N}x{K} {lpx.describe(rec)}", flush=True)
+            C = lpx.gemm(Ad, Bd, record=rec)
+            torch.cuda.synchronize()
+            check(C.double().cpu().numpy(), A, B, precision)
+
+
+def test_gemm_integer_exact_and_identity():
+    A, B = inputs.integer_gemm_inputs(150, 90, 70, seed=2)
+    exact = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float64)
+    Ad, Bd = to_dev(A), to_dev(B)
+    for precision, tl in TILES.items():
+        for tiles in tl[:3]:
+            C = lpx.gemm(Ad, Bd, record=lpx.record(precision, gemm=tiles))
+            torch.cuda.synchronize()
+            assert np.array_equal(C.double().cpu().numpy(), exact), (precision, tiles)
+    I = torch.eye(70, device="cuda")
+    C = lpx.gemm(I, Bd, record=None)
+    torch.cuda.synchronize()
+    assert torch.equal(C, Bd)
+
+
+def test_gemm_strided_rows():
+    A, B = inputs.gemm_inputs(70, 50, 40, seed=3)
+    Ab = torch.zeros((70, 44), device="cuda")
+    Ab[:, :40] = to_dev(A)
+    Cb = torch.full((70, 53), 7.0, device="cuda")
+    lpx.gemm(Ab[:, :40], to_dev(B), C=Cb[:, :50], record=lpx.record("fp32", gemm=(64, 64, 32)))
+    torch.cuda.synchronize()
+    check(Cb[:, :50].double().cpu().numpy(), A, B, "fp32")
+    assert bool((Cb[:, 50:] == 7.0).all())
+
+
+@pytest.mark.parametrize("shape", [(4096, 4096, 4096), (8192, 1024, 4096)])
+def test_gemm_full_size_sampled_rows(shape):
+    M, N, K = shape
+    A, B = inputs.gemm_inputs(M, N, K, seed=0)
+    Ad, Bd = to_dev(A), to_dev(B)
+    rows = [0, 1, M // 2 + 17, M - 1]
+    for precision in ("fp32", "bf16", "bf16x3"):
+        rec = lpx.record(precision, gemm=(128, 128, 32))
+        print(f"case: gemm full {shape} {precision}", flush=True)
+        C = lpx.gemm(Ad, Bd, record=rec)
+        torch.cuda.synchronize()
+        for m in rows:
+            check(C[m:m + 1].double().cpu().numpy(), A, B, precision, m0=m)
+        del C
