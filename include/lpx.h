@@ -273,6 +273,9 @@ lpx_status lpx_batch_destroy(lpx_batch* b);
  * (lpx_record_enumerate order) on the caller's buffers -- `warmup` untimed
  * launches, then `reps` launches each bracketed by HIP events on `stream`,
  * median kept -- and returns the fastest in *best (ties: lowest index).
+ * If flush (device, flush_bytes, a multiple of 16) is not NULL it is
+ * overwritten before every timed launch, outside the events, so that the
+ * caches do not hold the problem's data (needed for small problems).
  * Blocks the calling thread until the timing launches finish.  Overwrites
  * c->out.  Candidates that lpx_contract_validate rejects (e.g. LDS budget)
  * are skipped and reported as +infinity.  Writes min(cap, count) median
@@ -281,8 +284,8 @@ lpx_status lpx_batch_destroy(lpx_batch* b);
  * cache, keyed by (device, K, Np, E, layout, precision), where
  * LPX_PICK_EXHAUSTIVE finds it. */
 lpx_status lpx_autotune(const lpx_contract_desc* c, int32_t precision, int32_t warmup,
-                        int32_t reps, void* stream, lpx_record* best, float* times_us,
-                        int32_t cap, int32_t* n);
+                        int32_t reps, void* flush, int64_t flush_bytes, void* stream,
+                        lpx_record* best, float* times_us, int32_t cap, int32_t* n);
 
 /* Seeds the tuning cache for the current device (e.g. from a stored timing
  * database); the record's precision must equal p->precision. */
@@ -290,6 +293,82 @@ lpx_status lpx_tune_cache_insert(const lpx_problem* p, const lpx_record* rec);
 
 /* Empties the tuning cache. */
 lpx_status lpx_tune_cache_clear(void);
+
+/* --------------------------------------------------- learned picker */
+/* Cost model: a perceptron 12 -> 64 -> 64 -> 1 with ReLU hidden units that
+ * predicts the log run time of one (problem, record) pair.  Parameters are
+ * one flat FP32 vector: W1[64][12], b1[64], W2[64][64], b2[64], w3[64], b3.
+ * Every kernel below sums in a fixed order (deterministic results). */
+#define LPX_MLP_FEATURES 12
+#define LPX_MLP_HIDDEN 64
+#define LPX_MLP_PARAMS 5057
+
+/* The 12 features of (problem, record), into the host array out[12]:
+ * log2 Np, log2 E, K, layout, log2 tile_e, D-prefetch bit, u-prefetch bit,
+ * log2 unroll, precision code, MFMA row padding (16*ceil(Np/16) - Np) /
+ * (16*ceil(Np/16)), log2 of the element-tile count, dynamic LDS bytes per
+ * work-group / 160 KiB.  Needs 0 < K, 0 < Np <= 128, 0 < E. */
+lpx_status lpx_features(const lpx_problem* p, const lpx_record* r, float* out);
+
+/* Forward pass of n rows.  params: device, LPX_MLP_PARAMS floats; X: device
+ * n x 12; act: device n x 128 (per row z1[64] then z2[64], kept for the
+ * backward pass) or NULL; y: device n predictions. */
+lpx_status lpx_mlp_forward(const float* params, const float* X, int32_t n, float* act,
+                           float* y, void* stream);
+
+/* Mean squared error L = mean((y - t)^2) into loss[0] (device, may be NULL)
+ * and its gradient dy = 2 (y - t) / n (device n floats, may be NULL);
+ * n > 0. */
+lpx_status lpx_mlp_loss(const float* y, const float* t, int32_t n, float* dy, float* loss,
+                        void* stream);
+
+/* Backward pass: grads (device, LPX_MLP_PARAMS) = gradient of
+ * sum_b dy[b] * y[b] with respect to the parameters (ReLU'(0) = 0), from the
+ * forward pass's X and act; work: device n x 128 scratch. */
+lpx_status lpx_mlp_backward(const float* params, const float* X, const float* act,
+                            const float* dy, int32_t n, float* work, float* grads, void* stream);
+
+/* One Adam update of n parameters in place (device m, v moments), with
+ * bias correction for `step` (>= 1): p -= lr * mhat / (sqrt(vhat) + eps). */
+lpx_status lpx_adam_step(float* params, const float* grads, float* m, float* v, int32_t n,
+                         int32_t step, float lr, float beta1, float beta2, float eps,
+                         void* stream);
+
+/* Pick kernel: standardises ncand (1..256) candidate feature rows (device
+ * ncand x 12) with mean/std (device, 12 each; std 0 counts as 1), predicts
+ * each (pred: device ncand floats or NULL) and writes the argmin index to
+ * best (device int; ties: lowest index). */
+lpx_status lpx_mlp_pick(const float* params, const float* feats, int32_t ncand,
+                        const float* mean, const float* stdv, float* pred, int32_t* best,
+                        void* stream);
+
+/* A trained picker: weights plus feature standardisation, loaded from a
+ * model file (magic "LPXPICK1", version, dimensions, mean[12], std[12],
+ * params[5057], FNV-1a checksum; little-endian).  Opaque. */
+typedef struct lpx_picker lpx_picker;
+
+/* Writes a model file from host arrays. */
+lpx_status lpx_picker_save(const char* path, const float* params, const float* mean,
+                           const float* stdv);
+/* Loads a model file; LPX_ERR_MODEL if it is missing, truncated, of another
+ * version or dimensions, fails its checksum, or holds non-finite values. */
+lpx_status lpx_picker_load(const char* path, lpx_picker** out);
+/* Copies a loaded picker's weights/standardisation to host arrays (any may
+ * be NULL). */
+lpx_status lpx_picker_params(const lpx_picker* m, float* params, float* mean, float* stdv);
+lpx_status lpx_picker_free(lpx_picker* m);
+
+#define LPX_PICK_UNTUNED 0    /* the default record                     */
+#define LPX_PICK_EXHAUSTIVE 1 /* the tuning cache (LPX_ERR_NOT_TUNED)   */
+#define LPX_PICK_LEARNED 2    /* the cost model's argmin                */
+
+/* Chooses a record of p->precision for the problem.  LEARNED enumerates the
+ * candidates that fit (lpx_record_enumerate minus LDS misfits), computes
+ * their features on the host, runs lpx_mlp_pick on `stream` and waits for
+ * the index (a blocking round trip; the answer is cached per problem in the
+ * picker).  model is needed only for LEARNED (LPX_ERR_MODEL if NULL). */
+lpx_status lpx_pick_variant(const lpx_problem* p, int32_t mode, lpx_picker* model,
+                            void* stream, lpx_record* out);
 
 /* ------------------------------------------------------ measurement */
 /* Streaming probe, the analogue of Table 1's "saxpy" row: y[r*n + t] =

@@ -66,34 +66,29 @@ lpx_status contract_geometry(int K, int Np, int64_t E, int layout,
     g->tile_e = r.tile_e;
     g->prefetch = r.prefetch;
     g->unroll = r.unroll;
-    g->threads = 64 * 4 * (r.tile_e / 16);
     g->kstep = (r.precision == LPX_FP32) ? 4 : 32;
     g->nt = (int)ceil_div(Np, 16);
     g->ntmax = g->nt <= 2 ? 2 : (g->nt <= 4 ? 4 : 8);
+    g->threads = contract_shape(r.tile_e, g->ntmax, r.prefetch).threads;
     g->nsteps = (int)ceil_div(Np, g->kstep);
     g->ntiles = ceil_div(E, r.tile_e);
     g->nfrag = (int64_t)K * g->nt * g->nsteps * 64;
-    if (r.precision == LPX_FP32) {
-        // row stride = 2 (mod 4) floats: the 16 rows x 4 k-slots an MFMA
-        // operand read touches fall in distinct LDS banks.
-        g->ldu = (int)round_up(Np, 4) + 2;
-    } else {
-        // row stride = 16 (mod 64) bytes: 16-byte operand reads of
-        // consecutive rows start in distinct bank groups.
-        g->ldu = (int)round_up(Np, 32) + 8;
-    }
+    // A staged u tile is a raw copy of the tile (tile_e * Np floats) plus
+    // slack for reads of padding columns up to the next multiple of 32.
+    g->ldu = r.tile_e * (int)round_up(Np, 32) + 32;  // ring slot stride in floats
     g->lds_bytes = 0;
     if (r.prefetch) {
-        int64_t frag_bytes = r.precision == LPX_FP32 ? 4 : (r.precision == LPX_BF16 ? 16 : 32);
-        int64_t u_bytes = (int64_t)r.tile_e * g->ldu *
-                          (r.precision == LPX_FP32 ? 4 : (r.precision == LPX_BF16 ? 2 : 4));
+        const int64_t frag_bytes =
+            r.precision == LPX_FP32 ? 4 : (r.precision == LPX_BF16 ? 16 : 32);
+        const int64_t ring_bytes = 2 * (int64_t)g->ldu * 4;
         g->lds_bytes = ((r.prefetch & 1) ? g->nfrag * frag_bytes : 0) +
-                       ((r.prefetch & 2) ? u_bytes : 0);
+                       ((r.prefetch & 2) ? ring_bytes : 0);
         if (g->lds_bytes > kMaxLdsPerWorkgroup)
             return set_error(LPX_ERR_UNSUPPORTED,
-                             "prefetch=1 needs %lld bytes of LDS per work-group for K=%d "
-                             "Np=%d (limit %lld); use prefetch=0",
-                             (long long)g->lds_bytes, K, Np, (long long)kMaxLdsPerWorkgroup);
+                             "prefetch=%u needs %lld bytes of LDS per work-group for K=%d "
+                             "Np=%d (limit %lld)",
+                             r.prefetch, (long long)g->lds_bytes, K, Np,
+                             (long long)kMaxLdsPerWorkgroup);
     }
     return LPX_OK;
 }

@@ -81,10 +81,10 @@ __global__ __launch_bounds__(kThreadsB) void batch_kernel(BatchArgs b) {
             }
             const int64_t eb0 = (t - b.items[lo].tile_begin) * 16;
             if (dl)
-                kern::block_compute<PREC, LAYOUT, NTMAX, true, false, 16, 2>(a, lds, nullptr, 0,
+                kern::block_compute<PREC, LAYOUT, NTMAX, true, false, 16, 4, 2>(a, lds, nullptr, 0,
                                                                              eb0, wave, lane);
             else
-                kern::block_compute<PREC, LAYOUT, NTMAX, false, false, 16, 2>(a, lds, nullptr, 0,
+                kern::block_compute<PREC, LAYOUT, NTMAX, false, false, 16, 4, 2>(a, lds, nullptr, 0,
                                                                               eb0, wave, lane);
         }
     }
@@ -154,8 +154,10 @@ lpx_status fill_table(lpx_batch* b, const lpx_contract_desc* items, const lpx_re
         const int32_t i = b->order[slot];
         const lpx_contract_desc& c = items[i];
         lpx_record r = recs ? recs[i] : default_record(b->precision);
+        lpx_record r0 = r;
+        r0.prefetch = 0;  // geometry without LDS staging; the D bit is decided below
         ContractGeom g;
-        lpx_status s = contract_geometry(c.K, c.Np, c.E, c.layout, r, &g);
+        lpx_status s = contract_geometry(c.K, c.Np, c.E, c.layout, r0, &g);
         if (s != LPX_OK) return s;
         Item& it = b->host_items[slot];
         std::memset(&it, 0, sizeof it);
@@ -189,7 +191,11 @@ lpx_status check_items(const lpx_contract_desc* items, const lpx_record* recs, i
     *layout = items[0].layout;
     *ntmax = 2;
     for (int32_t i = 0; i < n; ++i) {
-        const lpx_record* r = recs ? &recs[i] : nullptr;
+        // The batch stages D only when it fits its own budget, so the
+        // record is checked with LDS staging off.
+        lpx_record rr = recs ? recs[i] : default_record(LPX_FP32);
+        rr.prefetch = 0;
+        const lpx_record* r = &rr;
         ContractGeom g;
         lpx_status s = validate_contract(&items[i], r, &g);
         if (s != LPX_OK) {

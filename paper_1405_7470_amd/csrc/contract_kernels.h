@@ -195,8 +195,7 @@ __device__ __forceinline__ Frag<PREC> u_frag_global(const ContractArgs& a, int64
 // ------------------------------------------------------------ LDS layout
 // [D fragments, operand order: ((k*nt + t)*nsteps + s)*64 + lane]
 //   fp32: float; bf16: 16-byte hi plane; bf16x3: hi plane then lo plane
-// [u tile, TILE_E rows of ldu elements]
-//   fp32: float; bf16: bf16 hi; bf16x3: hi rows then lo rows
+// [u ring: two slots of ldu floats, raw FP32 copies of u tiles]
 template <int PREC>
 struct Lds {
     static constexpr int DFRAG_BYTES = PREC == LPX_FP32 ? 4 : 16;  // per plane
@@ -231,84 +230,123 @@ __device__ __forceinline__ void d_frag_store_lds(unsigned char* lds, int64_t nfr
     }
 }
 
-// Writes one u value (element row r of the tile, column j) in the staged
-// precision.
-template <int PREC, int TILE_E>
-__device__ __forceinline__ void u_put_lds(unsigned char* ut, int ldu, int r, int j, float v) {
-    if constexpr (PREC == LPX_FP32) {
-        reinterpret_cast<float*>(ut)[r * ldu + j] = v;
-    } else {
-        __bf16* p = reinterpret_cast<__bf16*>(ut);
-        __bf16 h = (__bf16)v;
-        p[r * ldu + j] = h;
-        if constexpr (PREC == LPX_BF16X3) p[TILE_E * ldu + r * ldu + j] = (__bf16)(v - (float)h);
-    }
-}
-
-template <int PREC, int TILE_E>
-__device__ __forceinline__ Frag<PREC> u_frag_lds(const unsigned char* ut, int ldu, int row0,
+// ---------------------------------------------------- staged u tiles
+// A staged u tile is a raw copy of the tile's bytes in global memory, in a
+// two-slot LDS ring:
+//   element-major: the contiguous run u[e0 .. e0+nvalid)[0 .. Np), so
+//                  element r, column j sits at r*Np + j;
+//   DOF-major:     the Np row segments u[j][e0 .. e0+TILE_E), so column j,
+//                  element r sits at j*TILE_E + r.
+// A slot has slack past the tile so that reads of padding columns
+// (j >= Np, up to the next multiple of 32) stay inside it; those values are
+// replaced by zero with a select, never multiplied.  Compute waves convert
+// what they read to the operand precision.
+template <int PREC, int LAYOUT, int TILE_E>
+__device__ __forceinline__ Frag<PREC> u_frag_lds(const float* ut, int Np, bool np_vec, int row0,
                                                  int s, int lane) {
     const int r = row0 + (lane & 15);
     const int j0 = s * Traits<PREC>::KSTEP + (lane >> 4) * Traits<PREC>::KPL;
     if constexpr (PREC == LPX_FP32) {
-        return {reinterpret_cast<const float*>(ut)[r * ldu + j0]};
-    } else if constexpr (PREC == LPX_BF16) {
-        return {*reinterpret_cast<const bf16x8*>(reinterpret_cast<const __bf16*>(ut) +
-                                                 r * ldu + j0)};
+        const float x = LAYOUT == LPX_ELEMENT_MAJOR ? ut[r * Np + j0] : ut[j0 * TILE_E + r];
+        return {j0 < Np ? x : 0.0f};
     } else {
-        const __bf16* p = reinterpret_cast<const __bf16*>(ut);
-        return {*reinterpret_cast<const bf16x8*>(p + r * ldu + j0),
-                *reinterpret_cast<const bf16x8*>(p + TILE_E * ldu + r * ldu + j0)};
+        float v[8];
+        if (LAYOUT == LPX_ELEMENT_MAJOR && np_vec) {  // 16-byte aligned rows
+            const f4 a = *reinterpret_cast<const f4*>(ut + r * Np + j0);
+            const f4 b = *reinterpret_cast<const f4*>(ut + r * Np + j0 + 4);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                v[t] = a[t];
+                v[t + 4] = b[t];
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                v[t] = LAYOUT == LPX_ELEMENT_MAJOR ? ut[r * Np + j0 + t] : ut[(j0 + t) * TILE_E + r];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = j0 + t < Np ? v[t] : 0.0f;
+        return make_frag8<PREC>(v);
     }
 }
 
-// Stage the u tile [e0, e0 + nvalid) into LDS rows 0..nvalid-1, columns
-// 0..Np-1 (the zero columns Np..ldu-1 are written once at kernel start).
-template <int PREC, int LAYOUT, int TILE_E, int NTHREADS>
-__device__ __forceinline__ void stage_u_tile(const ContractArgs& a, unsigned char* ut,
-                                             int64_t e0, int nvalid, int tid) {
-    const int Np = a.Np;
+// Loader waves.  A tile is cut into 16-byte chunks; chunk c goes to slot
+// offset 16c bytes.  Loader wave lw (of NLW) holds chunks
+// c = lane + 64 * (lw + NLW * q), q < PER_LANE, in registers from one
+// iteration to the next, so its global loads are in flight while the
+// compute waves work on the previous tile.  Loader waves issue no global
+// stores, so their waits cover their own loads only.
+//   element-major: chunk c = floats 4c..4c+3 of the run of nvalid*Np floats;
+//   DOF-major:     chunk c = row j = c / (TILE_E/4), columns
+//                  4*(c % (TILE_E/4)) .. +3.
+template <int TILE_E, int NTMAX, int NLW>
+struct Loader {
+    static constexpr int CHUNKS = TILE_E * 16 * NTMAX / 4;  // upper bound per tile
+    static constexpr int PER_LANE = (CHUNKS + 64 * NLW - 1) / (64 * NLW);
+};
+
+// Number of chunks of a tile with nvalid elements.
+template <int LAYOUT, int TILE_E>
+__device__ __forceinline__ int tile_chunks(const ContractArgs& a, int nvalid) {
+    return LAYOUT == LPX_ELEMENT_MAJOR ? (nvalid * a.Np + 3) / 4 : a.Np * (TILE_E / 4);
+}
+
+template <int LAYOUT, int TILE_E, int NTMAX, int NLW>
+__device__ __forceinline__ void loader_fetch(const ContractArgs& a, int64_t e0, int nvalid, int lw,
+                                             int lane, f4 (&v)[Loader<TILE_E, NTMAX, NLW>::PER_LANE]) {
+    constexpr int PL = Loader<TILE_E, NTMAX, NLW>::PER_LANE;
+    const int nch = tile_chunks<LAYOUT, TILE_E>(a, nvalid);
     if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
-        // The tile is one contiguous run of nvalid*Np floats.
-        const float* src = a.u + e0 * Np;
-        const int nflat = nvalid * Np;
-        const float inv = 1.0f / (float)Np;
-        if (a.np_vec) {
-            // 16-byte chunks never straddle a row when Np % 4 == 0.
-            for (int c = tid; c < nflat / 4; c += NTHREADS) {
-                f4 v = reinterpret_cast<const f4*>(src)[c];
-                const int f = 4 * c;
-                const int r = (int)(((float)f + 0.5f) * inv);  // exact: f < 2^13
-                const int j = f - r * Np;
+        const float* src = a.u + e0 * a.Np;  // 16-byte aligned: e0 % 16 == 0
+        const int nflat = nvalid * a.Np;
+        const bool full = nflat % 4 == 0;    // no chunk straddles the end
 #pragma unroll
-                for (int q = 0; q < 4; ++q) u_put_lds<PREC, TILE_E>(ut, a.ldu, r, j + q, v[q]);
-            }
-        } else {
-            for (int f = tid; f < nflat; f += NTHREADS) {
-                const int r = (int)(((float)f + 0.5f) * inv);
-                u_put_lds<PREC, TILE_E>(ut, a.ldu, r, f - r * Np, src[f]);
-            }
-        }
-    } else {
-        // Np rows of nvalid contiguous floats, row stride E.
-        if (a.e_vec) {
-            constexpr int CPR = TILE_E / 4;  // 16-byte chunks per row
-            for (int c = tid; c < Np * CPR; c += NTHREADS) {
-                const int j = c / CPR;
-                const int r = 4 * (c % CPR);
-                if (r < nvalid) {  // E % 4 == 0 and e0 % 4 == 0: all 4 valid
-                    f4 v = *reinterpret_cast<const f4*>(a.u + (int64_t)j * a.E + e0 + r);
+        for (int q = 0; q < PL; ++q) {
+            const int c = lane + 64 * (lw + NLW * q);
+            f4 x = {0.f, 0.f, 0.f, 0.f};
+            if (c < nch) {
+                if (full || 4 * c + 4 <= nflat) {
+                    x = *reinterpret_cast<const f4*>(src + 4 * c);
+                } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) u_put_lds<PREC, TILE_E>(ut, a.ldu, r + q, j, v[q]);
+                    for (int t = 0; t < 4; ++t)
+                        if (4 * c + t < nflat) x[t] = src[4 * c + t];
                 }
             }
-        } else {
-            for (int f = tid; f < Np * TILE_E; f += NTHREADS) {
-                const int j = f / TILE_E;
-                const int r = f % TILE_E;
-                if (r < nvalid) u_put_lds<PREC, TILE_E>(ut, a.ldu, r, j, a.u[(int64_t)j * a.E + e0 + r]);
-            }
+            v[q] = x;
         }
+    } else {
+        constexpr int CPR = TILE_E / 4;
+#pragma unroll
+        for (int q = 0; q < PL; ++q) {
+            const int c = lane + 64 * (lw + NLW * q);
+            f4 x = {0.f, 0.f, 0.f, 0.f};
+            const int j = c / CPR, col = 4 * (c % CPR);
+            if (c < nch && col < nvalid) {
+                const float* src = a.u + (int64_t)j * a.E + e0 + col;
+                if (a.e_vec) {  // E % 4 == 0: nvalid % 4 == 0 and the segment is aligned
+                    x = *reinterpret_cast<const f4*>(src);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if (col + t < nvalid) x[t] = src[t];
+                }
+            }
+            v[q] = x;
+        }
+    }
+}
+
+template <int LAYOUT, int TILE_E, int NTMAX, int NLW>
+__device__ __forceinline__ void loader_put(const ContractArgs& a, float* ut, int nvalid, int lw,
+                                           int lane,
+                                           const f4 (&v)[Loader<TILE_E, NTMAX, NLW>::PER_LANE]) {
+    constexpr int PL = Loader<TILE_E, NTMAX, NLW>::PER_LANE;
+    const int nch = tile_chunks<LAYOUT, TILE_E>(a, nvalid);
+#pragma unroll
+    for (int q = 0; q < PL; ++q) {
+        const int c = lane + 64 * (lw + NLW * q);
+        if (c < nch) reinterpret_cast<f4*>(ut)[c] = v[q];
     }
 }
 
@@ -330,16 +368,15 @@ __device__ __forceinline__ void stage_d(const ContractArgs& a, unsigned char* ld
 }
 
 // One wave's share of a 16-element block starting at element eb0: the
-// (k, i-block) pairs p = part, part + 4, ... ; for each, the MFMA chain over
+// (k, i-block) pairs p = part, part + WPE, ... (WPE waves share a block); for each, the MFMA chain over
 // the k-steps of j, then the write-back.  D fragments come from LDS (PF_D)
 // or global memory; u fragments from the staged tile `ut` at row `row0`
 // (PF_U) or global memory.  The summation order of every output depends
 // only on PREC: all records of a precision give bit-identical results.
-template <int PREC, int LAYOUT, int NTMAX, bool PF_D, bool PF_U, int TILE_E, int UNROLL>
+template <int PREC, int LAYOUT, int NTMAX, bool PF_D, bool PF_U, int TILE_E, int WPE, int UNROLL>
 __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsigned char* lds,
-                                              const unsigned char* ut, int row0, int64_t eb0,
-                                              int part, int lane) {
-    constexpr int WPE = 4;                             // waves per 16-element block
+                                              const float* ut, int row0, int64_t eb0, int part,
+                                              int lane) {
     constexpr int PMAX = (3 * NTMAX + WPE - 1) / WPE;  // pairs held per wave
     const int npairs = a.K * a.nt;
     const int64_t nfrag = (int64_t)npairs * a.nsteps * 64;
@@ -356,7 +393,7 @@ __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsig
         auto step = [&](int s) {
             Frag<PREC> uf;
             if constexpr (PF_U)
-                uf = u_frag_lds<PREC, TILE_E>(ut, a.ldu, row0, s, lane);
+                uf = u_frag_lds<PREC, LAYOUT, TILE_E>(ut, a.Np, a.np_vec, row0, s, lane);
             else
                 uf = u_frag_global<PREC, LAYOUT>(a, eb0, s, lane);
 #pragma unroll
@@ -419,47 +456,91 @@ __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsig
 }
 
 // ------------------------------------------------------------ the kernel
-// Work-group size of a TILE_E-element tile: four waves per 16-element
-// block, which split that block's (k, i-block) pairs between them.
-template <int TILE_E>
-constexpr int contract_threads() { return 64 * 4 * (TILE_E / 16); }
+// Work-group shape.  Without a staged u tile: four waves per 16-element
+// block, splitting its (k, i-block) pairs.  With one: min(4 * TILE_E/16, 8)
+// compute waves (so WPE = that / (TILE_E/16) per block) plus NLW loader
+// waves that keep the next tile in registers.
+template <int TILE_E, int NTMAX, int PREFETCH>
+struct Shape {
+    static constexpr bool PF_U = (PREFETCH & 2) != 0;
+    static constexpr ContractShape CS = contract_shape(TILE_E, NTMAX, PREFETCH);
+    static constexpr int NCW = CS.ncw, WPE = CS.wpe, NLW = CS.nlw, THREADS = CS.threads;
+};
 
 template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PREFETCH, int UNROLL>
-__global__ __launch_bounds__(contract_threads<TILE_E>()) void contract_kernel(ContractArgs a) {
+__global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void contract_kernel(
+    ContractArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
-    constexpr int NTHREADS = contract_threads<TILE_E>();
+    using S = Shape<TILE_E, NTMAX, PREFETCH>;
     constexpr bool PF_D = (PREFETCH & 1) != 0;
-    constexpr bool PF_U = (PREFETCH & 2) != 0;
+    constexpr bool PF_U = S::PF_U;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int eblk = wave / 4;  // which 16-element block of the tile
-    const int part = wave % 4;  // which share of that block's pairs
     const int64_t nfrag = (int64_t)a.K * a.nt * a.nsteps * 64;
-    unsigned char* ut = lds + (PF_D ? nfrag * Lds<PREC>::DFRAG_BYTES * Lds<PREC>::PLANES : 0);
+    float* ring = reinterpret_cast<float*>(
+        lds + (PF_D ? nfrag * Lds<PREC>::DFRAG_BYTES * Lds<PREC>::PLANES : 0));
+    const int slot_floats = a.ldu;  // ring slot stride (floats)
 
-    if constexpr (PF_D) stage_d<PREC, NTHREADS>(a, lds, tid);
-    if constexpr (PF_U) {
-        // Zero the padding columns [Np, ldu) of every tile row once; tile
-        // staging never writes them.
-        const int padw = a.ldu - a.Np;
-        for (int f = tid; f < TILE_E * padw; f += NTHREADS)
-            u_put_lds<PREC, TILE_E>(ut, a.ldu, f / padw, a.Np + f % padw, 0.0f);
-    }
-    if constexpr (PREFETCH != 0) __syncthreads();
+    if constexpr (PF_D) stage_d<PREC, S::THREADS>(a, lds, tid);
 
-    for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-        const int64_t e0 = tile * TILE_E;
-        const int nvalid = (int)((a.E - e0) < TILE_E ? (a.E - e0) : TILE_E);
-        if constexpr (PF_U) {
-            __syncthreads();  // previous tile's operand reads are done
-            stage_u_tile<PREC, LAYOUT, TILE_E, NTHREADS>(a, ut, e0, nvalid, tid);
-            __syncthreads();
+    if constexpr (!PF_U) {
+        if constexpr (PF_D) __syncthreads();
+        const int eblk = wave / S::WPE, part = wave % S::WPE;
+        for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+            const int64_t e0 = tile * TILE_E;
+            if (e0 + 16 * eblk >= a.E) continue;  // uniform per wave; no barrier below
+            block_compute<PREC, LAYOUT, NTMAX, PF_D, false, TILE_E, S::WPE, UNROLL>(
+                a, lds, nullptr, 0, e0 + 16 * eblk, part, lane);
         }
-        if (16 * eblk >= nvalid) continue;  // uniform per wave; no barrier below
-        block_compute<PREC, LAYOUT, NTMAX, PF_D, PF_U, TILE_E, UNROLL>(
-            a, lds, ut, 16 * eblk, e0 + 16 * eblk, part, lane);
+    } else {
+        auto nvalid_of = [&](int64_t tile) {
+            const int64_t rest = a.E - tile * TILE_E;
+            return (int)(rest < TILE_E ? rest : TILE_E);
+        };
+        // Loader and compute waves run separate loops with one barrier per
+        // tile each, so their registers are never live at the same time.
+        if (wave >= S::NCW) {
+            const int lw = wave - S::NCW;
+            f4 held[Loader<TILE_E, NTMAX, S::NLW>::PER_LANE];
+            int64_t tile = blockIdx.x;
+            if (tile < a.ntiles) {
+                // Prologue: tile 0 into slot 0, tile 1 held in registers.
+                loader_fetch<LAYOUT, TILE_E, NTMAX, S::NLW>(a, tile * TILE_E, nvalid_of(tile),
+                                                             lw, lane, held);
+                loader_put<LAYOUT, TILE_E, NTMAX, S::NLW>(a, ring, nvalid_of(tile), lw, lane,
+                                                           held);
+                const int64_t t1 = tile + gridDim.x;
+                if (t1 < a.ntiles)
+                    loader_fetch<LAYOUT, TILE_E, NTMAX, S::NLW>(a, t1 * TILE_E, nvalid_of(t1),
+                                                                 lw, lane, held);
+            }
+            __syncthreads();
+            for (int n = 0; tile < a.ntiles; ++n, tile += gridDim.x) {
+                const int64_t t1 = tile + gridDim.x, t2 = t1 + gridDim.x;
+                if (t1 < a.ntiles) {
+                    // slot ^ 1 was last read in the previous iteration
+                    loader_put<LAYOUT, TILE_E, NTMAX, S::NLW>(
+                        a, ring + ((n & 1) ^ 1) * slot_floats, nvalid_of(t1), lw, lane, held);
+                    if (t2 < a.ntiles)
+                        loader_fetch<LAYOUT, TILE_E, NTMAX, S::NLW>(a, t2 * TILE_E,
+                                                                     nvalid_of(t2), lw, lane, held);
+                }
+                __syncthreads();  // slot read by the compute waves; slot ^ 1 filled
+            }
+        } else {
+            const int eblk = wave / S::WPE, part = wave % S::WPE;
+            __syncthreads();
+            int64_t tile = blockIdx.x;
+            for (int n = 0; tile < a.ntiles; ++n, tile += gridDim.x) {
+                if (16 * eblk < nvalid_of(tile))
+                    block_compute<PREC, LAYOUT, NTMAX, PF_D, true, TILE_E, S::WPE, UNROLL>(
+                        a, lds, ring + (n & 1) * slot_floats, 16 * eblk,
+                        tile * TILE_E + 16 * eblk, part, lane);
+                __syncthreads();
+            }
+        }
     }
 }
 

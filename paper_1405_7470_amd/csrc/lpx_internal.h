@@ -25,6 +25,23 @@ lpx_record default_record(int precision);
 lpx_status check_record(const lpx_record* rec);
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Work-group shape of a contraction kernel instance (host and device agree
+// on it through this one function).  Without a staged u tile (prefetch bit
+// 1 clear): four waves per 16-element block, splitting its (k, i-block)
+// pairs.  With one: min(4 * tile_e/16, 8) compute waves, wpe of them per
+// block, plus nlw loader waves (1, or tile_e * ntmax / 256 when larger)
+// that keep the next u tile in registers.
+struct ContractShape {
+    int ncw, wpe, nlw, threads;
+};
+constexpr ContractShape contract_shape(int tile_e, int ntmax, int prefetch) {
+    const bool pf_u = (prefetch & 2) != 0;
+    const int nb = tile_e / 16;
+    const int ncw = pf_u ? (4 * nb < 8 ? 4 * nb : 8) : 4 * nb;
+    const int nlw = pf_u ? (tile_e * ntmax / 256 > 1 ? tile_e * ntmax / 256 : 1) : 0;
+    return ContractShape{ncw, ncw / nb, nlw, 64 * (ncw + nlw)};
+}
 inline int64_t ceil_div(int64_t x, int64_t m) { return (x + m - 1) / m; }
 
 // Geometry of one contraction launch, derived from (problem, record) on the
@@ -37,7 +54,7 @@ struct ContractGeom {
     int nt = 0;        // i-blocks of 16 rows: ceil(Np / 16)
     int ntmax = 2;     // compiled bound on nt: 2, 4 or 8
     int nsteps = 0;    // MFMA k-steps: ceil(Np / kstep)
-    int ldu = 0;       // LDS row stride of the staged u tile (elements)
+    int ldu = 0;       // LDS ring slot stride of a staged u tile (floats)
     int64_t ntiles = 0;
     int64_t nfrag = 0;     // staged D fragments: K*nt*nsteps*64 lanes
     int64_t lds_bytes = 0; // dynamic LDS per work-group (0 if no prefetch)
@@ -71,6 +88,9 @@ lpx_status launch_gemm(const lpx_gemm_desc& d, const lpx_record& r, void* stream
 // Elementwise bf16 split kernel launch (n > 0, pointers validated).
 lpx_status launch_split_bf16(const float* x, uint16_t* hi, uint16_t* lo,
                              int64_t n, void* stream);
+
+// The 12 cost-model features of (problem, record) into f[12].
+lpx_status features(const lpx_problem& p, const lpx_record& r, float* f);
 
 // Device properties of the current device, cached per device.
 struct DeviceInfo {

@@ -27,6 +27,12 @@ lpx_status key_for(const lpx_problem& p, TuneKey* k) {
     return LPX_OK;
 }
 
+__global__ void flush_kernel(float4* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 struct Events {
     hipEvent_t a = nullptr, b = nullptr;
     ~Events() {
@@ -66,8 +72,8 @@ using namespace lpx;
 extern "C" {
 
 lpx_status lpx_autotune(const lpx_contract_desc* c, int32_t precision, int32_t warmup,
-                        int32_t reps, void* stream, lpx_record* best, float* times_us,
-                        int32_t cap, int32_t* n) {
+                        int32_t reps, void* flush, int64_t flush_bytes, void* stream,
+                        lpx_record* best, float* times_us, int32_t cap, int32_t* n) {
     clear_error();
     try {
         if (!c || !best) return set_error(LPX_ERR_INVALID_ARG, "descriptor or best is NULL");
@@ -75,6 +81,9 @@ lpx_status lpx_autotune(const lpx_contract_desc* c, int32_t precision, int32_t w
             return set_error(LPX_ERR_INVALID_ARG, "bad warmup/reps/times array");
         if (precision < LPX_FP32 || precision > LPX_BF16X3)
             return set_error(LPX_ERR_INVALID_ARG, "unknown precision %d", precision);
+        if (flush && (flush_bytes <= 0 || flush_bytes % 16 ||
+                      (reinterpret_cast<uintptr_t>(flush) & 15)))
+            return set_error(LPX_ERR_INVALID_ARG, "flush buffer must be 16-byte aligned and sized");
         lpx_record def = default_record(precision);
         lpx_status s = lpx_contract_validate(c, &def);
         if (s != LPX_OK) return s;
@@ -100,6 +109,11 @@ lpx_status lpx_autotune(const lpx_contract_desc* c, int32_t precision, int32_t w
                 for (int32_t w = 0; w < warmup; ++w)
                     if ((s = lpx_contract(c, &recs[r], stream)) != LPX_OK) return s;
                 for (int32_t q = 0; q < reps; ++q) {
+                    if (flush) {
+                        hipLaunchKernelGGL(flush_kernel, dim3(2048), dim3(256), 0, st,
+                                           reinterpret_cast<float4*>(flush), flush_bytes / 16);
+                        if ((e = hipGetLastError()) != hipSuccess) break;
+                    }
                     if ((e = hipEventRecord(ev.a, st)) != hipSuccess) break;
                     if ((s = lpx_contract(c, &recs[r], stream)) != LPX_OK) return s;
                     if ((e = hipEventRecord(ev.b, st)) != hipSuccess) break;

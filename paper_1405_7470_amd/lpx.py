@@ -120,9 +120,27 @@ def lib():
         L.lpx_contract.argtypes = [ctypes.POINTER(ContractDesc), ctypes.POINTER(Record), vp]
         L.lpx_split_bf16.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
         L.lpx_autotune.argtypes = [ctypes.POINTER(ContractDesc), ctypes.c_int32, ctypes.c_int32,
-                                   ctypes.c_int32, vp, ctypes.POINTER(Record),
+                                   ctypes.c_int32, vp, ctypes.c_int64, vp, ctypes.POINTER(Record),
                                    ctypes.POINTER(ctypes.c_float), ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_int32)]
+        f32p = ctypes.POINTER(ctypes.c_float)
+        L.lpx_features.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Record), f32p]
+        L.lpx_mlp_forward.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp]
+        L.lpx_mlp_loss.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp]
+        L.lpx_mlp_backward.argtypes = [vp, vp, vp, vp, ctypes.c_int32, vp, vp, vp]
+        L.lpx_adam_step.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                    ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
+        L.lpx_mlp_pick.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp, vp, vp]
+        L.lpx_picker_save.argtypes = [ctypes.c_char_p, f32p, f32p, f32p]
+        L.lpx_picker_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]
+        L.lpx_picker_params.argtypes = [vp, f32p, f32p, f32p]
+        L.lpx_picker_free.argtypes = [vp]
+        L.lpx_pick_variant.argtypes = [ctypes.POINTER(Problem), ctypes.c_int32, vp, vp,
+                                       ctypes.POINTER(Record)]
+        for name in ("lpx_features", "lpx_mlp_forward", "lpx_mlp_loss", "lpx_mlp_backward",
+                     "lpx_adam_step", "lpx_mlp_pick", "lpx_picker_save", "lpx_picker_load",
+                     "lpx_picker_params", "lpx_picker_free", "lpx_pick_variant"):
+            getattr(L, name).restype = st
         L.lpx_tune_cache_insert.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Record)]
         L.lpx_tune_cache_clear.argtypes = []
         L.lpx_gemm.argtypes = [ctypes.POINTER(GemmDesc), ctypes.POINTER(Record), vp]
@@ -305,9 +323,11 @@ def split_bf16(x, hi=None, lo=None, stream=None):
 
 
 # ------------------------------------------------------------- autotuning
-def autotune(D, u, out=None, layout="em", precision="fp32", warmup=2, reps=7, stream=None):
+def autotune(D, u, out=None, layout="em", precision="fp32", warmup=2, reps=7, stream=None,
+             flush=None):
     """Exhaustive tuning on the given buffers; returns (best Record, list of
-    median microseconds per candidate in enumeration order; inf = skipped)."""
+    median microseconds per candidate in enumeration order; inf = skipped).
+    flush: optional CUDA tensor overwritten before every timed launch."""
     K, Np, E = contract_shapes(D, u, layout)
     if out is None:
         out = torch.empty(out_shape(K, Np, E, layout), dtype=torch.float32, device=u.device)
@@ -315,9 +335,11 @@ def autotune(D, u, out=None, layout="em", precision="fp32", warmup=2, reps=7, st
     best = Record()
     times = (ctypes.c_float * 64)()
     n = ctypes.c_int32()
+    fptr = ctypes.c_void_p(flush.data_ptr()) if flush is not None else None
+    fbytes = flush.numel() * flush.element_size() if flush is not None else 0
     _check(lib().lpx_autotune(ctypes.byref(desc), PRECISION[precision], warmup, reps,
-                              _stream_handle(stream), ctypes.byref(best), times, 64,
-                              ctypes.byref(n)))
+                              fptr, fbytes, _stream_handle(stream), ctypes.byref(best), times,
+                              64, ctypes.byref(n)))
     return best, [times[i] for i in range(n.value)]
 
 
@@ -412,3 +434,110 @@ class Batch:
             self.destroy()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------ cost model
+MLP_FEATURES, MLP_HIDDEN, MLP_PARAMS = 12, 64, 5057
+PICK_UNTUNED, PICK_EXHAUSTIVE, PICK_LEARNED = 0, 1, 2
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def features(K, Np, E, layout, rec):
+    """The 12 cost-model features of (problem, record) as a list."""
+    p = problem(K, Np, E, layout, PRECISION_NAME[rec.precision])
+    out = (ctypes.c_float * MLP_FEATURES)()
+    _check(lib().lpx_features(ctypes.byref(p), ctypes.byref(rec), out))
+    return list(out)
+
+
+def mlp_forward(params, X, act=None, y=None, stream=None):
+    n = X.shape[0]
+    if y is None:
+        y = torch.empty(n, device=X.device)
+    _check(lib().lpx_mlp_forward(_ptr(params), _ptr(X), n, _ptr(act), _ptr(y), _stream_handle(stream)))
+    return y
+
+
+def mlp_loss(y, t, dy=None, loss=None, stream=None):
+    n = y.shape[0]
+    if dy is None:
+        dy = torch.empty(n, device=y.device)
+    if loss is None:
+        loss = torch.empty(1, device=y.device)
+    _check(lib().lpx_mlp_loss(_ptr(y), _ptr(t), n, _ptr(dy), _ptr(loss), _stream_handle(stream)))
+    return dy, loss
+
+
+def mlp_backward(params, X, act, dy, grads=None, work=None, stream=None):
+    n = X.shape[0]
+    if grads is None:
+        grads = torch.empty(MLP_PARAMS, device=X.device)
+    if work is None:
+        work = torch.empty((max(n, 1), 2 * MLP_HIDDEN), device=X.device)
+    _check(lib().lpx_mlp_backward(_ptr(params), _ptr(X), _ptr(act), _ptr(dy), n, _ptr(work),
+                                  _ptr(grads), _stream_handle(stream)))
+    return grads
+
+
+def adam_step(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().lpx_adam_step(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), params.numel(), step,
+                               lr, beta1, beta2, eps, _stream_handle(stream)))
+
+
+def mlp_pick(params, feats, mean, std, pred=None, best=None, stream=None):
+    n = feats.shape[0]
+    if best is None:
+        best = torch.empty(1, dtype=torch.int32, device=feats.device)
+    _check(lib().lpx_mlp_pick(_ptr(params), _ptr(feats), n, _ptr(mean), _ptr(std), _ptr(pred),
+                              _ptr(best), _stream_handle(stream)))
+    return best
+
+
+def picker_save(path, params, mean, std):
+    import numpy as np
+    arr = [np.ascontiguousarray(a, dtype=np.float32) for a in (params, mean, std)]
+    fp = ctypes.POINTER(ctypes.c_float)
+    _check(lib().lpx_picker_save(str(path).encode(), *[a.ctypes.data_as(fp) for a in arr]))
+
+
+class Picker:
+    """A loaded cost model (lpx_picker_load); raises LpxError(ERR_MODEL) on a
+    missing or corrupt file."""
+
+    def __init__(self, path):
+        self.handle = ctypes.c_void_p(None)
+        _check(lib().lpx_picker_load(str(path).encode(), ctypes.byref(self.handle)))
+
+    def params(self):
+        import numpy as np
+        p = np.empty(MLP_PARAMS, np.float32)
+        m = np.empty(MLP_FEATURES, np.float32)
+        s = np.empty(MLP_FEATURES, np.float32)
+        fp = ctypes.POINTER(ctypes.c_float)
+        _check(lib().lpx_picker_params(self.handle, p.ctypes.data_as(fp), m.ctypes.data_as(fp),
+                                       s.ctypes.data_as(fp)))
+        return p, m, s
+
+    def close(self):
+        if self.handle:
+            lib().lpx_picker_free(self.handle)
+            self.handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pick_variant(K, Np, E, layout, precision, mode=PICK_LEARNED, picker=None, stream=None):
+    """Record chosen for the problem by mode (untuned / exhaustive / learned)."""
+    p = problem(K, Np, E, layout, precision)
+    out = Record()
+    h = picker.handle if picker is not None else None
+    _check(lib().lpx_pick_variant(ctypes.byref(p), mode, h, _stream_handle(stream),
+                                  ctypes.byref(out)))
+    return out

@@ -136,16 +136,16 @@ def test_lds_budget():
     assert status(desc(Np=128), r) == lpx.ERR_UNSUPPORTED
     s, b = lpx.lds_bytes(3, 128, 4096, "em", r)
     assert s == lpx.ERR_UNSUPPORTED and b == 3 * 8 * 32 * 64 * 4
-    # bit 1 alone stages only the u tile: 64 rows of 130 floats
+    # bit 1 alone stages only u: a two-slot ring, each slot a raw tile copy
+    # with room for padding columns: 64 * 128 + 32 floats
     s, b = lpx.lds_bytes(3, 128, 4096, "em", lpx.record("fp32", 64, 2, 1))
-    assert s == lpx.OK and b == 64 * 130 * 4
-    # the full-scale shape fits both: D 3*4*14*64*4 bytes + u tile 64*58*4
+    assert s == lpx.OK and b == 2 * (64 * 128 + 32) * 4
+    # the full-scale shape fits both: D 3*4*14*64*4 bytes + ring 2*(64*64+32)*4
     s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", lpx.record("fp32", 64, 3, 1))
-    assert s == lpx.OK and b == 3 * 4 * 14 * 64 * 4 + 64 * 58 * 4
-    # bf16x3: two bf16 planes of D fragments (16 B per lane each), u rows
-    # padded to 64 + 8 bf16 in two planes
+    assert s == lpx.OK and b == 3 * 4 * 14 * 64 * 4 + 2 * (64 * 64 + 32) * 4
+    # bf16x3: two bf16 planes of D fragments (16 B per lane each)
     s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", lpx.record("bf16x3", 32, 3, 1))
-    assert s == lpx.OK and b == 3 * 4 * 2 * 64 * 32 + 32 * 72 * 4
+    assert s == lpx.OK and b == 3 * 4 * 2 * 64 * 32 + 2 * (32 * 64 + 32) * 4
     s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", lpx.record("fp32", 64, 0, 1))
     assert s == lpx.OK and b == 0
 

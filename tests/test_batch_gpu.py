@@ -34,6 +34,12 @@ def test_batch_bitwise_equals_separate_calls(precision, layout):
     b = lpx.Batch(items, recs)
     torch.cuda.synchronize()
     for (D, u, out, lay), rec, (Dh, uh) in zip(items, recs, host):
+        K, Np = D.shape[0], D.shape[1]
+        E = u.shape[0] if lay == "em" else u.shape[1]
+        if lpx.lds_bytes(K, Np, E, lay, rec)[0] != lpx.OK:
+            # LDS staging does not fit this shape; any record of the same
+            # precision sums in the same order
+            rec = lpx.record(precision, rec.tile_e, 0, rec.unroll)
         ref = lpx.contract(D, u, layout=lay, record=rec)
         torch.cuda.synchronize()
         assert torch.equal(out, ref), lpx.describe(rec)

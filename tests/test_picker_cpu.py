@@ -1,0 +1,90 @@
+"""Picker host logic on the CPU: model file round trip and rejection of
+damaged files, the 12 features, and the pick modes that need no GPU."""
+import ctypes
+import math
+import struct
+
+import numpy as np
+import pytest
+
+from paper_1405_7470_amd import lpx
+
+
+def write_model(path, seed=0):
+    rng = np.random.default_rng(seed)
+    p = rng.normal(0, 0.1, lpx.MLP_PARAMS).astype(np.float32)
+    m = rng.normal(0, 1, 12).astype(np.float32)
+    s = np.abs(rng.normal(1, 0.1, 12)).astype(np.float32)
+    lpx.picker_save(path, p, m, s)
+    return p, m, s
+
+
+def test_round_trip(tmp_path):
+    f = tmp_path / "m.lpxpick"
+    p, m, s = write_model(f)
+    pk = lpx.Picker(f)
+    p2, m2, s2 = pk.params()
+    assert np.array_equal(p, p2) and np.array_equal(m, m2) and np.array_equal(s, s2)
+    pk.close()
+    assert f.stat().st_size == 8 + 16 + 4 * (24 + 5057) + 4
+
+
+def damaged(tmp_path, how):
+    f = tmp_path / "m.lpxpick"
+    write_model(f)
+    b = bytearray(f.read_bytes())
+    if how == "truncated":
+        b = b[:-10]
+    elif how == "magic":
+        b[0] ^= 0xFF
+    elif how == "version":
+        b[8:12] = struct.pack("<I", 2)
+    elif how == "dims":
+        b[16:20] = struct.pack("<I", 32)
+    elif how == "checksum":
+        b[200] ^= 0x01
+    elif how == "nan":
+        off = 24 + 4 * (24 + 7)
+        b[off:off + 4] = struct.pack("<f", float("nan"))
+        h = 2166136261
+        for x in bytes(b[:-4]):
+            h = ((h ^ x) * 16777619) & 0xFFFFFFFF
+        b[-4:] = struct.pack("<I", h)
+    f.write_bytes(bytes(b))
+    return f
+
+
+@pytest.mark.parametrize("how", ["truncated", "magic", "version", "dims", "checksum", "nan"])
+def test_damaged_model_rejected(tmp_path, how):
+    with pytest.raises(lpx.LpxError) as ei:
+        lpx.Picker(damaged(tmp_path, how))
+    assert ei.value.status == lpx.ERR_MODEL
+
+
+def test_missing_model_rejected(tmp_path):
+    with pytest.raises(lpx.LpxError) as ei:
+        lpx.Picker(tmp_path / "nope")
+    assert ei.value.status == lpx.ERR_MODEL
+
+
+def test_features_by_hand():
+    r = lpx.record("bf16x3", 32, 3, 4)
+    f = lpx.features(3, 56, 1 << 20, "dm", r)
+    lds = 3 * 4 * 2 * 64 * 32 + 2 * (32 * 64 + 32) * 4
+    expect = [math.log2(56), 20.0, 3.0, 1.0, 5.0, 1.0, 1.0, 2.0, 2.0, 8 / 64,
+              math.log2((1 << 20) / 32), lds / (160 * 1024)]
+    assert np.allclose(f, expect, rtol=1e-6)
+    f = lpx.features(3, 10, 1000, "em", lpx.default_record("fp32"))
+    assert f[9] == pytest.approx(6 / 16) and f[10] == pytest.approx(math.log2(63))
+    assert f[5] == 0 and f[6] == 0 and f[11] == 0
+
+
+def test_pick_modes_without_gpu():
+    r = lpx.pick_variant(3, 56, 1000, "em", "bf16", mode=lpx.PICK_UNTUNED, stream=0)
+    assert (r.tile_e, r.prefetch, r.unroll, r.precision) == (16, 0, 1, 1)
+    with pytest.raises(lpx.LpxError) as ei:
+        lpx.pick_variant(3, 56, 1000, "em", "fp32", mode=lpx.PICK_LEARNED, picker=None, stream=0)
+    assert ei.value.status == lpx.ERR_MODEL
+    with pytest.raises(lpx.LpxError) as ei:
+        lpx.pick_variant(3, 56, 1000, "em", "fp32", mode=7, stream=0)
+    assert ei.value.status == lpx.ERR_INVALID_ARG
