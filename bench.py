@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-clock budget of the oracle's bounded sample")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the GEMM and ragged-batch side measurements")
+    ap.add_argument("--model", default=None, help="picker model file (default: the packaged one)")
     return ap.parse_args()
 
 
@@ -73,25 +76,95 @@ def time_steps(work, recs, steps, warmup, stream):
     return 1000.0 * wall / steps, per
 
 
+def _event_time(fn, reps, stream):
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b) * 1e-3)
+    return sorted(ts)[len(ts) // 2]
+
+
+def extras(stream, learned_picker=None):
+    """Side measurements of the other hot-path rows: dense GEMM (the
+    degenerate case) in three precisions, and the 512-instance ragged batch
+    as one graph replay vs 512 separate launches."""
+    res = {"gemm": [], "batch": None}
+    for (M, N, Kd) in ((4096, 4096, 4096), (8192, 1024, 4096)):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(0)
+        A = torch.randn((M, Kd), device="cuda", generator=g)
+        B = torch.randn((Kd, N), device="cuda", generator=g)
+        C = torch.empty((M, N), device="cuda")
+        for prec, tiles in (("fp32", (128, 128, 64)), ("bf16", (128, 128, 64)),
+                            ("bf16x3", (128, 128, 32))):
+            rec = lpx.record(prec, gemm=tiles)
+            t = _event_time(lambda: lpx.gemm(A, B, C, record=rec, stream=stream), 5, stream)
+            tf = 2 * M * N * Kd / t / 1e12
+            res["gemm"].append({"shape": [M, N, Kd], "precision": prec, "tiles": list(tiles),
+                                "us": t * 1e6, "tflops": tf,
+                                "pct_peak": 100 * tf / PEAK_TFLOPS[prec]})
+        del A, B, C
+    shapes = inputs.ragged_shapes(n=512, seed=0)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    items = []
+    for Np, Ei in shapes:
+        D = torch.randn((K, Np, Np), device="cuda", generator=g) / math.sqrt(Np)
+        u = torch.rand((Ei, Np), device="cuda", generator=g) * 2 - 1
+        items.append((D, u, torch.empty((K, Ei, Np), device="cuda"), "em"))
+    if learned_picker is not None:
+        recs = [lpx.pick_variant(K, Np, Ei, "em", "fp32", mode=lpx.PICK_LEARNED,
+                                 picker=learned_picker, stream=stream) for Np, Ei in shapes]
+        how = "learned"
+    else:
+        recs = [lpx.record("fp32", 64, 1, 2)] * len(shapes)
+        how = "fixed fp32 tile_e=64 prefetch=1 unroll=2"
+    flop = sum(2 * K * Ei * Np * Np for Np, Ei in shapes)
+    roof = sum(max(2 * K * Ei * Np * Np / (PEAK_TFLOPS["fp32"] * 1e12),
+                   4 * (Ei * Np + K * Ei * Np + K * Np * Np) / (PEAK_HBM_GBS * 1e9))
+               for Np, Ei in shapes)
+    bt = lpx.Batch(items, recs, stream=stream)
+    t_graph = _event_time(lambda: bt.submit(stream=stream), 5, stream)
+    bt.destroy()
+    t_sep = _event_time(lambda: [lpx.contract(D, u, out=o, record=r, stream=stream)
+                                 for (D, u, o, l), r in zip(items, recs)], 3, stream)
+    res["batch"] = {"instances": len(shapes), "records": how, "gflop": flop / 1e9,
+                    "graph_us": t_graph * 1e6, "separate_us": t_sep * 1e6,
+                    "graph_tflops": flop / t_graph / 1e12,
+                    "separate_tflops": flop / t_sep / 1e12,
+                    "roofline_us": roof * 1e6, "graph_pct_roof": 100 * roof / t_graph}
+    return res
+
+
 def cpu_baseline(seconds):
     """The FP64 oracle on the host cores over a bounded sample of the same
-    workload (element-major, fp32): chunks of 4096 elements until the time
-    budget is spent."""
+    step: rounds of 2048 more elements of each of the four (layout,
+    precision) problems until the time budget is spent."""
     import oracle
-    D, u = inputs.contraction_inputs(K, NP, E, seed=0, layout="em")
-    chunk = 4096
+    data = {}
+    for layout in ("em", "dm"):
+        data[layout] = inputs.contraction_inputs(K, NP, E, seed=0, layout=layout)
+    chunk = 2048
     done = 0
     t0 = time.perf_counter()
     while done < E and time.perf_counter() - t0 < seconds:
         n = min(chunk, E - done)
-        oracle.contract(D, u, "em", "fp32", done, n)
+        for layout, prec in PROBLEMS:
+            D, u = data[layout]
+            oracle.contract(D, u, layout, prec, done, n)
         done += n
     dt = time.perf_counter() - t0
-    flop = 2 * K * done * NP * NP
+    flop = len(PROBLEMS) * 2 * K * done * NP * NP
     return {"value": flop / dt / 1e12, "unit": "TFLOP/s", "cores": oracle.threads(),
             "kind": "oracle",
-            "sample": f"elements [0, {done}) of E={E}, K={K}, Np={NP}, element-major, fp32 "
-                      f"products with fp64 accumulation, {dt:.1f} s"}
+            "sample": f"elements [0, {done}) of E={E} for each of em/fp32, dm/fp32, "
+                      f"em/bf16x3, dm/bf16x3 (K={K}, Np={NP}), fp64 accumulation, {dt:.1f} s"}
 
 
 def main():
@@ -119,7 +192,18 @@ def main():
     for key, (D, u, out) in work.items():
         tuned[key], tune_times[key] = lpx.autotune(D, u, out, key[0], key[1], warmup=2, reps=5,
                                                    stream=stream)
-    learned = None  # filled once a trained cost model is available
+    learned, pick_info = None, None
+    from paper_1405_7470_amd import picker as picker_mod
+    model = args.model or picker_mod.MODEL_PATH
+    if os.path.exists(model):
+        pk = lpx.Picker(model)
+        learned = {}
+        t0 = time.perf_counter()
+        for key in work:
+            learned[key] = lpx.pick_variant(K, NP, E, key[0], key[1], mode=lpx.PICK_LEARNED,
+                                            picker=pk, stream=stream)
+        pick_info = {"model": os.path.basename(model),
+                     "first_pick_us_per_problem": 1e6 * (time.perf_counter() - t0) / len(work)}
 
     results = {}
     for name, recs in (("untuned", untuned), ("autotuned", tuned), ("learned", learned)):
@@ -169,6 +253,13 @@ def main():
         "roofline": roofline,
         "variants": results,
     }
+    if pick_info:
+        line["picker"] = pick_info
+    if not args.no_extras:
+        try:
+            line["extras"] = extras(stream, learned_picker=(pk if learned is not None else None))
+        except Exception as exc:  # side measurements never hide the main line
+            line["extras"] = {"error": repr(exc)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)

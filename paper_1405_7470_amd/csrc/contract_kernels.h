@@ -128,21 +128,33 @@ __device__ __forceinline__ f4 mma(const Frag<LPX_BF16X3>& a, const Frag<LPX_BF16
 }
 
 // ------------------------------------------------------- global fragments
-// Eight consecutive values of a row, zero past `n`; 16-byte loads when the
-// row start is aligned and the eight values are all in range.
+// Loads here never sit behind a per-lane branch: out-of-range lanes read a
+// clamped in-bounds address and the value is replaced by zero with a select
+// where it is consumed.  (A divergent branch around a load makes the
+// compiler wait for that load at the join, serialising every load.)
+
+// Eight consecutive values row[j0 .. j0+8), zero at columns >= n (n >= 1).
+// vec: the row start is 16-byte aligned and n % 4 == 0, so each half is
+// either wholly inside or wholly outside the row.
 __device__ __forceinline__ void load_row8(const float* __restrict__ row, int j0, int n,
                                           bool vec, float (&v)[8]) {
-    if (vec && j0 + 8 <= n) {
-        f4 a = *reinterpret_cast<const f4*>(row + j0);
-        f4 b = *reinterpret_cast<const f4*>(row + j0 + 4);
+    if (vec) {  // uniform
+        const int ja = j0 < n - 4 ? j0 : n - 4;
+        const int jb = j0 + 4 < n - 4 ? j0 + 4 : n - 4;
+        const f4 a = *reinterpret_cast<const f4*>(row + ja);
+        const f4 b = *reinterpret_cast<const f4*>(row + jb);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            v[t] = a[t];
-            v[t + 4] = b[t];
+            v[t] = j0 + t < n ? a[t] : 0.0f;
+            v[t + 4] = j0 + 4 + t < n ? b[t] : 0.0f;
         }
     } else {
 #pragma unroll
-        for (int t = 0; t < 8; ++t) v[t] = (j0 + t < n) ? row[j0 + t] : 0.0f;
+        for (int t = 0; t < 8; ++t) {
+            const int j = j0 + t < n ? j0 + t : n - 1;
+            const float x = row[j];
+            v[t] = j0 + t < n ? x : 0.0f;
+        }
     }
 }
 
@@ -151,18 +163,17 @@ template <int PREC>
 __device__ __forceinline__ Frag<PREC> d_frag_global(const ContractArgs& a, int k, int t,
                                                     int s, int lane) {
     const int i = 16 * t + (lane & 15);
+    const int ic = i < a.Np ? i : a.Np - 1;
     const int j0 = s * Traits<PREC>::KSTEP + (lane >> 4) * Traits<PREC>::KPL;
-    const float* row = a.D + ((int64_t)k * a.Np + i) * a.Np;
+    const float* row = a.D + ((int64_t)k * a.Np + ic) * a.Np;
     if constexpr (PREC == LPX_FP32) {
-        return make_frag_fp32((i < a.Np && j0 < a.Np) ? row[j0] : 0.0f);
+        const float x = row[j0 < a.Np ? j0 : a.Np - 1];
+        return make_frag_fp32(i < a.Np && j0 < a.Np ? x : 0.0f);
     } else {
         float v[8];
-        if (i < a.Np) {
-            load_row8(row, j0, a.Np, a.np_vec, v);
-        } else {
+        load_row8(row, j0, a.Np, a.np_vec, v);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = 0.0f;
-        }
+        for (int q = 0; q < 8; ++q) v[q] = i < a.Np ? v[q] : 0.0f;
         return make_frag8<PREC>(v);
     }
 }
@@ -172,22 +183,27 @@ template <int PREC, int LAYOUT>
 __device__ __forceinline__ Frag<PREC> u_frag_global(const ContractArgs& a, int64_t eb0,
                                                     int s, int lane) {
     const int64_t e = eb0 + (lane & 15);
-    const int j0 = s * Traits<PREC>::KSTEP + (lane >> 4) * Traits<PREC>::KPL;
     const bool ev = e < a.E;
+    const int64_t ec = ev ? e : a.E - 1;
+    const int j0 = s * Traits<PREC>::KSTEP + (lane >> 4) * Traits<PREC>::KPL;
     if constexpr (PREC == LPX_FP32) {
-        float v = 0.0f;
-        if (ev && j0 < a.Np)
-            v = (LAYOUT == LPX_ELEMENT_MAJOR) ? a.u[e * a.Np + j0] : a.u[(int64_t)j0 * a.E + e];
-        return make_frag_fp32(v);
+        const int jc = j0 < a.Np ? j0 : a.Np - 1;
+        const float x = LAYOUT == LPX_ELEMENT_MAJOR ? a.u[ec * a.Np + jc] : a.u[(int64_t)jc * a.E + ec];
+        return make_frag_fp32(ev && j0 < a.Np ? x : 0.0f);
     } else {
         float v[8];
-        if (LAYOUT == LPX_ELEMENT_MAJOR && ev) {
-            load_row8(a.u + e * a.Np, j0, a.Np, a.np_vec, v);
+        if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
+            load_row8(a.u + ec * a.Np, j0, a.Np, a.np_vec, v);
         } else {
 #pragma unroll
-            for (int t = 0; t < 8; ++t)
-                v[t] = (ev && j0 + t < a.Np) ? a.u[(int64_t)(j0 + t) * a.E + e] : 0.0f;
+            for (int t = 0; t < 8; ++t) {
+                const int j = j0 + t < a.Np ? j0 + t : a.Np - 1;
+                const float x = a.u[(int64_t)j * a.E + ec];
+                v[t] = j0 + t < a.Np ? x : 0.0f;
+            }
         }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = ev ? v[t] : 0.0f;
         return make_frag8<PREC>(v);
     }
 }
@@ -299,40 +315,44 @@ __device__ __forceinline__ void loader_fetch(const ContractArgs& a, int64_t e0, 
     if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
         const float* src = a.u + e0 * a.Np;  // 16-byte aligned: e0 % 16 == 0
         const int nflat = nvalid * a.Np;
-        const bool full = nflat % 4 == 0;    // no chunk straddles the end
+        if (nflat % 4 == 0) {  // uniform: every chunk below nch is whole
 #pragma unroll
-        for (int q = 0; q < PL; ++q) {
-            const int c = lane + 64 * (lw + NLW * q);
-            f4 x = {0.f, 0.f, 0.f, 0.f};
-            if (c < nch) {
-                if (full || 4 * c + 4 <= nflat) {
-                    x = *reinterpret_cast<const f4*>(src + 4 * c);
-                } else {
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        if (4 * c + t < nflat) x[t] = src[4 * c + t];
-                }
+            for (int q = 0; q < PL; ++q) {
+                int c = lane + 64 * (lw + NLW * q);
+                c = c < nch ? c : nch - 1;  // the duplicate is not stored
+                v[q] = *reinterpret_cast<const f4*>(src + 4 * c);
             }
-            v[q] = x;
+        } else {  // the last tile of an odd-sized run
+            for (int q = 0; q < PL; ++q) {
+                const int c = lane + 64 * (lw + NLW * q);
+                f4 x = {0.f, 0.f, 0.f, 0.f};
+                for (int t = 0; t < 4; ++t)
+                    if (4 * c + t < nflat) x[t] = src[4 * c + t];
+                v[q] = x;
+            }
         }
     } else {
         constexpr int CPR = TILE_E / 4;
+        if (a.e_vec) {  // uniform: E % 4 == 0, so nvalid % 4 == 0 and rows are aligned
 #pragma unroll
-        for (int q = 0; q < PL; ++q) {
-            const int c = lane + 64 * (lw + NLW * q);
-            f4 x = {0.f, 0.f, 0.f, 0.f};
-            const int j = c / CPR, col = 4 * (c % CPR);
-            if (c < nch && col < nvalid) {
-                const float* src = a.u + (int64_t)j * a.E + e0 + col;
-                if (a.e_vec) {  // E % 4 == 0: nvalid % 4 == 0 and the segment is aligned
-                    x = *reinterpret_cast<const f4*>(src);
-                } else {
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        if (col + t < nvalid) x[t] = src[t];
-                }
+            for (int q = 0; q < PL; ++q) {
+                int c = lane + 64 * (lw + NLW * q);
+                c = c < nch ? c : nch - 1;
+                const int j = c / CPR;
+                int col = 4 * (c % CPR);
+                col = col < nvalid ? col : nvalid - 4;  // columns >= nvalid are never used
+                v[q] = *reinterpret_cast<const f4*>(a.u + (int64_t)j * a.E + e0 + col);
             }
-            v[q] = x;
+        } else {
+            for (int q = 0; q < PL; ++q) {
+                const int c = lane + 64 * (lw + NLW * q);
+                const int j = c / CPR, col = 4 * (c % CPR);
+                f4 x = {0.f, 0.f, 0.f, 0.f};
+                if (c < nch)
+                    for (int t = 0; t < 4; ++t)
+                        if (col + t < nvalid) x[t] = a.u[(int64_t)j * a.E + e0 + col + t];
+                v[q] = x;
+            }
         }
     }
 }
@@ -355,15 +375,29 @@ __device__ __forceinline__ void loader_put(const ContractArgs& a, float* ut, int
 // LDS by the NTHREADS threads of a work-group (caller adds the barrier).
 template <int PREC, int NTHREADS>
 __device__ __forceinline__ void stage_d(const ContractArgs& a, unsigned char* lds, int tid) {
+    // Fragments are built in batches of U per thread so that U loads are in
+    // flight together (D is small and read from L2 after the first touch).
+    constexpr int U = PREC == LPX_FP32 ? 8 : 4;
     const int64_t nfrag = (int64_t)a.K * a.nt * a.nsteps * 64;
-    for (int64_t idx = tid; idx < nfrag; idx += NTHREADS) {
-        const int l = (int)(idx & 63);
-        const int rest = (int)(idx >> 6);
-        const int s = rest % a.nsteps;
-        const int p = rest / a.nsteps;
-        const int k = p / a.nt;
-        const int t = p - k * a.nt;
-        d_frag_store_lds<PREC>(lds, nfrag, (int)idx, d_frag_global<PREC>(a, k, t, s, l));
+    for (int64_t base = 0; base < nfrag; base += (int64_t)NTHREADS * U) {
+        Frag<PREC> f[U];
+#pragma unroll
+        for (int b = 0; b < U; ++b) {
+            int64_t idx = base + tid + (int64_t)NTHREADS * b;
+            idx = idx < nfrag ? idx : nfrag - 1;  // clamped: the duplicate is not stored
+            const int l = (int)(idx & 63);
+            const int rest = (int)(idx >> 6);
+            const int s = rest % a.nsteps;
+            const int p = rest / a.nsteps;
+            const int k = p / a.nt;
+            const int t = p - k * a.nt;
+            f[b] = d_frag_global<PREC>(a, k, t, s, l);
+        }
+#pragma unroll
+        for (int b = 0; b < U; ++b) {
+            const int64_t idx = base + tid + (int64_t)NTHREADS * b;
+            if (idx < nfrag) d_frag_store_lds<PREC>(lds, nfrag, (int)idx, f[b]);
+        }
     }
 }
 
