@@ -90,14 +90,21 @@ typedef int32_t lpx_status;
  *              (the MFMA row block); each 16-element block has four wave64s
  *              that split its (k, i-block) pairs, so a work-group has
  *              4 * tile_e / 16 wavefronts.
- *   prefetch : add_prefetch (sec. 2.4.4), one bit per array, 0..3.
+ *   prefetch : storage of the operands (add_prefetch / precompute, sec.
+ *              2.4.4), a bit set from {0,1,2,3,4,6}:
  *              bit 0: all of D is staged in LDS once per work-group, in
  *              MFMA operand order and converted to the operand precision;
- *              bit 1: each u tile is staged in LDS (converted on the way)
- *              before its reduction, with the work-group barriers the
- *              paper's precompute inserts.  A clear bit means that array's
- *              MFMA operands are loaded from global memory straight into
- *              registers.
+ *              bit 1: each u tile is staged in LDS by dedicated loader waves
+ *              one tile ahead of the compute waves (a two-slot ring, one
+ *              work-group barrier per tile);
+ *              bit 2: D is precomputed into private memory -- each wave
+ *              keeps the D fragments of its own (k, i-block) pairs in
+ *              registers for the whole kernel (Np <= 64, K*ceil(Np/16) <=
+ *              12, and tile_e < 64 when bit 1 is set; else
+ *              LPX_ERR_UNSUPPORTED; unroll does not apply, the k-step
+ *              loop is fully unrolled).  Bits 0 and 2 are exclusive.
+ *              A clear bit means that array's MFMA operands are loaded
+ *              from global memory straight into registers.
  *   unroll   : 1, 2 or 4; the reduction loop over MFMA k-steps is split by
  *              `unroll` and the inner part unrolled (tag "unr", sec. 2.4.2).
  *   precision: LPX_FP32 / LPX_BF16 / LPX_BF16X3.
@@ -180,9 +187,10 @@ lpx_status lpx_record_validate(const lpx_record* rec);
 lpx_status lpx_record_describe(const lpx_record* rec, char* buf, size_t len);
 
 /* The candidate records of a problem in canonical order: precision fixed to
- * p->precision, then tile_e in {16,32,64} (outer), prefetch in {0,1,2,3},
- * unroll in {1,2,4} (inner): 36 records.  Writes min(cap, 36) records to
- * the host array `recs` and the total count to *n. */
+ * p->precision, then tile_e in {16,32,64} (outer), prefetch in
+ * {0,1,2,3,4,6}, unroll in {1,2,4} (inner): 54 records (some may be
+ * unsupported for a given shape).  Writes min(cap, 54) records to the host
+ * array `recs` and the total count to *n. */
 lpx_status lpx_record_enumerate(const lpx_problem* p, lpx_record* recs,
                                 int32_t cap, int32_t* n);
 
@@ -304,10 +312,11 @@ lpx_status lpx_tune_cache_clear(void);
 #define LPX_MLP_PARAMS 5057
 
 /* The 12 features of (problem, record), into the host array out[12]:
- * log2 Np, log2 E, K, layout, log2 tile_e, D-prefetch bit, u-prefetch bit,
+ * log2 Np, log2 E, K, layout, log2 tile_e, D storage, u-prefetch bit,
  * log2 unroll, precision code, MFMA row padding (16*ceil(Np/16) - Np) /
  * (16*ceil(Np/16)), log2 of the element-tile count, dynamic LDS bytes per
- * work-group / 160 KiB.  Needs 0 < K, 0 < Np <= 128, 0 < E. */
+ * work-group / 160 KiB.  The D-prefetch feature is the storage of D:
+ * 0 global, 1 LDS, 2 registers.  Needs 0 < K, 0 < Np <= 128, 0 < E. */
 lpx_status lpx_features(const lpx_problem* p, const lpx_record* r, float* out);
 
 /* Forward pass of n rows.  params: device, LPX_MLP_PARAMS floats; X: device

@@ -46,8 +46,8 @@ lpx_status check_record(const lpx_record* rec) {
         return set_error(LPX_ERR_INVALID_ARG, "unknown precision %u", rec->precision);
     if (rec->tile_e != 16 && rec->tile_e != 32 && rec->tile_e != 64)
         return set_error(LPX_ERR_INVALID_ARG, "tile_e %u not in {16,32,64}", rec->tile_e);
-    if (rec->prefetch > 3)
-        return set_error(LPX_ERR_INVALID_ARG, "prefetch %u not in {0,1,2,3}", rec->prefetch);
+    if (rec->prefetch > 6 || rec->prefetch == 5)
+        return set_error(LPX_ERR_INVALID_ARG, "prefetch %u not in {0,1,2,3,4,6}", rec->prefetch);
     if (rec->unroll != 1 && rec->unroll != 2 && rec->unroll != 4)
         return set_error(LPX_ERR_INVALID_ARG, "unroll %u not in {1,2,4}", rec->unroll);
     if (rec->assume_tile_divides > 1)
@@ -76,6 +76,18 @@ lpx_status contract_geometry(int K, int Np, int64_t E, int layout,
     // A staged u tile is a raw copy of the tile (tile_e * Np floats) plus
     // slack for reads of padding columns up to the next multiple of 32.
     g->ldu = r.tile_e * (int)round_up(Np, 32) + 32;  // ring slot stride in floats
+    if (r.prefetch & 4) {
+        // D in registers: each wave holds the fragments of its pairs, which
+        // needs Np <= 64, four waves per 16-element block and all of a
+        // block's pairs in one chunk.
+        const ContractShape cs = contract_shape(r.tile_e, g->ntmax, r.prefetch);
+        const int pmax = (3 * g->ntmax + cs.wpe - 1) / cs.wpe;
+        if (g->ntmax > 4 || cs.wpe != 4 || (int64_t)K * g->nt > (int64_t)cs.wpe * pmax)
+            return set_error(LPX_ERR_UNSUPPORTED,
+                             "prefetch=%u (D in registers) needs Np <= 64, K*ceil(Np/16) <= %d "
+                             "and tile_e < 64 when u is staged (K=%d Np=%d tile_e=%u)",
+                             r.prefetch, cs.wpe * pmax, K, Np, r.tile_e);
+    }
     g->lds_bytes = 0;
     if (r.prefetch) {
         const int64_t frag_bytes =
@@ -266,7 +278,7 @@ lpx_status lpx_record_enumerate(const lpx_problem* p, lpx_record* recs, int32_t 
     static const uint8_t unrolls[] = {1, 2, 4};
     int32_t count = 0;
     for (uint8_t t : tiles)
-        for (uint8_t pf = 0; pf < 4; ++pf)
+        for (uint8_t pf : {0, 1, 2, 3, 4, 6})
             for (uint8_t un : unrolls) {
                 if (count < cap) {
                     lpx_record r = default_record(p->precision);

@@ -176,7 +176,8 @@ lpx_status fill_table(lpx_batch* b, const lpx_contract_desc* items, const lpx_re
         it.tile_begin = tile;
         const int64_t frag_bytes = b->precision == LPX_FP32 ? 4 : (b->precision == LPX_BF16 ? 16 : 32);
         const int64_t dbytes = g.nfrag * frag_bytes;
-        it.d_lds = (r.prefetch & 1) && dbytes <= kLdsBudget;
+        // D staged in LDS when the record keeps D on chip (LDS or registers)
+        it.d_lds = (r.prefetch & 5) != 0 && dbytes <= kLdsBudget;
         if (it.d_lds) b->lds = std::max(b->lds, dbytes);
         tile += it.a.ntiles;
     }

@@ -26,8 +26,17 @@ ContractFn by_prefetch(int pf, int un) {
         case 0: return by_unroll<LAYOUT, NTMAX, TILE_E, 0>(un);
         case 1: return by_unroll<LAYOUT, NTMAX, TILE_E, 1>(un);
         case 2: return by_unroll<LAYOUT, NTMAX, TILE_E, 2>(un);
-        default: return by_unroll<LAYOUT, NTMAX, TILE_E, 3>(un);
+        case 3: return by_unroll<LAYOUT, NTMAX, TILE_E, 3>(un);
+        default: break;
     }
+    // D in registers: built only where the fragments fit (Np <= 64, four
+    // waves per block); the unroll knob does not apply (fully unrolled).
+    if constexpr (NTMAX <= 4) {
+        if (pf == 4) return fn<LAYOUT, NTMAX, TILE_E, 4, 1>();
+        if constexpr (contract_shape(TILE_E, NTMAX, 6).wpe == 4)
+            if (pf == 6) return fn<LAYOUT, NTMAX, TILE_E, 6, 1>();
+    }
+    return nullptr;
 }
 
 template <int LAYOUT, int NTMAX>

@@ -401,12 +401,53 @@ __device__ __forceinline__ void stage_d(const ContractArgs& a, unsigned char* ld
     }
 }
 
+// Write-back of one chunk of a wave's pairs (p = pc + q*WPE, q < PMAX).
+template <int LAYOUT, int PMAX, int WPE>
+__device__ __forceinline__ void store_pairs(const ContractArgs& a, const f4 (&acc)[PMAX], int pc,
+                                            int64_t eb0, int lane) {
+    const int npairs = a.K * a.nt;
+#pragma unroll
+    for (int q = 0; q < PMAX; ++q) {
+        const int p = pc + q * WPE;
+        if (p >= npairs) continue;
+        const int k = p / a.nt, t = p - (p / a.nt) * a.nt;
+        if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
+            const int64_t e = eb0 + (lane & 15);
+            const int i0 = 16 * t + 4 * (lane >> 4);
+            if (e < a.E && i0 < a.Np) {
+                float* dst = a.out + ((int64_t)k * a.E + e) * a.Np + i0;
+                if (a.np_vec) {
+                    *reinterpret_cast<f4*>(dst) = acc[q];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (i0 + r < a.Np) dst[r] = acc[q][r];
+                }
+            }
+        } else {
+            const int i = 16 * t + (lane & 15);
+            const int64_t e = eb0 + 4 * (lane >> 4);
+            if (i < a.Np && e < a.E) {
+                float* dst = a.out + ((int64_t)k * a.Np + i) * a.E + e;
+                if (a.e_vec) {
+                    *reinterpret_cast<f4*>(dst) = acc[q];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (e + r < a.E) dst[r] = acc[q][r];
+                }
+            }
+        }
+    }
+}
+
 // One wave's share of a 16-element block starting at element eb0: the
-// (k, i-block) pairs p = part, part + WPE, ... (WPE waves share a block); for each, the MFMA chain over
-// the k-steps of j, then the write-back.  D fragments come from LDS (PF_D)
-// or global memory; u fragments from the staged tile `ut` at row `row0`
-// (PF_U) or global memory.  The summation order of every output depends
-// only on PREC: all records of a precision give bit-identical results.
+// (k, i-block) pairs p = part, part + WPE, ... (WPE waves share a block);
+// for each, the MFMA chain over the k-steps of j, then the write-back.
+// D fragments come from LDS (PF_D) or global memory; u fragments from the
+// staged tile `ut` at row `row0` (PF_U) or global memory.  The summation
+// order of every output depends only on PREC: all records of a precision
+// give bit-identical results.
 template <int PREC, int LAYOUT, int NTMAX, bool PF_D, bool PF_U, int TILE_E, int WPE, int UNROLL>
 __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsigned char* lds,
                                               const float* ut, int row0, int64_t eb0, int part,
@@ -452,41 +493,65 @@ __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsig
             for (int uu = 0; uu < UNROLL; ++uu) step(s + uu);
         }
         for (; s < a.nsteps; ++s) step(s);
+        store_pairs<LAYOUT, PMAX, WPE>(a, acc, pc, eb0, lane);
+    }
+}
 
+// D held in registers (precompute into private memory, sec. 2.4.4): each
+// wave loads the D fragments of its own pairs once and keeps them for the
+// whole kernel.  NS k-steps cover the 16*NTMAX columns; steps past nsteps
+// hold zeros.  Needs all of the block's pairs in one chunk: K*nt <= WPE*PMAX.
+template <int PREC, int NTMAX, int WPE>
+struct DRegs {
+    static constexpr int PMAX = (3 * NTMAX + WPE - 1) / WPE;
+    static constexpr int NS = 16 * NTMAX / Traits<PREC>::KSTEP;
+    Frag<PREC> f[PMAX][NS];
+};
+
+template <int PREC, int NTMAX, int WPE>
+__device__ __forceinline__ void load_dregs(const ContractArgs& a, int part, int lane,
+                                           DRegs<PREC, NTMAX, WPE>& d) {
+    using DR = DRegs<PREC, NTMAX, WPE>;
+    const int npairs = a.K * a.nt;
 #pragma unroll
-        for (int q = 0; q < PMAX; ++q) {
-            const int p = pc + q * WPE;
-            if (p >= npairs) continue;
-            const int k = pk[q], t = pt[q];
-            if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
-                const int64_t e = eb0 + (lane & 15);
-                const int i0 = 16 * t + 4 * (lane >> 4);
-                if (e < a.E && i0 < a.Np) {
-                    float* dst = a.out + ((int64_t)k * a.E + e) * a.Np + i0;
-                    if (a.np_vec) {
-                        *reinterpret_cast<f4*>(dst) = acc[q];
-                    } else {
+    for (int q = 0; q < DR::PMAX; ++q) {
+        int p = part + q * WPE;
+        p = p < npairs ? p : npairs - 1;  // clamped: the duplicate is never used
+        const int k = p / a.nt, t = p - (p / a.nt) * a.nt;
 #pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            if (i0 + r < a.Np) dst[r] = acc[q][r];
-                    }
-                }
-            } else {
-                const int i = 16 * t + (lane & 15);
-                const int64_t e = eb0 + 4 * (lane >> 4);
-                if (i < a.Np && e < a.E) {
-                    float* dst = a.out + ((int64_t)k * a.Np + i) * a.E + e;
-                    if (a.e_vec) {
-                        *reinterpret_cast<f4*>(dst) = acc[q];
-                    } else {
+        for (int s = 0; s < DR::NS; ++s) d.f[q][s] = d_frag_global<PREC>(a, k, t, s, lane);
+    }
+}
+
+template <int PREC, int LAYOUT, int NTMAX, bool PF_U, int TILE_E, int WPE>
+__device__ __forceinline__ void block_compute_dreg(const ContractArgs& a,
+                                                   const DRegs<PREC, NTMAX, WPE>& d,
+                                                   const float* ut, int row0, int64_t eb0,
+                                                   int part, int lane) {
+    using DR = DRegs<PREC, NTMAX, WPE>;
+    const int npairs = a.K * a.nt;
+    f4 acc[DR::PMAX];
 #pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            if (e + r < a.E) dst[r] = acc[q][r];
-                    }
-                }
+    for (int q = 0; q < DR::PMAX; ++q) acc[q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < DR::NS; ++s) {
+        if (s >= a.nsteps) break;  // uniform
+        Frag<PREC> uf;
+        if constexpr (PF_U)
+            uf = u_frag_lds<PREC, LAYOUT, TILE_E>(ut, a.Np, a.np_vec, row0, s, lane);
+        else
+            uf = u_frag_global<PREC, LAYOUT>(a, eb0, s, lane);
+#pragma unroll
+        for (int q = 0; q < DR::PMAX; ++q) {
+            if (part + q * WPE < npairs) {
+                if constexpr (LAYOUT == LPX_ELEMENT_MAJOR)
+                    acc[q] = mma(d.f[q][s], uf, acc[q]);
+                else
+                    acc[q] = mma(uf, d.f[q][s], acc[q]);
             }
         }
     }
+    store_pairs<LAYOUT, DR::PMAX, WPE>(a, acc, part, eb0, lane);
 }
 
 // ------------------------------------------------------------ the kernel
@@ -508,6 +573,7 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
     using S = Shape<TILE_E, NTMAX, PREFETCH>;
     constexpr bool PF_D = (PREFETCH & 1) != 0;
     constexpr bool PF_U = S::PF_U;
+    constexpr bool D_REG = (PREFETCH & 4) != 0;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -522,11 +588,22 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
     if constexpr (!PF_U) {
         if constexpr (PF_D) __syncthreads();
         const int eblk = wave / S::WPE, part = wave % S::WPE;
-        for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-            const int64_t e0 = tile * TILE_E;
-            if (e0 + 16 * eblk >= a.E) continue;  // uniform per wave; no barrier below
-            block_compute<PREC, LAYOUT, NTMAX, PF_D, false, TILE_E, S::WPE, UNROLL>(
-                a, lds, nullptr, 0, e0 + 16 * eblk, part, lane);
+        if constexpr (D_REG) {
+            DRegs<PREC, NTMAX, S::WPE> d;
+            load_dregs<PREC, NTMAX, S::WPE>(a, part, lane, d);
+            for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+                const int64_t e0 = tile * TILE_E;
+                if (e0 + 16 * eblk >= a.E) continue;
+                block_compute_dreg<PREC, LAYOUT, NTMAX, false, TILE_E, S::WPE>(
+                    a, d, nullptr, 0, e0 + 16 * eblk, part, lane);
+            }
+        } else {
+            for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+                const int64_t e0 = tile * TILE_E;
+                if (e0 + 16 * eblk >= a.E) continue;  // uniform per wave; no barrier below
+                block_compute<PREC, LAYOUT, NTMAX, PF_D, false, TILE_E, S::WPE, UNROLL>(
+                    a, lds, nullptr, 0, e0 + 16 * eblk, part, lane);
+            }
         }
     } else {
         auto nvalid_of = [&](int64_t tile) {
@@ -565,14 +642,28 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
             }
         } else {
             const int eblk = wave / S::WPE, part = wave % S::WPE;
-            __syncthreads();
-            int64_t tile = blockIdx.x;
-            for (int n = 0; tile < a.ntiles; ++n, tile += gridDim.x) {
-                if (16 * eblk < nvalid_of(tile))
-                    block_compute<PREC, LAYOUT, NTMAX, PF_D, true, TILE_E, S::WPE, UNROLL>(
-                        a, lds, ring + (n & 1) * slot_floats, 16 * eblk,
-                        tile * TILE_E + 16 * eblk, part, lane);
+            if constexpr (D_REG) {
+                DRegs<PREC, NTMAX, S::WPE> d;
+                load_dregs<PREC, NTMAX, S::WPE>(a, part, lane, d);
                 __syncthreads();
+                int64_t tile = blockIdx.x;
+                for (int n = 0; tile < a.ntiles; ++n, tile += gridDim.x) {
+                    if (16 * eblk < nvalid_of(tile))
+                        block_compute_dreg<PREC, LAYOUT, NTMAX, true, TILE_E, S::WPE>(
+                            a, d, ring + (n & 1) * slot_floats, 16 * eblk,
+                            tile * TILE_E + 16 * eblk, part, lane);
+                    __syncthreads();
+                }
+            } else {
+                __syncthreads();
+                int64_t tile = blockIdx.x;
+                for (int n = 0; tile < a.ntiles; ++n, tile += gridDim.x) {
+                    if (16 * eblk < nvalid_of(tile))
+                        block_compute<PREC, LAYOUT, NTMAX, PF_D, true, TILE_E, S::WPE, UNROLL>(
+                            a, lds, ring + (n & 1) * slot_floats, 16 * eblk,
+                            tile * TILE_E + 16 * eblk, part, lane);
+                    __syncthreads();
+                }
             }
         }
     }

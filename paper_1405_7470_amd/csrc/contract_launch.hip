@@ -63,6 +63,7 @@ lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g, vo
         return set_error(LPX_ERR_UNSUPPORTED, "needs %lld bytes of LDS, device allows %d",
                          (long long)g.lds_bytes, dev.max_lds_per_block);
     ContractFn fn = select(g);
+    if (!fn) return set_error(LPX_ERR_INTERNAL, "no kernel instance for a validated record");
     int nb = 0;
     s = blocks_per_cu(reinterpret_cast<const void*>(fn), g.threads, g.lds_bytes, dev.device, &nb);
     if (s != LPX_OK) return s;

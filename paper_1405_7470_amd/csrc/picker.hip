@@ -48,7 +48,7 @@ lpx_status features(const lpx_problem& p, const lpx_record& r, float* f) {
     f[2] = (float)p.K;
     f[3] = (float)p.layout;
     f[4] = (float)std::log2((double)r.tile_e);
-    f[5] = (float)(r.prefetch & 1);
+    f[5] = (float)((r.prefetch & 4) ? 2 : (r.prefetch & 1));  // D: global, LDS, registers
     f[6] = (float)((r.prefetch >> 1) & 1);
     f[7] = (float)std::log2((double)r.unroll);
     f[8] = (float)r.precision;

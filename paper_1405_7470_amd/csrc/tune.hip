@@ -88,7 +88,7 @@ lpx_status lpx_autotune(const lpx_contract_desc* c, int32_t precision, int32_t w
         lpx_status s = lpx_contract_validate(c, &def);
         if (s != LPX_OK) return s;
         lpx_problem p{c->K, c->Np, c->E, c->layout, precision};
-        lpx_record recs[64];
+        lpx_record recs[64];  // >= the 54 candidates
         int32_t nrec = 0;
         s = lpx_record_enumerate(&p, recs, 64, &nrec);
         if (s != LPX_OK) return s;

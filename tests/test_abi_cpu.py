@@ -51,15 +51,15 @@ def test_default_record_is_the_untuned_variant():
 
 def test_enumeration_canonical_order_and_truncation():
     recs = lpx.enumerate_records(3, 56, 1 << 20, "em", "bf16x3")
-    assert len(recs) == 36
+    assert len(recs) == 54
     keys = [(r.tile_e, r.prefetch, r.unroll) for r in recs]
-    assert keys == [(t, p, u) for t in (16, 32, 64) for p in (0, 1, 2, 3) for u in (1, 2, 4)]
+    assert keys == [(t, p, u) for t in (16, 32, 64) for p in (0, 1, 2, 3, 4, 6) for u in (1, 2, 4)]
     assert all(lpx.PRECISION_NAME[r.precision] == "bf16x3" for r in recs)
     p = lpx.problem(3, 56, 1 << 20, "em", "fp32")
     arr = (lpx.Record * 4)()
     n = ctypes.c_int32()
     assert lpx.lib().lpx_record_enumerate(ctypes.byref(p), arr, 4, ctypes.byref(n)) == 0
-    assert n.value == 36 and arr[3].unroll == 1 and arr[3].prefetch == 1
+    assert n.value == 54 and arr[3].unroll == 1 and arr[3].prefetch == 1
 
 
 def test_describe():
@@ -68,7 +68,8 @@ def test_describe():
 
 
 @pytest.mark.parametrize("field,value", [
-    ("version", 2), ("precision", 3), ("tile_e", 8), ("tile_e", 128), ("prefetch", 4),
+    ("version", 2), ("precision", 3), ("tile_e", 8), ("tile_e", 128), ("prefetch", 5),
+    ("prefetch", 7),
     ("unroll", 3), ("assume_tile_divides", 2), ("reserved1", 1)])
 def test_malformed_records_rejected(field, value):
     r = lpx.default_record()
@@ -91,7 +92,8 @@ def status(d, rec=None):
 def test_validate_accepts_well_formed():
     assert status(desc()) == lpx.OK
     for r in lpx.enumerate_records(3, 56, 1000, "dm", "bf16x3"):
-        assert status(desc(layout=1), r) == lpx.OK
+        want = lpx.ERR_UNSUPPORTED if (r.tile_e, r.prefetch) == (64, 6) else lpx.OK
+        assert status(desc(layout=1), r) == want, lpx.describe(r)
 
 
 @pytest.mark.parametrize("kw,code", [
@@ -127,6 +129,19 @@ def test_assumption_checked():
     assert status(desc(E=1024), r) == lpx.OK
     assert status(desc(E=1000), r) == lpx.ERR_ASSUMPTION
     assert "assumes" in lpx.last_error()
+
+
+def test_register_d_limits():
+    # D in registers: fits Np <= 64 with K*ceil(Np/16) <= 12
+    assert status(desc(Np=56), lpx.record("fp32", 32, 4, 1)) == lpx.OK
+    assert status(desc(Np=56), lpx.record("bf16x3", 32, 6, 1)) == lpx.OK
+    assert status(desc(Np=84), lpx.record("fp32", 32, 4, 1)) == lpx.ERR_UNSUPPORTED
+    assert status(desc(K=4, Np=56), lpx.record("fp32", 32, 4, 1)) == lpx.ERR_UNSUPPORTED
+    # a staged 64-element tile leaves two waves per block: not enough registers
+    assert status(desc(Np=56), lpx.record("fp32", 64, 6, 1)) == lpx.ERR_UNSUPPORTED
+    assert status(desc(Np=56), lpx.record("fp32", 64, 4, 1)) == lpx.OK
+    s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", lpx.record("fp32", 32, 6, 1))
+    assert s == lpx.OK and b == 2 * (32 * 64 + 32) * 4  # only the u ring
 
 
 def test_lds_budget():

@@ -15,6 +15,13 @@ PRECS = ("fp32", "bf16x3", "bf16")
 LAYOUTS = ("em", "dm")
 
 
+def supported(K, Np, E, layout, rec):
+    """Records that validation accepts for the shape (some storage choices,
+    e.g. D in registers, only exist for part of the shapes)."""
+    st, _ = lpx.lds_bytes(K, Np, E, layout, rec)
+    return st == lpx.OK
+
+
 def run(D, u, layout, rec):
     Dd, ud = to_dev(D), to_dev(u)
     out = lpx.contract(Dd, ud, layout=layout, record=rec)
@@ -38,6 +45,8 @@ def test_every_record_matches_oracle(precision, layout):
     for Np, E in ((20, 1000), (56, 333), (35, 77)):
         D, u = inputs.contraction_inputs(3, Np, E, seed=Np, layout=layout)
         for rec in lpx.enumerate_records(3, Np, E, layout, precision):
+            if not supported(3, Np, E, layout, rec):
+                continue
             print(f"case: {precision} {layout} Np={Np} E={E} {lpx.describe(rec)}", flush=True)
             out = run(D, u, layout, rec)
             check_against_oracle(D, u, as_em(out, layout), layout, precision)
@@ -50,12 +59,12 @@ def test_edge_shapes(precision, layout):
     shapes = [(1, 1), (1, 17), (10, 15), (16, 16), (17, 65), (64, 64), (84, 129),
               (120, 31), (128, 70)]
     recs = [lpx.record(precision, t, p, un) for (t, p, un) in
-            ((16, 0, 1), (64, 0, 4), (32, 1, 2), (64, 3, 1), (16, 2, 4))]
+            ((16, 0, 1), (64, 0, 4), (32, 1, 2), (64, 3, 1), (16, 2, 4), (32, 4, 1),
+             (32, 6, 1))]
     for Np, E in shapes:
         D, u = inputs.contraction_inputs(2, Np, E, seed=E, layout=layout)
         for rec in recs:
-            s, _ = lpx.lds_bytes(2, Np, E, layout, rec)
-            if s == lpx.ERR_UNSUPPORTED:
+            if not supported(2, Np, E, layout, rec):
                 continue
             print(f"case: edge {precision} {layout} Np={Np} E={E} {lpx.describe(rec)}", flush=True)
             out = run(D, u, layout, rec)
@@ -72,6 +81,8 @@ def test_integer_inputs_bitwise_for_every_record(layout):
     exact = np.einsum("kij,ej->kei", D.astype(np.int64), ue.astype(np.int64)).astype(np.float64)
     for precision in PRECS:
         for rec in lpx.enumerate_records(K, Np, E, layout, precision):
+            if not supported(K, Np, E, layout, rec):
+                continue
             out = as_em(run(D, u, layout, rec), layout)
             assert np.array_equal(out, exact), (precision, lpx.describe(rec))
 
@@ -87,6 +98,8 @@ def test_coverage_sentinel_and_canary(layout):
     canary = 1024
     for precision in PRECS:
         for rec in lpx.enumerate_records(K, Np, E, layout, precision):
+            if not supported(K, Np, E, layout, rec):
+                continue
             buf = torch.full((n + canary,), float("nan"), device=dev())
             buf[n:] = 12345.0
             out = buf[:n].view(lpx.out_shape(K, Np, E, layout))

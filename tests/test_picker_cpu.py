@@ -74,6 +74,8 @@ def test_features_by_hand():
     expect = [math.log2(56), 20.0, 3.0, 1.0, 5.0, 1.0, 1.0, 2.0, 2.0, 8 / 64,
               math.log2((1 << 20) / 32), lds / (160 * 1024)]
     assert np.allclose(f, expect, rtol=1e-6)
+    f = lpx.features(3, 56, 1000, "em", lpx.record("fp32", 16, 6, 1))
+    assert f[5] == 2.0 and f[6] == 1.0               # D in registers, u staged
     f = lpx.features(3, 10, 1000, "em", lpx.default_record("fp32"))
     assert f[9] == pytest.approx(6 / 16) and f[10] == pytest.approx(math.log2(63))
     assert f[5] == 0 and f[6] == 0 and f[11] == 0
