@@ -25,12 +25,15 @@ import time
 import numpy as np
 import torch
 
-from paper_1405_7470_amd import inputs, lpx
+from paper_1405_7470_amd import inputs, lpx, profsum
 
 K, NP, E = 3, 56, 1 << 20
 PROBLEMS = [("em", "fp32"), ("dm", "fp32"), ("em", "bf16x3"), ("dm", "bf16x3")]
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6 / 3, "bf16": 2516.6}
 PEAK_HBM_GBS = 8000.0
+COPY_FLOATS = 1 << 26                            # 256 MiB copy: HBM reference and counter calibration
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "contract_traffic_K3_Np56_E1M.txt")
 FLOP = 2 * K * E * NP * NP                      # one contraction
 BYTES = 4 * (E * NP + K * E * NP + K * NP * NP)  # read u, D once; write out once
 
@@ -88,6 +91,17 @@ def _event_time(fn, reps, stream):
         torch.cuda.synchronize()
         ts.append(a.elapsed_time(b) * 1e-3)
     return sorted(ts)[len(ts) // 2]
+
+
+def hbm_copy(stream):
+    """Achievable HBM bandwidth on this GPU: a plain 256 MiB device copy
+    (lpx_stream_probe), median of 5.  Its dispatches also calibrate the
+    rocprofv3 byte counters."""
+    x = torch.zeros(COPY_FLOATS, device="cuda")
+    y = torch.empty(COPY_FLOATS, device="cuda")
+    t = _event_time(lambda: lpx.stream_probe(x, y, 1, stream=stream), 5, stream)
+    del x, y
+    return {"bytes_each_way": 4 * COPY_FLOATS, "us": t * 1e6, "GBps": 8 * COPY_FLOATS / t / 1e9}
 
 
 def extras(stream, learned_picker=None):
@@ -231,7 +245,15 @@ def main():
     else:
         roofline = {"bound": "hbm", "achieved": dom["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     roofline["frac"] = roofline["achieved"] / roofline["peak"]
-    roofline["traffic"] = None
+    dom_layout = dom_key.split("/")[0]
+    dom_rec = (learned or tuned)[(dom_layout, dom_prec)]
+    kname = profsum.contraction_kernel_name(dom_prec, dom_layout, NP, dom_rec)
+    t = profsum.lookup_traffic(TRAFFIC_FILE, kname)
+    roofline["traffic"] = t
+    roofline["traffic_note"] = (
+        "HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE scaled by the copy kernel"
+        if t is not None else "no counter reading for this kernel at the current sources")
+    roofline["algorithmic_bytes"] = BYTES
     roofline["kernel"] = f"contraction {dom_key} {dom['record']}"
 
     line = {
@@ -255,6 +277,7 @@ def main():
     }
     if pick_info:
         line["picker"] = pick_info
+    line["hbm_copy"] = hbm_copy(stream)
     if not args.no_extras:
         try:
             line["extras"] = extras(stream, learned_picker=(pk if learned is not None else None))

@@ -91,20 +91,25 @@ typedef int32_t lpx_status;
  *              that split its (k, i-block) pairs, so a work-group has
  *              4 * tile_e / 16 wavefronts.
  *   prefetch : storage of the operands (add_prefetch / precompute, sec.
- *              2.4.4), a bit set from {0,1,2,3,4,6}:
+ *              2.4.4), a bit set from {0,1,2,3,4,6,10,11,14}:
  *              bit 0: all of D is staged in LDS once per work-group, in
  *              MFMA operand order and converted to the operand precision;
  *              bit 1: each u tile is staged in LDS by dedicated loader waves
- *              one tile ahead of the compute waves (a two-slot ring, one
+ *              that keep two tiles in flight (a two-slot LDS ring, one
  *              work-group barrier per tile);
  *              bit 2: D is precomputed into private memory -- each wave
  *              keeps the D fragments of its own (k, i-block) pairs in
  *              registers for the whole kernel (Np <= 64, K*ceil(Np/16) <=
  *              12, and tile_e < 64 when bit 1 is set; else
  *              LPX_ERR_UNSUPPORTED; unroll does not apply, the k-step
- *              loop is fully unrolled).  Bits 0 and 2 are exclusive.
- *              A clear bit means that array's MFMA operands are loaded
- *              from global memory straight into registers.
+ *              loop is fully unrolled);
+ *              bit 3 (needs bit 1): each output tile is staged in LDS and
+ *              written back by dedicated store waves with contiguous
+ *              16-byte stores one tile behind the compute waves, which then
+ *              touch no global memory at all.
+ *              Bits 0 and 2 are exclusive.  A clear bit means that array's
+ *              MFMA operands are loaded from global memory straight into
+ *              registers (or, for the output, stored straight from them).
  *   unroll   : 1, 2 or 4; the reduction loop over MFMA k-steps is split by
  *              `unroll` and the inner part unrolled (tag "unr", sec. 2.4.2).
  *   precision: LPX_FP32 / LPX_BF16 / LPX_BF16X3.
@@ -188,9 +193,10 @@ lpx_status lpx_record_describe(const lpx_record* rec, char* buf, size_t len);
 
 /* The candidate records of a problem in canonical order: precision fixed to
  * p->precision, then tile_e in {16,32,64} (outer), prefetch in
- * {0,1,2,3,4,6}, unroll in {1,2,4} (inner): 54 records (some may be
- * unsupported for a given shape).  Writes min(cap, 54) records to the host
- * array `recs` and the total count to *n. */
+ * {0,1,2,3,4,6,10,11,14}, unroll in {1,2,4} (inner): LPX_MAX_RECORDS = 81
+ * records (some may be unsupported for a given shape).  Writes
+ * min(cap, 81) records to the host array `recs` and the total count to *n. */
+#define LPX_MAX_RECORDS 81
 lpx_status lpx_record_enumerate(const lpx_problem* p, lpx_record* recs,
                                 int32_t cap, int32_t* n);
 
@@ -312,7 +318,8 @@ lpx_status lpx_tune_cache_clear(void);
 #define LPX_MLP_PARAMS 5057
 
 /* The 12 features of (problem, record), into the host array out[12]:
- * log2 Np, log2 E, K, layout, log2 tile_e, D storage, u-prefetch bit,
+ * log2 Np, log2 E, K, layout, log2 tile_e, D storage, staging (0 none,
+ * 1 u tile, 2 u and output tiles),
  * log2 unroll, precision code, MFMA row padding (16*ceil(Np/16) - Np) /
  * (16*ceil(Np/16)), log2 of the element-tile count, dynamic LDS bytes per
  * work-group / 160 KiB.  The D-prefetch feature is the storage of D:

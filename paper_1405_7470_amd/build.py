@@ -7,6 +7,7 @@ paper_1405_7470_amd.build``.
 """
 import concurrent.futures as cf
 import glob
+import re
 import os
 import subprocess
 import sys
@@ -45,6 +46,8 @@ def _compile(src):
 def build(verbose: bool = True, jobs: int = 0) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    # the kernel-instance units take longest: start them first
+    srcs.sort(key=lambda f: not re.search(r"contract_\w+_(em|dm)\.hip$", f))
     jobs = jobs or min(len(srcs), os.cpu_count() or 4, 16)
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, srcs))

@@ -37,6 +37,17 @@ lpx_record default_record(int precision) {
     return r;
 }
 
+// The prefetch bit sets of sec. 2.4.4 that are built: bits 0 (D in LDS)
+// and 2 (D in registers) exclude each other, and bit 3 (staged output)
+// needs bit 1 (staged u, the pipeline its store waves join).
+static const uint8_t kPrefetchSets[] = {0, 1, 2, 3, 4, 6, 10, 11, 14};
+
+static bool prefetch_valid(unsigned pf) {
+    for (uint8_t v : kPrefetchSets)
+        if (v == pf) return true;
+    return false;
+}
+
 lpx_status check_record(const lpx_record* rec) {
     if (!rec) return set_error(LPX_ERR_INVALID_ARG, "record is NULL");
     if (rec->version != LPX_RECORD_VERSION)
@@ -46,8 +57,9 @@ lpx_status check_record(const lpx_record* rec) {
         return set_error(LPX_ERR_INVALID_ARG, "unknown precision %u", rec->precision);
     if (rec->tile_e != 16 && rec->tile_e != 32 && rec->tile_e != 64)
         return set_error(LPX_ERR_INVALID_ARG, "tile_e %u not in {16,32,64}", rec->tile_e);
-    if (rec->prefetch > 6 || rec->prefetch == 5)
-        return set_error(LPX_ERR_INVALID_ARG, "prefetch %u not in {0,1,2,3,4,6}", rec->prefetch);
+    if (!prefetch_valid(rec->prefetch))
+        return set_error(LPX_ERR_INVALID_ARG, "prefetch %u not in {0,1,2,3,4,6,10,11,14}",
+                         rec->prefetch);
     if (rec->unroll != 1 && rec->unroll != 2 && rec->unroll != 4)
         return set_error(LPX_ERR_INVALID_ARG, "unroll %u not in {1,2,4}", rec->unroll);
     if (rec->assume_tile_divides > 1)
@@ -75,7 +87,22 @@ lpx_status contract_geometry(int K, int Np, int64_t E, int layout,
     g->nfrag = (int64_t)K * g->nt * g->nsteps * 64;
     // A staged u tile is a raw copy of the tile (tile_e * Np floats) plus
     // slack for reads of padding columns up to the next multiple of 32.
-    g->ldu = r.tile_e * (int)round_up(Np, 32) + 32;  // ring slot stride in floats
+    // u ring slot stride in floats: a raw tile copy with slack for reads of
+    // padding columns (up to the next multiple of 32), and room for every
+    // chunk the loader waves write (tiles are loaded in whole rounds of
+    // 64 chunks per loader wave).
+    {
+        const ContractShape cs = contract_shape(r.tile_e, g->ntmax, r.prefetch);
+        const int nlw = cs.nlw > 0 ? cs.nlw : 1;
+        const int64_t need = (int64_t)r.tile_e * round_up(Np, 32) + 32;
+        const int64_t rounds = 256LL * nlw * loader_per_lane(r.tile_e, g->ntmax, nlw);
+        g->ldu = (int)(need > rounds ? need : rounds);
+    }
+    // A staged output tile: element-major K*tile_e*Np floats, DOF-major
+    // K*Np rows of tile_e + 4 floats (both multiples of 4 floats).
+    const int64_t ldo = layout == LPX_ELEMENT_MAJOR ? round_up((int64_t)K * r.tile_e * Np, 4)
+                                                    : (int64_t)K * Np * (r.tile_e + 4);
+    g->ldo = (r.prefetch & 8) && ldo <= kMaxLdsPerWorkgroup ? (int)ldo : 0;
     if (r.prefetch & 4) {
         // D in registers: each wave holds the fragments of its pairs, which
         // needs Np <= 64, four waves per 16-element block and all of a
@@ -92,9 +119,10 @@ lpx_status contract_geometry(int K, int Np, int64_t E, int layout,
     if (r.prefetch) {
         const int64_t frag_bytes =
             r.precision == LPX_FP32 ? 4 : (r.precision == LPX_BF16 ? 16 : 32);
-        const int64_t ring_bytes = 2 * (int64_t)g->ldu * 4;
+        const int64_t ring_bytes = 4 * (int64_t)g->ldu * 4;  // four slots
         g->lds_bytes = ((r.prefetch & 1) ? g->nfrag * frag_bytes : 0) +
-                       ((r.prefetch & 2) ? ring_bytes : 0);
+                       ((r.prefetch & 2) ? ring_bytes : 0) +
+                       ((r.prefetch & 8) ? 2 * ldo * 4 : 0);
         if (g->lds_bytes > kMaxLdsPerWorkgroup)
             return set_error(LPX_ERR_UNSUPPORTED,
                              "prefetch=%u needs %lld bytes of LDS per work-group for K=%d "
@@ -278,7 +306,7 @@ lpx_status lpx_record_enumerate(const lpx_problem* p, lpx_record* recs, int32_t 
     static const uint8_t unrolls[] = {1, 2, 4};
     int32_t count = 0;
     for (uint8_t t : tiles)
-        for (uint8_t pf : {0, 1, 2, 3, 4, 6})
+        for (uint8_t pf : kPrefetchSets)
             for (uint8_t un : unrolls) {
                 if (count < cap) {
                     lpx_record r = default_record(p->precision);

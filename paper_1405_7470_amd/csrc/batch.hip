@@ -171,6 +171,7 @@ lpx_status fill_table(lpx_batch* b, const lpx_contract_desc* items, const lpx_re
         it.a.nt = g.nt;
         it.a.nsteps = g.nsteps;
         it.a.ldu = g.ldu;
+        it.a.ldo = g.ldo;
         it.a.np_vec = (c.Np % 4) == 0;
         it.a.e_vec = (c.E % 4) == 0;
         it.tile_begin = tile;

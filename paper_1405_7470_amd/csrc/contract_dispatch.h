@@ -1,0 +1,79 @@
+// Record -> kernel instance table of the contraction family, one
+// translation unit per (precision, layout) so that the instances compile in
+// parallel.  Records outside what is built map to nullptr.
+#pragma once
+
+#include "contract_kernels.h"
+
+namespace lpx {
+
+using ContractFn = void (*)(kern::ContractArgs);
+
+namespace dispatch {
+
+template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PF, int UN>
+ContractFn fn() {
+    return &kern::contract_kernel<PREC, LAYOUT, NTMAX, TILE_E, PF, UN>;
+}
+
+template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PF>
+ContractFn by_unroll(int un) {
+    switch (un) {
+        case 1: return fn<PREC, LAYOUT, NTMAX, TILE_E, PF, 1>();
+        case 2: return fn<PREC, LAYOUT, NTMAX, TILE_E, PF, 2>();
+        default: return fn<PREC, LAYOUT, NTMAX, TILE_E, PF, 4>();
+    }
+}
+
+template <int PREC, int LAYOUT, int NTMAX, int TILE_E>
+ContractFn by_prefetch(int pf, int un) {
+    switch (pf) {
+        case 0: return by_unroll<PREC, LAYOUT, NTMAX, TILE_E, 0>(un);
+        case 1: return by_unroll<PREC, LAYOUT, NTMAX, TILE_E, 1>(un);
+        case 2: return by_unroll<PREC, LAYOUT, NTMAX, TILE_E, 2>(un);
+        case 3: return by_unroll<PREC, LAYOUT, NTMAX, TILE_E, 3>(un);
+        case 10: return by_unroll<PREC, LAYOUT, NTMAX, TILE_E, 10>(un);
+        case 11: return by_unroll<PREC, LAYOUT, NTMAX, TILE_E, 11>(un);
+        default: break;
+    }
+    // D in registers: built only where the fragments fit (Np <= 64, four
+    // waves per block); the unroll knob does not apply (fully unrolled).
+    if constexpr (NTMAX <= 4) {
+        if (pf == 4) return fn<PREC, LAYOUT, NTMAX, TILE_E, 4, 1>();
+        if constexpr (contract_shape(TILE_E, NTMAX, 6).wpe == 4) {
+            if (pf == 6) return fn<PREC, LAYOUT, NTMAX, TILE_E, 6, 1>();
+            if (pf == 14) return fn<PREC, LAYOUT, NTMAX, TILE_E, 14, 1>();
+        }
+    }
+    return nullptr;
+}
+
+template <int PREC, int LAYOUT, int NTMAX>
+ContractFn by_tile(int tile, int pf, int un) {
+    switch (tile) {
+        case 16: return by_prefetch<PREC, LAYOUT, NTMAX, 16>(pf, un);
+        case 32: return by_prefetch<PREC, LAYOUT, NTMAX, 32>(pf, un);
+        default: return by_prefetch<PREC, LAYOUT, NTMAX, 64>(pf, un);
+    }
+}
+
+template <int PREC, int LAYOUT>
+ContractFn by_nt(int ntmax, int tile, int pf, int un) {
+    switch (ntmax) {
+        case 2: return by_tile<PREC, LAYOUT, 2>(tile, pf, un);
+        case 4: return by_tile<PREC, LAYOUT, 4>(tile, pf, un);
+        default: return by_tile<PREC, LAYOUT, 8>(tile, pf, un);
+    }
+}
+
+}  // namespace dispatch
+
+// One definition per (precision, layout) translation unit.
+ContractFn contract_kernel_fp32_em(int ntmax, int tile, int pf, int un);
+ContractFn contract_kernel_fp32_dm(int ntmax, int tile, int pf, int un);
+ContractFn contract_kernel_bf16_em(int ntmax, int tile, int pf, int un);
+ContractFn contract_kernel_bf16_dm(int ntmax, int tile, int pf, int un);
+ContractFn contract_kernel_bf16x3_em(int ntmax, int tile, int pf, int un);
+ContractFn contract_kernel_bf16x3_dm(int ntmax, int tile, int pf, int un);
+
+}  // namespace lpx

@@ -9,7 +9,8 @@
 //   NTMAX     compiled bound on the number of 16-row i-blocks (2, 4, 8)
 //   TILE_E    split_iname(e, TILE_E), outer index -> work-group (sec. 2.4.1)
 //   PREFETCH  add_prefetch (sec. 2.4.4), one bit per array: bit 0 stages all
-//             of D in LDS (once per work-group), bit 1 stages each u tile
+//             of D in LDS (once per work-group), bit 1 stages each u tile,
+//             bit 2 keeps D in registers, bit 3 stages each output tile
 //   UNROLL    split of the MFMA k-step loop with the inner part unrolled
 //             (tag "unr", sec. 2.4.2)
 //
@@ -33,7 +34,11 @@
 // column) l % 16 and the k-slots (l / 16) * KPL ... + KPL - 1 of the step,
 // KPL = 1 (fp32) or 8 (bf16).  The product pairs A and B values of the same
 // lane-group/slot, so any mapping of j onto (step, group, slot) is correct
-// as long as both operands use it; here j = step*KSTEP + group*KPL + slot.
+// as long as both operands use it.  bf16: j = step*32 + group*8 + slot.
+// fp32: steps come in quads of four (16 columns); step 4Q+m of quad Q gives
+// group g the column j = 16Q + 4g + m, so a lane's four values of a quad
+// are consecutive in memory and arrive in one 16-byte read.  Steps after
+// the last whole quad use j = 4*step + g.
 // The 16x16 result: lane l, register r holds row 4*(l/16) + r, column l%16.
 #pragma once
 
@@ -56,6 +61,7 @@ struct ContractArgs {
     int64_t E;
     int64_t ntiles;
     int K, Np, nt, nsteps, ldu;
+    int ldo;     // staged output slot stride (floats), prefetch bit 3
     int np_vec;  // Np % 4 == 0: 16-byte row accesses are aligned
     int e_vec;   // E % 4 == 0
 };
@@ -85,6 +91,11 @@ struct Traits<LPX_FP32> {
     static constexpr int KSTEP = 4;
     static constexpr int KPL = 1;
 };
+
+// Column j of lane group g at fp32 step s (nquad_steps = 4 * whole quads).
+__device__ __forceinline__ int fp32_col(int s, int g, int nquad_steps) {
+    return s < nquad_steps ? 16 * (s >> 2) + 4 * g + (s & 3) : 4 * s + g;
+}
 
 // ------------------------------------------------------------ conversions
 __device__ __forceinline__ Frag<LPX_FP32> make_frag_fp32(float v) { return {v}; }
@@ -164,12 +175,13 @@ __device__ __forceinline__ Frag<PREC> d_frag_global(const ContractArgs& a, int k
                                                     int s, int lane) {
     const int i = 16 * t + (lane & 15);
     const int ic = i < a.Np ? i : a.Np - 1;
-    const int j0 = s * Traits<PREC>::KSTEP + (lane >> 4) * Traits<PREC>::KPL;
     const float* row = a.D + ((int64_t)k * a.Np + ic) * a.Np;
     if constexpr (PREC == LPX_FP32) {
+        const int j0 = fp32_col(s, lane >> 4, a.nsteps & ~3);
         const float x = row[j0 < a.Np ? j0 : a.Np - 1];
         return make_frag_fp32(i < a.Np && j0 < a.Np ? x : 0.0f);
     } else {
+        const int j0 = s * Traits<PREC>::KSTEP + (lane >> 4) * Traits<PREC>::KPL;
         float v[8];
         load_row8(row, j0, a.Np, a.np_vec, v);
 #pragma unroll
@@ -185,12 +197,13 @@ __device__ __forceinline__ Frag<PREC> u_frag_global(const ContractArgs& a, int64
     const int64_t e = eb0 + (lane & 15);
     const bool ev = e < a.E;
     const int64_t ec = ev ? e : a.E - 1;
-    const int j0 = s * Traits<PREC>::KSTEP + (lane >> 4) * Traits<PREC>::KPL;
     if constexpr (PREC == LPX_FP32) {
+        const int j0 = fp32_col(s, lane >> 4, a.nsteps & ~3);
         const int jc = j0 < a.Np ? j0 : a.Np - 1;
         const float x = LAYOUT == LPX_ELEMENT_MAJOR ? a.u[ec * a.Np + jc] : a.u[(int64_t)jc * a.E + ec];
         return make_frag_fp32(ev && j0 < a.Np ? x : 0.0f);
     } else {
+        const int j0 = s * Traits<PREC>::KSTEP + (lane >> 4) * Traits<PREC>::KPL;
         float v[8];
         if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
             load_row8(a.u + ec * a.Np, j0, a.Np, a.np_vec, v);
@@ -208,9 +221,64 @@ __device__ __forceinline__ Frag<PREC> u_frag_global(const ContractArgs& a, int64
     }
 }
 
+// fp32 quads from global memory: the lane's four values of quad Q.
+// Four consecutive values row[j0 .. j0+4), zero at columns >= n (n >= 1,
+// j0 % 4 == 0).  vec: 16-byte aligned row start and n % 4 == 0.
+__device__ __forceinline__ f4 load_row4(const float* __restrict__ row, int j0, int n,
+                                        bool vec) {
+    f4 v;
+    if (vec) {  // uniform
+        const f4 x = *reinterpret_cast<const f4*>(row + (j0 < n ? j0 : n - 4));
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v[t] = j0 + t < n ? x[t] : 0.0f;
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const float x = row[j0 + t < n ? j0 + t : n - 1];
+            v[t] = j0 + t < n ? x : 0.0f;
+        }
+    }
+    return v;
+}
+
+__device__ __forceinline__ f4 d_quad_global(const ContractArgs& a, int k, int t, int Q,
+                                            int lane) {
+    const int i = 16 * t + (lane & 15);
+    const int ic = i < a.Np ? i : a.Np - 1;
+    const f4 v = load_row4(a.D + ((int64_t)k * a.Np + ic) * a.Np, 16 * Q + 4 * (lane >> 4),
+                           a.Np, a.np_vec);
+    const f4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+    return i < a.Np ? v : z;
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ f4 u_quad_global(const ContractArgs& a, int64_t eb0, int Q,
+                                            int lane) {
+    const int64_t e = eb0 + (lane & 15);
+    const bool ev = e < a.E;
+    const int64_t ec = ev ? e : a.E - 1;
+    const int j0 = 16 * Q + 4 * (lane >> 4);
+    f4 v;
+    if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
+        v = load_row4(a.u + ec * a.Np, j0, a.Np, a.np_vec);
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int j = j0 + t < a.Np ? j0 + t : a.Np - 1;
+            const float x = a.u[(int64_t)j * a.E + ec];
+            v[t] = j0 + t < a.Np ? x : 0.0f;
+        }
+    }
+    const f4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+    return ev ? v : z;
+}
+
 // ------------------------------------------------------------ LDS layout
 // [D fragments, operand order: ((k*nt + t)*nsteps + s)*64 + lane]
-//   fp32: float; bf16: 16-byte hi plane; bf16x3: hi plane then lo plane
+//   fp32: float; bf16: 16-byte hi plane; bf16x3: hi plane then lo plane.
+//   fp32 quads are lane-major inside their 4*64-float block: step 4Q+m of
+//   pair p, lane l sits at (p*nsteps + 4Q)*64 + 4l + m (one 16-byte read
+//   per lane and quad); the steps after the last quad keep operand order.
 // [u ring: two slots of ldu floats, raw FP32 copies of u tiles]
 template <int PREC>
 struct Lds {
@@ -230,6 +298,11 @@ __device__ __forceinline__ Frag<PREC> d_frag_lds(const unsigned char* lds, int64
         const bf16x8* p = reinterpret_cast<const bf16x8*>(lds);
         return {p[idx], p[nfrag + idx]};
     }
+}
+
+__device__ __forceinline__ f4 d_quad_lds(const unsigned char* lds, int p, int Q, int nsteps,
+                                         int lane) {
+    return reinterpret_cast<const f4*>(lds)[(p * nsteps + 4 * Q) * 16 + lane];
 }
 
 template <int PREC>
@@ -259,13 +332,15 @@ __device__ __forceinline__ void d_frag_store_lds(unsigned char* lds, int64_t nfr
 // what they read to the operand precision.
 template <int PREC, int LAYOUT, int TILE_E>
 __device__ __forceinline__ Frag<PREC> u_frag_lds(const float* ut, int Np, bool np_vec, int row0,
-                                                 int s, int lane) {
+                                                 int s, int nquad_steps, int lane) {
     const int r = row0 + (lane & 15);
-    const int j0 = s * Traits<PREC>::KSTEP + (lane >> 4) * Traits<PREC>::KPL;
     if constexpr (PREC == LPX_FP32) {
-        const float x = LAYOUT == LPX_ELEMENT_MAJOR ? ut[r * Np + j0] : ut[j0 * TILE_E + r];
+        const int j0 = fp32_col(s, lane >> 4, nquad_steps);
+        const int jc = j0 < Np ? j0 : Np - 1;  // callers may read steps past the last
+        const float x = LAYOUT == LPX_ELEMENT_MAJOR ? ut[r * Np + jc] : ut[jc * TILE_E + r];
         return {j0 < Np ? x : 0.0f};
     } else {
+        const int j0 = s * Traits<PREC>::KSTEP + (lane >> 4) * Traits<PREC>::KPL;
         float v[8];
         if (LAYOUT == LPX_ELEMENT_MAJOR && np_vec) {  // 16-byte aligned rows
             const f4 a = *reinterpret_cast<const f4*>(ut + r * Np + j0);
@@ -286,87 +361,114 @@ __device__ __forceinline__ Frag<PREC> u_frag_lds(const float* ut, int Np, bool n
     }
 }
 
-// Loader waves.  A tile is cut into 16-byte chunks; chunk c goes to slot
-// offset 16c bytes.  Loader wave lw (of NLW) holds chunks
-// c = lane + 64 * (lw + NLW * q), q < PER_LANE, in registers from one
-// iteration to the next, so its global loads are in flight while the
-// compute waves work on the previous tile.  Loader waves issue no global
-// stores, so their waits cover their own loads only.
+// fp32 quad Q of the staged tile (see u_frag_lds for the layout).
+template <int LAYOUT, int TILE_E>
+__device__ __forceinline__ f4 u_quad_lds(const float* ut, int Np, bool np_vec, int row0, int Q,
+                                         int lane) {
+    const int r = row0 + (lane & 15);
+    const int j0 = 16 * Q + 4 * (lane >> 4);
+    f4 v;
+    if (LAYOUT == LPX_ELEMENT_MAJOR && np_vec) {  // 16-byte aligned rows
+        v = *reinterpret_cast<const f4*>(ut + r * Np + j0);
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            v[t] = LAYOUT == LPX_ELEMENT_MAJOR ? ut[r * Np + j0 + t] : ut[(j0 + t) * TILE_E + r];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = j0 + t < Np ? v[t] : 0.0f;
+    return v;
+}
+
+// Loader waves fill the u ring with direct global-to-LDS loads
+// (global_load_lds: the data goes to LDS without passing through
+// registers, each lane's 4 or 16 bytes at base + lane * size).  A tile is
+// a raw copy of its bytes in global memory, cut into 16-byte chunks; chunk
+// c sits at slot byte 16c.  Loader wave lw (of NLW) loads chunks
+// c = lane + 64 * (lw + NLW * q), q < PER_LANE.  Chunks past the tile are
+// clamped to its last chunk (the duplicates land in the slot's slack and
+// are never read), so every regular tile costs exactly PER_LANE load
+// instructions per loader wave and the loader can wait for one tile with a
+// compile-time vmcnt while later tiles are still in flight.
 //   element-major: chunk c = floats 4c..4c+3 of the run of nvalid*Np floats;
 //   DOF-major:     chunk c = row j = c / (TILE_E/4), columns
 //                  4*(c % (TILE_E/4)) .. +3.
+// A tile whose chunks are not all whole 16-byte aligned runs (the last
+// element-major tile when nvalid*Np % 4 != 0; every DOF-major tile when
+// E % 4 != 0) is loaded with 4-byte loads instead (4*PER_LANE
+// instructions), and is waited for with vmcnt(0).
 template <int TILE_E, int NTMAX, int NLW>
 struct Loader {
-    static constexpr int CHUNKS = TILE_E * 16 * NTMAX / 4;  // upper bound per tile
-    static constexpr int PER_LANE = (CHUNKS + 64 * NLW - 1) / (64 * NLW);
+    static constexpr int PER_LANE = loader_per_lane(TILE_E, NTMAX, NLW);
 };
 
-// Number of chunks of a tile with nvalid elements.
-template <int LAYOUT, int TILE_E>
-__device__ __forceinline__ int tile_chunks(const ContractArgs& a, int nvalid) {
-    return LAYOUT == LPX_ELEMENT_MAJOR ? (nvalid * a.Np + 3) / 4 : a.Np * (TILE_E / 4);
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __forceinline__ void dma16(const float* g, float* lds_base) {
+    __builtin_amdgcn_global_load_lds(static_cast<const void*>(g),
+                                     (lds_void*)(lds_base), 16, 0, 0);
+}
+__device__ __forceinline__ void dma4(const float* g, float* lds_base) {
+    __builtin_amdgcn_global_load_lds(static_cast<const void*>(g),
+                                     (lds_void*)(lds_base), 4, 0, 0);
 }
 
+// s_waitcnt immediate that waits until at most n vector-memory operations
+// of this wave are outstanding (other counters untouched).
+constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+
+// Issues the loads of one tile into `slot`; returns true for a regular
+// tile (exactly PER_LANE 16-byte loads from this wave).
 template <int LAYOUT, int TILE_E, int NTMAX, int NLW>
-__device__ __forceinline__ void loader_fetch(const ContractArgs& a, int64_t e0, int nvalid, int lw,
-                                             int lane, f4 (&v)[Loader<TILE_E, NTMAX, NLW>::PER_LANE]) {
+__device__ __forceinline__ bool loader_issue(const ContractArgs& a, float* slot, int64_t e0,
+                                             int nvalid, int lw, int lane) {
     constexpr int PL = Loader<TILE_E, NTMAX, NLW>::PER_LANE;
-    const int nch = tile_chunks<LAYOUT, TILE_E>(a, nvalid);
     if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
         const float* src = a.u + e0 * a.Np;  // 16-byte aligned: e0 % 16 == 0
         const int nflat = nvalid * a.Np;
-        if (nflat % 4 == 0) {  // uniform: every chunk below nch is whole
+        if (nflat % 4 == 0) {  // uniform
+            const int nch = nflat / 4;
 #pragma unroll
             for (int q = 0; q < PL; ++q) {
-                int c = lane + 64 * (lw + NLW * q);
-                c = c < nch ? c : nch - 1;  // the duplicate is not stored
-                v[q] = *reinterpret_cast<const f4*>(src + 4 * c);
+                const int w = lw + NLW * q;
+                const int c = lane + 64 * w;
+                dma16(src + 4 * (c < nch ? c : nch - 1), slot + 256 * w);
             }
-        } else {  // the last tile of an odd-sized run
-            for (int q = 0; q < PL; ++q) {
-                const int c = lane + 64 * (lw + NLW * q);
-                f4 x = {0.f, 0.f, 0.f, 0.f};
-                for (int t = 0; t < 4; ++t)
-                    if (4 * c + t < nflat) x[t] = src[4 * c + t];
-                v[q] = x;
-            }
+            return true;
         }
+#pragma unroll
+        for (int q = 0; q < 4 * PL; ++q) {
+            const int w = lw + NLW * q;
+            const int f = lane + 64 * w;
+            dma4(src + (f < nflat ? f : nflat - 1), slot + 64 * w);
+        }
+        return false;
     } else {
         constexpr int CPR = TILE_E / 4;
         if (a.e_vec) {  // uniform: E % 4 == 0, so nvalid % 4 == 0 and rows are aligned
+            const int nch = a.Np * CPR;
 #pragma unroll
             for (int q = 0; q < PL; ++q) {
-                int c = lane + 64 * (lw + NLW * q);
+                const int w = lw + NLW * q;
+                int c = lane + 64 * w;
                 c = c < nch ? c : nch - 1;
-                const int j = c / CPR;
                 int col = 4 * (c % CPR);
                 col = col < nvalid ? col : nvalid - 4;  // columns >= nvalid are never used
-                v[q] = *reinterpret_cast<const f4*>(a.u + (int64_t)j * a.E + e0 + col);
+                dma16(a.u + (int64_t)(c / CPR) * a.E + e0 + col, slot + 256 * w);
             }
-        } else {
-            for (int q = 0; q < PL; ++q) {
-                const int c = lane + 64 * (lw + NLW * q);
-                const int j = c / CPR, col = 4 * (c % CPR);
-                f4 x = {0.f, 0.f, 0.f, 0.f};
-                if (c < nch)
-                    for (int t = 0; t < 4; ++t)
-                        if (col + t < nvalid) x[t] = a.u[(int64_t)j * a.E + e0 + col + t];
-                v[q] = x;
-            }
+            return true;
         }
-    }
-}
-
-template <int LAYOUT, int TILE_E, int NTMAX, int NLW>
-__device__ __forceinline__ void loader_put(const ContractArgs& a, float* ut, int nvalid, int lw,
-                                           int lane,
-                                           const f4 (&v)[Loader<TILE_E, NTMAX, NLW>::PER_LANE]) {
-    constexpr int PL = Loader<TILE_E, NTMAX, NLW>::PER_LANE;
-    const int nch = tile_chunks<LAYOUT, TILE_E>(a, nvalid);
+        const int nf = a.Np * TILE_E;
 #pragma unroll
-    for (int q = 0; q < PL; ++q) {
-        const int c = lane + 64 * (lw + NLW * q);
-        if (c < nch) reinterpret_cast<f4*>(ut)[c] = v[q];
+        for (int q = 0; q < 4 * PL; ++q) {
+            const int w = lw + NLW * q;
+            int f = lane + 64 * w;
+            f = f < nf ? f : nf - 1;
+            const int r = f % TILE_E;
+            dma4(a.u + (int64_t)(f / TILE_E) * a.E + e0 + (r < nvalid ? r : nvalid - 1),
+                 slot + 64 * w);
+        }
+        return false;
     }
 }
 
@@ -385,10 +487,15 @@ __device__ __forceinline__ void stage_d(const ContractArgs& a, unsigned char* ld
         for (int b = 0; b < U; ++b) {
             int64_t idx = base + tid + (int64_t)NTHREADS * b;
             idx = idx < nfrag ? idx : nfrag - 1;  // clamped: the duplicate is not stored
-            const int l = (int)(idx & 63);
             const int rest = (int)(idx >> 6);
-            const int s = rest % a.nsteps;
+            const int sb = rest % a.nsteps;  // 64-float block of the pair
             const int p = rest / a.nsteps;
+            int l = (int)(idx & 63), s = sb;
+            if (PREC == LPX_FP32 && sb < (a.nsteps & ~3)) {  // lane-major quad block
+                const int w = (sb & 3) * 64 + l;
+                l = w >> 2;
+                s = (sb & ~3) + (w & 3);
+            }
             const int k = p / a.nt;
             const int t = p - k * a.nt;
             f[b] = d_frag_global<PREC>(a, k, t, s, l);
@@ -441,6 +548,107 @@ __device__ __forceinline__ void store_pairs(const ContractArgs& a, const f4 (&ac
     }
 }
 
+// Staged output tile (prefetch bit 3).  Compute waves write their
+// accumulators to an LDS slot; store waves copy the slot to `out` with
+// contiguous 16-byte stores.
+//   element-major: slot float (k*TILE_E + r)*Np + i, so each k's part is
+//                  the contiguous run out[k][e0 .. e0+nvalid)[0 .. Np);
+//   DOF-major:     slot float (k*Np + i)*(TILE_E + 4) + r (rows padded by
+//                  4 floats against LDS bank conflicts); each (k, i) row is
+//                  the segment out[k][i][e0 .. e0+nvalid).
+template <int LAYOUT, int PMAX, int WPE, int TILE_E>
+__device__ __forceinline__ void stage_pairs(const ContractArgs& a, const f4 (&acc)[PMAX], int pc,
+                                            int row0, float* os, int lane) {
+    const int npairs = a.K * a.nt;
+#pragma unroll
+    for (int q = 0; q < PMAX; ++q) {
+        const int p = pc + q * WPE;
+        if (p >= npairs) continue;
+        const int k = p / a.nt, t = p - (p / a.nt) * a.nt;
+        if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
+            const int r = row0 + (lane & 15);
+            const int i0 = 16 * t + 4 * (lane >> 4);
+            float* dst = os + (k * TILE_E + r) * a.Np + i0;
+            if (a.np_vec) {
+                if (i0 < a.Np) *reinterpret_cast<f4*>(dst) = acc[q];
+            } else {
+#pragma unroll
+                for (int r2 = 0; r2 < 4; ++r2)
+                    if (i0 + r2 < a.Np) dst[r2] = acc[q][r2];
+            }
+        } else {
+            const int i = 16 * t + (lane & 15);
+            if (i < a.Np)
+                *reinterpret_cast<f4*>(os + (k * a.Np + i) * (TILE_E + 4) + row0 +
+                                       4 * (lane >> 4)) = acc[q];
+        }
+    }
+}
+
+// Store wave sw (of NSW) copies the staged tile at element e0 (nvalid
+// valid elements) from slot `os` to `out`.  Store waves issue no global
+// loads, so nothing ever waits for their stores.
+template <int LAYOUT, int TILE_E, int NSW>
+__device__ __forceinline__ void store_tile(const ContractArgs& a, const float* os, int64_t e0,
+                                           int nvalid, int sw, int lane) {
+    constexpr int U = 4;  // chunks read from LDS before their stores
+    constexpr int STRIDE = 64 * NSW;
+    if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
+        const int run = nvalid * a.Np;  // floats of one k
+        for (int k = 0; k < a.K; ++k) {
+            float* g = a.out + ((int64_t)k * a.E + e0) * a.Np;
+            const float* src = os + k * TILE_E * a.Np;
+            if (a.np_vec) {  // run % 4 == 0; g is 16-byte aligned
+                const int nch = run >> 2;
+                for (int c0 = 64 * sw + lane; c0 < nch; c0 += STRIDE * U) {
+                    f4 v[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int c = c0 + STRIDE * u;
+                        v[u] = reinterpret_cast<const f4*>(src)[c < nch ? c : nch - 1];
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int c = c0 + STRIDE * u;
+                        if (c < nch) reinterpret_cast<f4*>(g)[c] = v[u];
+                    }
+                }
+            } else {
+                for (int f = 64 * sw + lane; f < run; f += STRIDE) g[f] = src[f];
+            }
+        }
+    } else {
+        constexpr int CPR = TILE_E / 4;  // 16-byte chunks per row
+        constexpr int LDR = TILE_E + 4;  // padded slot row
+        const int rows = a.K * a.Np;
+        if (a.e_vec) {  // E % 4 == 0: nvalid % 4 == 0 and every row segment is aligned
+            const int nch = rows * CPR;
+            for (int c0 = 64 * sw + lane; c0 < nch; c0 += STRIDE * U) {
+                f4 v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    int c = c0 + STRIDE * u;
+                    c = c < nch ? c : nch - 1;
+                    v[u] = *reinterpret_cast<const f4*>(os + (c / CPR) * LDR + 4 * (c % CPR));
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int c = c0 + STRIDE * u;
+                    if (c < nch && 4 * (c % CPR) < nvalid)
+                        *reinterpret_cast<f4*>(a.out + (int64_t)(c / CPR) * a.E + e0 +
+                                               4 * (c % CPR)) = v[u];
+                }
+            }
+        } else {
+            const int n = rows * TILE_E;
+            for (int f = 64 * sw + lane; f < n; f += STRIDE) {
+                const int row = f / TILE_E, r = f % TILE_E;
+                if (r < nvalid) a.out[(int64_t)row * a.E + e0 + r] = os[row * LDR + r];
+            }
+        }
+    }
+}
+
 // One wave's share of a 16-element block starting at element eb0: the
 // (k, i-block) pairs p = part, part + WPE, ... (WPE waves share a block);
 // for each, the MFMA chain over the k-steps of j, then the write-back.
@@ -448,11 +656,14 @@ __device__ __forceinline__ void store_pairs(const ContractArgs& a, const f4 (&ac
 // staged tile `ut` at row `row0` (PF_U) or global memory.  The summation
 // order of every output depends only on PREC: all records of a precision
 // give bit-identical results.
-template <int PREC, int LAYOUT, int NTMAX, bool PF_D, bool PF_U, int TILE_E, int WPE, int UNROLL>
+template <int PREC, int LAYOUT, int NTMAX, bool PF_D, bool PF_U, int TILE_E, int WPE, int UNROLL,
+          bool PF_O = false>
 __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsigned char* lds,
                                               const float* ut, int row0, int64_t eb0, int part,
-                                              int lane) {
-    constexpr int PMAX = (3 * NTMAX + WPE - 1) / WPE;  // pairs held per wave
+                                              int lane, float* os = nullptr) {
+    // Pairs held per wave and chunk: a three-operator block's share, at
+    // most 6 (larger shares run in several chunks, re-reading u).
+    constexpr int PMAX = (3 * NTMAX + WPE - 1) / WPE < 6 ? (3 * NTMAX + WPE - 1) / WPE : 6;
     const int npairs = a.K * a.nt;
     const int64_t nfrag = (int64_t)npairs * a.nsteps * 64;
     for (int pc = part; pc < npairs; pc += WPE * PMAX) {
@@ -461,14 +672,15 @@ __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsig
 #pragma unroll
         for (int q = 0; q < PMAX; ++q) {
             acc[q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-            const int p = pc + q * WPE;
+            int p = pc + q * WPE;
+            p = p < npairs ? p : npairs - 1;  // clamped: a duplicate pair is loaded, never used
             pk[q] = p / a.nt;
             pt[q] = p - pk[q] * a.nt;
         }
         auto step = [&](int s) {
             Frag<PREC> uf;
             if constexpr (PF_U)
-                uf = u_frag_lds<PREC, LAYOUT, TILE_E>(ut, a.Np, a.np_vec, row0, s, lane);
+                uf = u_frag_lds<PREC, LAYOUT, TILE_E>(ut, a.Np, a.np_vec, row0, s, a.nsteps & ~3, lane);
             else
                 uf = u_frag_global<PREC, LAYOUT>(a, eb0, s, lane);
 #pragma unroll
@@ -488,12 +700,56 @@ __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsig
             }
         };
         int s = 0;
-        for (; s + UNROLL <= a.nsteps; s += UNROLL) {
+        if constexpr (PREC == LPX_FP32) {
+            // Whole quads: one 16-byte read per operand, then four MFMAs
+            // per pair; UNROLL counts quads.
+            auto quad = [&](int Q) {
+                f4 uq;
+                if constexpr (PF_U)
+                    uq = u_quad_lds<LAYOUT, TILE_E>(ut, a.Np, a.np_vec, row0, Q, lane);
+                else
+                    uq = u_quad_global<LAYOUT>(a, eb0, Q, lane);
+                f4 dq[PMAX];
 #pragma unroll
-            for (int uu = 0; uu < UNROLL; ++uu) step(s + uu);
+                for (int q = 0; q < PMAX; ++q) {
+                    if constexpr (PF_D)
+                        dq[q] = d_quad_lds(lds, pk[q] * a.nt + pt[q], Q, a.nsteps, lane);
+                    else
+                        dq[q] = d_quad_global(a, pk[q], pt[q], Q, lane);
+                }
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+#pragma unroll
+                    for (int q = 0; q < PMAX; ++q) {
+                        if (pc + q * WPE < npairs) {
+                            const Frag<PREC> df{dq[q][m]}, uf{uq[m]};
+                            if constexpr (LAYOUT == LPX_ELEMENT_MAJOR)
+                                acc[q] = mma(df, uf, acc[q]);
+                            else
+                                acc[q] = mma(uf, df, acc[q]);
+                        }
+                    }
+                }
+            };
+            const int nq = a.nsteps >> 2;
+            int Q = 0;
+            for (; Q + UNROLL <= nq; Q += UNROLL) {
+#pragma unroll
+                for (int uu = 0; uu < UNROLL; ++uu) quad(Q + uu);
+            }
+            for (; Q < nq; ++Q) quad(Q);
+            s = 4 * nq;
+        } else {
+            for (; s + UNROLL <= a.nsteps; s += UNROLL) {
+#pragma unroll
+                for (int uu = 0; uu < UNROLL; ++uu) step(s + uu);
+            }
         }
         for (; s < a.nsteps; ++s) step(s);
-        store_pairs<LAYOUT, PMAX, WPE>(a, acc, pc, eb0, lane);
+        if constexpr (PF_O)
+            stage_pairs<LAYOUT, PMAX, WPE, TILE_E>(a, acc, pc, row0, os, lane);
+        else
+            store_pairs<LAYOUT, PMAX, WPE>(a, acc, pc, eb0, lane);
     }
 }
 
@@ -523,24 +779,22 @@ __device__ __forceinline__ void load_dregs(const ContractArgs& a, int part, int 
     }
 }
 
-template <int PREC, int LAYOUT, int NTMAX, bool PF_U, int TILE_E, int WPE>
+template <int PREC, int LAYOUT, int NTMAX, bool PF_U, int TILE_E, int WPE, bool PF_O = false>
 __device__ __forceinline__ void block_compute_dreg(const ContractArgs& a,
                                                    const DRegs<PREC, NTMAX, WPE>& d,
                                                    const float* ut, int row0, int64_t eb0,
-                                                   int part, int lane) {
+                                                   int part, int lane, float* os = nullptr) {
     using DR = DRegs<PREC, NTMAX, WPE>;
     const int npairs = a.K * a.nt;
     f4 acc[DR::PMAX];
 #pragma unroll
     for (int q = 0; q < DR::PMAX; ++q) acc[q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int s = 0; s < DR::NS; ++s) {
-        if (s >= a.nsteps) break;  // uniform
-        Frag<PREC> uf;
-        if constexpr (PF_U)
-            uf = u_frag_lds<PREC, LAYOUT, TILE_E>(ut, a.Np, a.np_vec, row0, s, lane);
-        else
-            uf = u_frag_global<PREC, LAYOUT>(a, eb0, s, lane);
+    // Every u operand is read before the first MFMA, without branches
+    // (reads past the last step are in bounds and zero-selected), so the
+    // reads overlap one another and the wave waits once.  The MFMAs run to
+    // the compiled bound under uniform guards, with constant register
+    // indices throughout.
+    auto mma_all = [&](int s, const Frag<PREC>& uf) {
 #pragma unroll
         for (int q = 0; q < DR::PMAX; ++q) {
             if (part + q * WPE < npairs) {
@@ -550,20 +804,74 @@ __device__ __forceinline__ void block_compute_dreg(const ContractArgs& a,
                     acc[q] = mma(uf, d.f[q][s], acc[q]);
             }
         }
+    };
+    if constexpr (PREC == LPX_FP32) {
+        constexpr int NQ = DR::NS / 4;  // quads of the compiled bound
+        const int nq = a.nsteps >> 2;
+        const int ntail = a.nsteps - 4 * nq;  // 0..3 steps after the last quad
+        f4 uq[NQ];
+        Frag<PREC> ut3[3];
+#pragma unroll
+        for (int Q = 0; Q < NQ; ++Q) {
+            if constexpr (PF_U)
+                uq[Q] = u_quad_lds<LAYOUT, TILE_E>(ut, a.Np, a.np_vec, row0, Q, lane);
+            else
+                uq[Q] = u_quad_global<LAYOUT>(a, eb0, Q, lane);
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            if constexpr (PF_U)
+                ut3[m] = u_frag_lds<PREC, LAYOUT, TILE_E>(ut, a.Np, a.np_vec, row0, 4 * nq + m,
+                                                          4 * nq, lane);
+            else
+                ut3[m] = u_frag_global<PREC, LAYOUT>(a, eb0, 4 * nq + m, lane);
+        }
+#pragma unroll
+        for (int Q = 0; Q < NQ; ++Q) {
+            if (Q < nq) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m) mma_all(4 * Q + m, Frag<PREC>{uq[Q][m]});
+            }
+        }
+        // tail steps 4*nq + m: one branch per possible nq keeps the
+        // register index of D constant
+#pragma unroll
+        for (int Q0 = 0; Q0 < NQ; ++Q0) {
+            if (nq == Q0) {
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+                    if (m < ntail && 4 * Q0 + m < DR::NS) mma_all(4 * Q0 + m, ut3[m]);
+            }
+        }
+    } else {
+        Frag<PREC> uf[DR::NS];
+#pragma unroll
+        for (int s = 0; s < DR::NS; ++s) {
+            if constexpr (PF_U)
+                uf[s] = u_frag_lds<PREC, LAYOUT, TILE_E>(ut, a.Np, a.np_vec, row0, s, 0, lane);
+            else
+                uf[s] = u_frag_global<PREC, LAYOUT>(a, eb0, s, lane);
+        }
+#pragma unroll
+        for (int s = 0; s < DR::NS; ++s)
+            if (s < a.nsteps) mma_all(s, uf[s]);
     }
-    store_pairs<LAYOUT, DR::PMAX, WPE>(a, acc, part, eb0, lane);
+    if constexpr (PF_O)
+        stage_pairs<LAYOUT, DR::PMAX, WPE, TILE_E>(a, acc, part, row0, os, lane);
+    else
+        store_pairs<LAYOUT, DR::PMAX, WPE>(a, acc, part, eb0, lane);
 }
 
 // ------------------------------------------------------------ the kernel
-// Work-group shape.  Without a staged u tile: four waves per 16-element
-// block, splitting its (k, i-block) pairs.  With one: min(4 * TILE_E/16, 8)
-// compute waves (so WPE = that / (TILE_E/16) per block) plus NLW loader
-// waves that keep the next tile in registers.
+// Work-group shape (contract_shape).  Without a staged u tile: four waves
+// per 16-element block, splitting its (k, i-block) pairs.  With one:
+// NCW = min(4 * TILE_E/16, 8) compute waves (WPE per block), NLW loader
+// waves and, with a staged output tile, NSW store waves.
 template <int TILE_E, int NTMAX, int PREFETCH>
 struct Shape {
-    static constexpr bool PF_U = (PREFETCH & 2) != 0;
     static constexpr ContractShape CS = contract_shape(TILE_E, NTMAX, PREFETCH);
-    static constexpr int NCW = CS.ncw, WPE = CS.wpe, NLW = CS.nlw, THREADS = CS.threads;
+    static constexpr int NCW = CS.ncw, WPE = CS.wpe, NLW = CS.nlw, NSW = CS.nsw,
+                         THREADS = CS.threads;
 };
 
 template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PREFETCH, int UNROLL>
@@ -572,8 +880,9 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
     extern __shared__ __align__(16) unsigned char lds[];
     using S = Shape<TILE_E, NTMAX, PREFETCH>;
     constexpr bool PF_D = (PREFETCH & 1) != 0;
-    constexpr bool PF_U = S::PF_U;
+    constexpr bool PF_U = (PREFETCH & 2) != 0;
     constexpr bool D_REG = (PREFETCH & 4) != 0;
+    constexpr bool PF_O = (PREFETCH & 8) != 0;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -581,7 +890,7 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
     const int64_t nfrag = (int64_t)a.K * a.nt * a.nsteps * 64;
     float* ring = reinterpret_cast<float*>(
         lds + (PF_D ? nfrag * Lds<PREC>::DFRAG_BYTES * Lds<PREC>::PLANES : 0));
-    const int slot_floats = a.ldu;  // ring slot stride (floats)
+    float* oring = ring + 4 * a.ldu;  // staged output slots follow the u slots
 
     if constexpr (PF_D) stage_d<PREC, S::THREADS>(a, lds, tid);
 
@@ -606,39 +915,70 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
             }
         }
     } else {
+        // The work-group's n-th tile is blockIdx.x + n * gridDim.x, n < nmine.
+        // Every wave runs `niter` iterations of one barrier each (one more
+        // than nmine when store waves trail the compute waves by a tile):
+        //   iteration n: loaders start tile n+3 into u slot (n+3)&3 and wait
+        //   for tile n+1; compute waves work on tile n from u slot n&3
+        //   (writing output slot n&1 when staged); store waves copy output
+        //   slot (n-1)&1 to global memory.
+        // Each slot is rewritten only in an iteration after the one that
+        // read it, so the barrier ending each iteration orders every access.
+        const int64_t t0 = blockIdx.x, g = gridDim.x;
+        const int64_t nmine = t0 < a.ntiles ? (a.ntiles - 1 - t0) / g + 1 : 0;
+        const int64_t niter = PF_O ? nmine + 1 : nmine;
         auto nvalid_of = [&](int64_t tile) {
             const int64_t rest = a.E - tile * TILE_E;
             return (int)(rest < TILE_E ? rest : TILE_E);
         };
-        // Loader and compute waves run separate loops with one barrier per
-        // tile each, so their registers are never live at the same time.
-        if (wave >= S::NCW) {
-            const int lw = wave - S::NCW;
-            f4 held[Loader<TILE_E, NTMAX, S::NLW>::PER_LANE];
-            int64_t tile = blockIdx.x;
-            if (tile < a.ntiles) {
-                // Prologue: tile 0 into slot 0, tile 1 held in registers.
-                loader_fetch<LAYOUT, TILE_E, NTMAX, S::NLW>(a, tile * TILE_E, nvalid_of(tile),
-                                                             lw, lane, held);
-                loader_put<LAYOUT, TILE_E, NTMAX, S::NLW>(a, ring, nvalid_of(tile), lw, lane,
-                                                           held);
-                const int64_t t1 = tile + gridDim.x;
-                if (t1 < a.ntiles)
-                    loader_fetch<LAYOUT, TILE_E, NTMAX, S::NLW>(a, t1 * TILE_E, nvalid_of(t1),
-                                                                 lw, lane, held);
-            }
-            __syncthreads();
-            for (int n = 0; tile < a.ntiles; ++n, tile += gridDim.x) {
-                const int64_t t1 = tile + gridDim.x, t2 = t1 + gridDim.x;
-                if (t1 < a.ntiles) {
-                    // slot ^ 1 was last read in the previous iteration
-                    loader_put<LAYOUT, TILE_E, NTMAX, S::NLW>(
-                        a, ring + ((n & 1) ^ 1) * slot_floats, nvalid_of(t1), lw, lane, held);
-                    if (t2 < a.ntiles)
-                        loader_fetch<LAYOUT, TILE_E, NTMAX, S::NLW>(a, t2 * TILE_E,
-                                                                     nvalid_of(t2), lw, lane, held);
+        if (wave >= S::NCW + S::NLW) {
+            if constexpr (PF_O) {
+                const int sw = wave - S::NCW - S::NLW;
+                __syncthreads();
+                for (int64_t n = 0; n < niter; ++n) {
+                    if (n >= 1) {
+                        const int64_t tile = t0 + (n - 1) * g;
+                        store_tile<LAYOUT, TILE_E, S::NSW>(a, oring + ((n - 1) & 1) * a.ldo,
+                                                           tile * TILE_E, nvalid_of(tile), sw,
+                                                           lane);
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();  // slot read by the compute waves; slot ^ 1 filled
+            }
+        } else if (wave >= S::NCW) {
+            // Three tiles in flight: at iteration n the loader issues tile
+            // n+3 into slot (n+3)&3 (read by the compute waves in iteration
+            // n-1), then waits until tile n+1 has landed.  The waits and
+            // barriers are explicit: nothing else here touches LDS.
+            constexpr int PL = Loader<TILE_E, NTMAX, S::NLW>::PER_LANE;
+            const int lw = wave - S::NCW;
+            unsigned regular = 0xf;  // bit s: the tile in slot s was regular
+            auto issue = [&](int64_t n) {
+                const int64_t tile = t0 + n * g;
+                const bool r = loader_issue<LAYOUT, TILE_E, NTMAX, S::NLW>(
+                    a, ring + (n & 3) * a.ldu, tile * TILE_E, nvalid_of(tile), lw, lane);
+                regular = (regular & ~(1u << (n & 3))) | ((unsigned)r << (n & 3));
+            };
+            // Wait for tile m: the tiles after it that are in flight must all
+            // be regular for a partial wait; otherwise wait for everything.
+            auto wait_for = [&](int64_t m) {
+                const int64_t later = (nmine - 1 - m) < 2 ? (nmine - 1 - m) : 2;
+                const bool reg = (later < 1 || ((regular >> ((m + 1) & 3)) & 1)) &&
+                                 (later < 2 || ((regular >> ((m + 2) & 3)) & 1));
+                if (reg && later == 2)
+                    __builtin_amdgcn_s_waitcnt(vmcnt_imm(2 * PL));
+                else if (reg && later == 1)
+                    __builtin_amdgcn_s_waitcnt(vmcnt_imm(PL));
+                else
+                    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+            };
+            for (int64_t n = 0; n < 3 && n < nmine; ++n) issue(n);
+            if (nmine > 0) wait_for(0);
+            __builtin_amdgcn_s_barrier();
+            for (int64_t n = 0; n < niter; ++n) {
+                if (n + 3 < nmine) issue(n + 3);
+                if (n + 1 < nmine) wait_for(n + 1);
+                __builtin_amdgcn_s_barrier();
             }
         } else {
             const int eblk = wave / S::WPE, part = wave % S::WPE;
@@ -646,22 +986,23 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
                 DRegs<PREC, NTMAX, S::WPE> d;
                 load_dregs<PREC, NTMAX, S::WPE>(a, part, lane, d);
                 __syncthreads();
-                int64_t tile = blockIdx.x;
-                for (int n = 0; tile < a.ntiles; ++n, tile += gridDim.x) {
-                    if (16 * eblk < nvalid_of(tile))
-                        block_compute_dreg<PREC, LAYOUT, NTMAX, true, TILE_E, S::WPE>(
-                            a, d, ring + (n & 1) * slot_floats, 16 * eblk,
-                            tile * TILE_E + 16 * eblk, part, lane);
+                for (int64_t n = 0; n < niter; ++n) {
+                    const int64_t tile = t0 + n * g;
+                    if (n < nmine && 16 * eblk < nvalid_of(tile))
+                        block_compute_dreg<PREC, LAYOUT, NTMAX, true, TILE_E, S::WPE, PF_O>(
+                            a, d, ring + (n & 3) * a.ldu, 16 * eblk, tile * TILE_E + 16 * eblk,
+                            part, lane, oring + (n & 1) * a.ldo);
                     __syncthreads();
                 }
             } else {
                 __syncthreads();
-                int64_t tile = blockIdx.x;
-                for (int n = 0; tile < a.ntiles; ++n, tile += gridDim.x) {
-                    if (16 * eblk < nvalid_of(tile))
-                        block_compute<PREC, LAYOUT, NTMAX, PF_D, true, TILE_E, S::WPE, UNROLL>(
-                            a, lds, ring + (n & 1) * slot_floats, 16 * eblk,
-                            tile * TILE_E + 16 * eblk, part, lane);
+                for (int64_t n = 0; n < niter; ++n) {
+                    const int64_t tile = t0 + n * g;
+                    if (n < nmine && 16 * eblk < nvalid_of(tile))
+                        block_compute<PREC, LAYOUT, NTMAX, PF_D, true, TILE_E, S::WPE, UNROLL,
+                                      PF_O>(a, lds, ring + (n & 3) * a.ldu, 16 * eblk,
+                                            tile * TILE_E + 16 * eblk, part, lane,
+                                            oring + (n & 1) * a.ldo);
                     __syncthreads();
                 }
             }

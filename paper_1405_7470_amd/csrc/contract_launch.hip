@@ -5,22 +5,24 @@
 #include <mutex>
 #include <utility>
 
-#include "contract_kernels.h"
+#include "contract_dispatch.h"
 
 namespace lpx {
-
-using ContractFn = void (*)(kern::ContractArgs);
-ContractFn contract_kernel_fp32(int layout, int ntmax, int tile, int pf, int un);
-ContractFn contract_kernel_bf16(int layout, int ntmax, int tile, int pf, int un);
-ContractFn contract_kernel_bf16x3(int layout, int ntmax, int tile, int pf, int un);
 
 namespace {
 
 ContractFn select(const ContractGeom& g) {
+    const bool em = g.layout == LPX_ELEMENT_MAJOR;
     switch (g.prec) {
-        case LPX_FP32: return contract_kernel_fp32(g.layout, g.ntmax, g.tile_e, g.prefetch, g.unroll);
-        case LPX_BF16: return contract_kernel_bf16(g.layout, g.ntmax, g.tile_e, g.prefetch, g.unroll);
-        default: return contract_kernel_bf16x3(g.layout, g.ntmax, g.tile_e, g.prefetch, g.unroll);
+        case LPX_FP32:
+            return em ? contract_kernel_fp32_em(g.ntmax, g.tile_e, g.prefetch, g.unroll)
+                      : contract_kernel_fp32_dm(g.ntmax, g.tile_e, g.prefetch, g.unroll);
+        case LPX_BF16:
+            return em ? contract_kernel_bf16_em(g.ntmax, g.tile_e, g.prefetch, g.unroll)
+                      : contract_kernel_bf16_dm(g.ntmax, g.tile_e, g.prefetch, g.unroll);
+        default:
+            return em ? contract_kernel_bf16x3_em(g.ntmax, g.tile_e, g.prefetch, g.unroll)
+                      : contract_kernel_bf16x3_dm(g.ntmax, g.tile_e, g.prefetch, g.unroll);
     }
 }
 
@@ -84,6 +86,7 @@ lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g, vo
     a.nt = g.nt;
     a.nsteps = g.nsteps;
     a.ldu = g.ldu;
+    a.ldo = g.ldo;
     a.np_vec = (c.Np % 4) == 0;
     a.e_vec = (c.E % 4) == 0;
     void* args[] = {&a};

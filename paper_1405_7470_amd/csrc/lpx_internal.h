@@ -30,17 +30,27 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // on it through this one function).  Without a staged u tile (prefetch bit
 // 1 clear): four waves per 16-element block, splitting its (k, i-block)
 // pairs.  With one: min(4 * tile_e/16, 8) compute waves, wpe of them per
-// block, plus nlw loader waves (1, or tile_e * ntmax / 256 when larger)
-// that keep the next u tile in registers.
+// block, plus nlw loader waves (1, or tile_e * ntmax / 128 when larger,
+// so that a loader wave loads at most 8 16-byte chunks per lane and tile),
+// and with a staged output tile (bit 3) four store waves: the write-back
+// is three quarters of the traffic and needs that many waves issuing
+// stores to keep HBM busy.
 struct ContractShape {
-    int ncw, wpe, nlw, threads;
+    int ncw, wpe, nlw, nsw, threads;
 };
 constexpr ContractShape contract_shape(int tile_e, int ntmax, int prefetch) {
     const bool pf_u = (prefetch & 2) != 0;
+    const bool pf_o = (prefetch & 8) != 0;
     const int nb = tile_e / 16;
     const int ncw = pf_u ? (4 * nb < 8 ? 4 * nb : 8) : 4 * nb;
-    const int nlw = pf_u ? (tile_e * ntmax / 256 > 1 ? tile_e * ntmax / 256 : 1) : 0;
-    return ContractShape{ncw, ncw / nb, nlw, 64 * (ncw + nlw)};
+    const int nlw = pf_u ? (tile_e * ntmax / 128 > 1 ? tile_e * ntmax / 128 : 1) : 0;
+    const int nsw = pf_o ? 4 : 0;
+    return ContractShape{ncw, ncw / nb, nlw, nsw, 64 * (ncw + nlw + nsw)};
+}
+// 16-byte chunks one loader wave loads per u tile (nlw loader waves; a
+// tile holds at most tile_e * 16 * ntmax floats).
+constexpr int loader_per_lane(int tile_e, int ntmax, int nlw) {
+    return (tile_e * 16 * ntmax / 4 + 64 * nlw - 1) / (64 * nlw);
 }
 inline int64_t ceil_div(int64_t x, int64_t m) { return (x + m - 1) / m; }
 
@@ -55,6 +65,7 @@ struct ContractGeom {
     int ntmax = 2;     // compiled bound on nt: 2, 4 or 8
     int nsteps = 0;    // MFMA k-steps: ceil(Np / kstep)
     int ldu = 0;       // LDS ring slot stride of a staged u tile (floats)
+    int ldo = 0;       // LDS ring slot stride of a staged output tile (floats)
     int64_t ntiles = 0;
     int64_t nfrag = 0;     // staged D fragments: K*nt*nsteps*64 lanes
     int64_t lds_bytes = 0; // dynamic LDS per work-group (0 if no prefetch)

@@ -20,7 +20,7 @@ namespace {
 
 constexpr char kMagic[8] = {'L', 'P', 'X', 'P', 'I', 'C', 'K', '1'};
 constexpr uint32_t kVersion = 1;
-constexpr int kMaxCand = 64;
+constexpr int kMaxCand = LPX_MAX_RECORDS;
 
 uint32_t fnv1a(const unsigned char* p, size_t n) {
     uint32_t h = 2166136261u;
@@ -49,7 +49,7 @@ lpx_status features(const lpx_problem& p, const lpx_record& r, float* f) {
     f[3] = (float)p.layout;
     f[4] = (float)std::log2((double)r.tile_e);
     f[5] = (float)((r.prefetch & 4) ? 2 : (r.prefetch & 1));  // D: global, LDS, registers
-    f[6] = (float)((r.prefetch >> 1) & 1);
+    f[6] = (float)(((r.prefetch >> 1) & 1) + ((r.prefetch >> 3) & 1));  // u, u + output staged
     f[7] = (float)std::log2((double)r.unroll);
     f[8] = (float)r.precision;
     f[9] = (float)((pad16 - p.Np) / pad16);

@@ -88,9 +88,9 @@ lpx_status lpx_autotune(const lpx_contract_desc* c, int32_t precision, int32_t w
         lpx_status s = lpx_contract_validate(c, &def);
         if (s != LPX_OK) return s;
         lpx_problem p{c->K, c->Np, c->E, c->layout, precision};
-        lpx_record recs[64];  // >= the 54 candidates
+        lpx_record recs[LPX_MAX_RECORDS];
         int32_t nrec = 0;
-        s = lpx_record_enumerate(&p, recs, 64, &nrec);
+        s = lpx_record_enumerate(&p, recs, LPX_MAX_RECORDS, &nrec);
         if (s != LPX_OK) return s;
         if (n) *n = nrec;
         std::vector<float> med(nrec, INFINITY);

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liblpx.so")
 
 # status codes (include/lpx.h)
 OK = 0
+MAX_RECORDS = 81  # LPX_MAX_RECORDS
 ERR_INVALID_ARG = 1
 ERR_UNSUPPORTED = 2
 ERR_ASSUMPTION = 3
@@ -333,13 +334,13 @@ def autotune(D, u, out=None, layout="em", precision="fp32", warmup=2, reps=7, st
         out = torch.empty(out_shape(K, Np, E, layout), dtype=torch.float32, device=u.device)
     desc = make_desc(D, u, out, layout)
     best = Record()
-    times = (ctypes.c_float * 64)()
+    times = (ctypes.c_float * MAX_RECORDS)()
     n = ctypes.c_int32()
     fptr = ctypes.c_void_p(flush.data_ptr()) if flush is not None else None
     fbytes = flush.numel() * flush.element_size() if flush is not None else 0
     _check(lib().lpx_autotune(ctypes.byref(desc), PRECISION[precision], warmup, reps,
                               fptr, fbytes, _stream_handle(stream), ctypes.byref(best), times,
-                              64, ctypes.byref(n)))
+                              MAX_RECORDS, ctypes.byref(n)))
     return best, [times[i] for i in range(n.value)]
 
 

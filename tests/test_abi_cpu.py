@@ -51,15 +51,16 @@ def test_default_record_is_the_untuned_variant():
 
 def test_enumeration_canonical_order_and_truncation():
     recs = lpx.enumerate_records(3, 56, 1 << 20, "em", "bf16x3")
-    assert len(recs) == 54
+    assert len(recs) == 81 == lpx.MAX_RECORDS
     keys = [(r.tile_e, r.prefetch, r.unroll) for r in recs]
-    assert keys == [(t, p, u) for t in (16, 32, 64) for p in (0, 1, 2, 3, 4, 6) for u in (1, 2, 4)]
+    assert keys == [(t, p, u) for t in (16, 32, 64) for p in (0, 1, 2, 3, 4, 6, 10, 11, 14)
+                    for u in (1, 2, 4)]
     assert all(lpx.PRECISION_NAME[r.precision] == "bf16x3" for r in recs)
     p = lpx.problem(3, 56, 1 << 20, "em", "fp32")
     arr = (lpx.Record * 4)()
     n = ctypes.c_int32()
     assert lpx.lib().lpx_record_enumerate(ctypes.byref(p), arr, 4, ctypes.byref(n)) == 0
-    assert n.value == 54 and arr[3].unroll == 1 and arr[3].prefetch == 1
+    assert n.value == 81 and arr[3].unroll == 1 and arr[3].prefetch == 1
 
 
 def test_describe():
@@ -69,7 +70,7 @@ def test_describe():
 
 @pytest.mark.parametrize("field,value", [
     ("version", 2), ("precision", 3), ("tile_e", 8), ("tile_e", 128), ("prefetch", 5),
-    ("prefetch", 7),
+    ("prefetch", 7), ("prefetch", 8), ("prefetch", 9), ("prefetch", 12), ("prefetch", 15),
     ("unroll", 3), ("assume_tile_divides", 2), ("reserved1", 1)])
 def test_malformed_records_rejected(field, value):
     r = lpx.default_record()
@@ -92,7 +93,10 @@ def status(d, rec=None):
 def test_validate_accepts_well_formed():
     assert status(desc()) == lpx.OK
     for r in lpx.enumerate_records(3, 56, 1000, "dm", "bf16x3"):
-        want = lpx.ERR_UNSUPPORTED if (r.tile_e, r.prefetch) == (64, 6) else lpx.OK
+        # (64, 6/14): two waves per block cannot hold D in registers;
+        # (64, 11): D fragments + u ring + DOF-major output ring exceed LDS
+        bad = ((64, 6), (64, 14), (64, 11))
+        want = lpx.ERR_UNSUPPORTED if (r.tile_e, r.prefetch) in bad else lpx.OK
         assert status(desc(layout=1), r) == want, lpx.describe(r)
 
 
@@ -141,7 +145,7 @@ def test_register_d_limits():
     assert status(desc(Np=56), lpx.record("fp32", 64, 6, 1)) == lpx.ERR_UNSUPPORTED
     assert status(desc(Np=56), lpx.record("fp32", 64, 4, 1)) == lpx.OK
     s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", lpx.record("fp32", 32, 6, 1))
-    assert s == lpx.OK and b == 2 * (32 * 64 + 32) * 4  # only the u ring
+    assert s == lpx.OK and b == 4 * (32 * 64 + 32) * 4  # only the u ring
 
 
 def test_lds_budget():
@@ -151,18 +155,33 @@ def test_lds_budget():
     assert status(desc(Np=128), r) == lpx.ERR_UNSUPPORTED
     s, b = lpx.lds_bytes(3, 128, 4096, "em", r)
     assert s == lpx.ERR_UNSUPPORTED and b == 3 * 8 * 32 * 64 * 4
-    # bit 1 alone stages only u: a two-slot ring, each slot a raw tile copy
+    # bit 1 alone stages only u: a four-slot ring, each slot a raw tile copy
     # with room for padding columns: 64 * 128 + 32 floats
     s, b = lpx.lds_bytes(3, 128, 4096, "em", lpx.record("fp32", 64, 2, 1))
-    assert s == lpx.OK and b == 2 * (64 * 128 + 32) * 4
-    # the full-scale shape fits both: D 3*4*14*64*4 bytes + ring 2*(64*64+32)*4
+    assert s == lpx.OK and b == 4 * (64 * 128 + 32) * 4
+    # Np = 72 needs only 64 * 96 + 32 floats of tile, but the loader waves
+    # write whole rounds of 64 chunks each: 4 waves * 8 rounds * 256 floats
+    s, b = lpx.lds_bytes(3, 72, 4096, "em", lpx.record("fp32", 64, 2, 1))
+    assert s == lpx.OK and b == 4 * (4 * 8 * 256) * 4
+    # the full-scale shape fits both: D 3*4*14*64*4 bytes + ring 4*(64*64+32)*4
     s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", lpx.record("fp32", 64, 3, 1))
-    assert s == lpx.OK and b == 3 * 4 * 14 * 64 * 4 + 2 * (64 * 64 + 32) * 4
+    assert s == lpx.OK and b == 3 * 4 * 14 * 64 * 4 + 4 * (64 * 64 + 32) * 4
     # bf16x3: two bf16 planes of D fragments (16 B per lane each)
     s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", lpx.record("bf16x3", 32, 3, 1))
-    assert s == lpx.OK and b == 3 * 4 * 2 * 64 * 32 + 2 * (32 * 64 + 32) * 4
+    assert s == lpx.OK and b == 3 * 4 * 2 * 64 * 32 + 4 * (32 * 64 + 32) * 4
     s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", lpx.record("fp32", 64, 0, 1))
     assert s == lpx.OK and b == 0
+    # bit 3 adds a two-slot output ring: element-major K*tile_e*Np floats per
+    # slot, DOF-major K*Np rows of tile_e + 4 floats
+    s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", lpx.record("fp32", 32, 14, 1))
+    assert s == lpx.OK and b == 4 * (32 * 64 + 32) * 4 + 2 * 3 * 32 * 56 * 4
+    s, b = lpx.lds_bytes(3, 56, 1 << 20, "dm", lpx.record("bf16x3", 32, 11, 1))
+    assert s == lpx.OK and b == (3 * 4 * 2 * 64 * 32 + 4 * (32 * 64 + 32) * 4
+                                 + 2 * 3 * 56 * 36 * 4)
+    # K = 8 at Np = 120 with a 64-element tile: the output ring alone needs
+    # 2*8*64*120*4 bytes
+    s, b = lpx.lds_bytes(8, 120, 4096, "em", lpx.record("fp32", 64, 10, 1))
+    assert s == lpx.ERR_UNSUPPORTED
 
 
 def test_null_descriptor_and_split_args():

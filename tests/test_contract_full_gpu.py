@@ -22,7 +22,8 @@ def test_full_scale_sampled(layout):
     for precision in ("fp32", "bf16x3"):
         for rec in (lpx.default_record(precision), lpx.record(precision, 64, 1, 2),
                     lpx.record(precision, 32, 3, 4), lpx.record(precision, 16, 2, 1),
-                    lpx.record(precision, 32, 6, 1), lpx.record(precision, 64, 4, 1)):
+                    lpx.record(precision, 32, 6, 1), lpx.record(precision, 64, 4, 1),
+                    lpx.record(precision, 32, 14, 1), lpx.record(precision, 64, 10, 4)):
             print(f"case: full {layout} {lpx.describe(rec)}", flush=True)
             out = lpx.contract(Dd, ud, layout=layout, record=rec)
             torch.cuda.synchronize()

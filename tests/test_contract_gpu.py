@@ -60,7 +60,7 @@ def test_edge_shapes(precision, layout):
               (120, 31), (128, 70)]
     recs = [lpx.record(precision, t, p, un) for (t, p, un) in
             ((16, 0, 1), (64, 0, 4), (32, 1, 2), (64, 3, 1), (16, 2, 4), (32, 4, 1),
-             (32, 6, 1))]
+             (32, 6, 1), (32, 10, 2), (64, 11, 1), (16, 14, 1))]
     for Np, E in shapes:
         D, u = inputs.contraction_inputs(2, Np, E, seed=E, layout=layout)
         for rec in recs:
@@ -69,6 +69,35 @@ def test_edge_shapes(precision, layout):
             print(f"case: edge {precision} {layout} Np={Np} E={E} {lpx.describe(rec)}", flush=True)
             out = run(D, u, layout, rec)
             check_against_oracle(D, u, as_em(out, layout), layout, precision)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_many_tiles_per_work_group(layout):
+    """E large enough that every work-group walks several tiles (the
+    staged pipelines' steady state and drain) with a ragged last tile.  All
+    records of a precision sum in the same order, so every record must match
+    the untuned default bit for bit; the default is checked against the
+    oracle on sampled elements."""
+    E = 200_003
+    rng = np.random.default_rng(1)
+    for Np in (20, 56, 84):
+        D, u = inputs.contraction_inputs(3, Np, E, seed=Np, layout=layout)
+        Dd, ud = to_dev(D), to_dev(u)
+        for precision in PRECS:
+            ref = lpx.contract(Dd, ud, layout=layout, record=lpx.default_record(precision))
+            torch.cuda.synchronize()
+            for s0 in [0, E - 51] + [int(x) for x in rng.integers(0, E - 51, 3)]:
+                chunk = ref[:, s0:s0 + 51, :] if layout == "em" else ref[:, :, s0:s0 + 51]
+                check_against_oracle(D, u, as_em(chunk, layout), layout, precision, e0=s0)
+            for rec in lpx.enumerate_records(3, Np, E, layout, precision):
+                if not rec.prefetch & 2 or not supported(3, Np, E, layout, rec):
+                    continue
+                print(f"case: many-tiles {precision} {layout} Np={Np} {lpx.describe(rec)}",
+                      flush=True)
+                out = lpx.contract(Dd, ud, layout=layout, record=rec)
+                assert torch.equal(out, ref), lpx.describe(rec)
+                del out
+            del ref
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
