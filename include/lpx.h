@@ -88,8 +88,9 @@ typedef int32_t lpx_status;
  *              16, 32 or 64 elements per work-group tile.  Inside a tile,
  *              e is split again by 16 (the MFMA column block) and i by 16
  *              (the MFMA row block); each 16-element block has four wave64s
- *              that split its (k, i-block) pairs, so a work-group has
- *              4 * tile_e / 16 wavefronts.
+ *              that split its (k, i-block) pairs (with a staged u tile,
+ *              at most eight compute waves per work-group, each taking
+ *              tile_e / 32 blocks of a 64-element tile).
  *   prefetch : storage of the operands (add_prefetch / precompute, sec.
  *              2.4.4), a bit set from {0,1,2,3,4,6,10,11,14}:
  *              bit 0: all of D is staged in LDS once per work-group, in
@@ -99,10 +100,9 @@ typedef int32_t lpx_status;
  *              work-group barrier per tile);
  *              bit 2: D is precomputed into private memory -- each wave
  *              keeps the D fragments of its own (k, i-block) pairs in
- *              registers for the whole kernel (Np <= 64, K*ceil(Np/16) <=
- *              12, and tile_e < 64 when bit 1 is set; else
- *              LPX_ERR_UNSUPPORTED; unroll does not apply, the k-step
- *              loop is fully unrolled);
+ *              registers for the whole kernel (Np <= 64 and K*ceil(Np/16)
+ *              <= 12, else LPX_ERR_UNSUPPORTED; unroll does not apply, the
+ *              k-step loop is fully unrolled);
  *              bit 3 (needs bit 1): each output tile is staged in LDS and
  *              written back by dedicated store waves with contiguous
  *              16-byte stores one tile behind the compute waves, which then

@@ -111,9 +111,9 @@ lpx_status contract_geometry(int K, int Np, int64_t E, int layout,
         const int pmax = (3 * g->ntmax + cs.wpe - 1) / cs.wpe;
         if (g->ntmax > 4 || cs.wpe != 4 || (int64_t)K * g->nt > (int64_t)cs.wpe * pmax)
             return set_error(LPX_ERR_UNSUPPORTED,
-                             "prefetch=%u (D in registers) needs Np <= 64, K*ceil(Np/16) <= %d "
-                             "and tile_e < 64 when u is staged (K=%d Np=%d tile_e=%u)",
-                             r.prefetch, cs.wpe * pmax, K, Np, r.tile_e);
+                             "prefetch=%u (D in registers) needs Np <= 64 and K*ceil(Np/16) <= %d "
+                             "(K=%d Np=%d)",
+                             r.prefetch, cs.wpe * pmax, K, Np);
     }
     g->lds_bytes = 0;
     if (r.prefetch) {

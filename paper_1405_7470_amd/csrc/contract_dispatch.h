@@ -36,14 +36,12 @@ ContractFn by_prefetch(int pf, int un) {
         case 11: return by_unroll<PREC, LAYOUT, NTMAX, TILE_E, 11>(un);
         default: break;
     }
-    // D in registers: built only where the fragments fit (Np <= 64, four
-    // waves per block); the unroll knob does not apply (fully unrolled).
+    // D in registers: built only where the fragments fit (Np <= 64); the
+    // unroll knob does not apply (fully unrolled).
     if constexpr (NTMAX <= 4) {
         if (pf == 4) return fn<PREC, LAYOUT, NTMAX, TILE_E, 4, 1>();
-        if constexpr (contract_shape(TILE_E, NTMAX, 6).wpe == 4) {
-            if (pf == 6) return fn<PREC, LAYOUT, NTMAX, TILE_E, 6, 1>();
-            if (pf == 14) return fn<PREC, LAYOUT, NTMAX, TILE_E, 14, 1>();
-        }
+        if (pf == 6) return fn<PREC, LAYOUT, NTMAX, TILE_E, 6, 1>();
+        if (pf == 14) return fn<PREC, LAYOUT, NTMAX, TILE_E, 14, 1>();
     }
     return nullptr;
 }

@@ -683,20 +683,20 @@ __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsig
                 uf = u_frag_lds<PREC, LAYOUT, TILE_E>(ut, a.Np, a.np_vec, row0, s, a.nsteps & ~3, lane);
             else
                 uf = u_frag_global<PREC, LAYOUT>(a, eb0, s, lane);
+            // every held pair runs: a pair past the last one holds a clamped
+            // duplicate and is never stored (no branch between the MFMAs)
 #pragma unroll
             for (int q = 0; q < PMAX; ++q) {
-                const int p = pc + q * WPE;
-                if (p < npairs) {
-                    Frag<PREC> df;
-                    if constexpr (PF_D)
-                        df = d_frag_lds<PREC>(lds, nfrag, (p * a.nsteps + s) * 64 + lane);
-                    else
-                        df = d_frag_global<PREC>(a, pk[q], pt[q], s, lane);
-                    if constexpr (LAYOUT == LPX_ELEMENT_MAJOR)
-                        acc[q] = mma(df, uf, acc[q]);  // rows i, columns e
-                    else
-                        acc[q] = mma(uf, df, acc[q]);  // rows e, columns i
-                }
+                Frag<PREC> df;
+                if constexpr (PF_D)
+                    df = d_frag_lds<PREC>(lds, nfrag,
+                                          ((pk[q] * a.nt + pt[q]) * a.nsteps + s) * 64 + lane);
+                else
+                    df = d_frag_global<PREC>(a, pk[q], pt[q], s, lane);
+                if constexpr (LAYOUT == LPX_ELEMENT_MAJOR)
+                    acc[q] = mma(df, uf, acc[q]);  // rows i, columns e
+                else
+                    acc[q] = mma(uf, df, acc[q]);  // rows e, columns i
             }
         };
         int s = 0;
@@ -721,13 +721,11 @@ __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsig
                 for (int m = 0; m < 4; ++m) {
 #pragma unroll
                     for (int q = 0; q < PMAX; ++q) {
-                        if (pc + q * WPE < npairs) {
-                            const Frag<PREC> df{dq[q][m]}, uf{uq[m]};
-                            if constexpr (LAYOUT == LPX_ELEMENT_MAJOR)
-                                acc[q] = mma(df, uf, acc[q]);
-                            else
-                                acc[q] = mma(uf, df, acc[q]);
-                        }
+                        const Frag<PREC> df{dq[q][m]}, uf{uq[m]};
+                        if constexpr (LAYOUT == LPX_ELEMENT_MAJOR)
+                            acc[q] = mma(df, uf, acc[q]);
+                        else
+                            acc[q] = mma(uf, df, acc[q]);
                     }
                 }
             };
@@ -761,7 +759,9 @@ template <int PREC, int NTMAX, int WPE>
 struct DRegs {
     static constexpr int PMAX = (3 * NTMAX + WPE - 1) / WPE;
     static constexpr int NS = 16 * NTMAX / Traits<PREC>::KSTEP;
+    static constexpr int NT = PREC == LPX_FP32 ? 3 : 1;  // fp32 steps after the last quad
     Frag<PREC> f[PMAX][NS];
+    Frag<PREC> t[PMAX][NT];  // fp32: step 4*(nsteps/4) + m, so its register is fixed
 };
 
 template <int PREC, int NTMAX, int WPE>
@@ -776,6 +776,11 @@ __device__ __forceinline__ void load_dregs(const ContractArgs& a, int part, int 
         const int k = p / a.nt, t = p - (p / a.nt) * a.nt;
 #pragma unroll
         for (int s = 0; s < DR::NS; ++s) d.f[q][s] = d_frag_global<PREC>(a, k, t, s, lane);
+        if constexpr (PREC == LPX_FP32) {
+#pragma unroll
+            for (int m = 0; m < DR::NT; ++m)
+                d.t[q][m] = d_frag_global<PREC>(a, k, t, (a.nsteps & ~3) + m, lane);
+        }
     }
 }
 
@@ -791,18 +796,17 @@ __device__ __forceinline__ void block_compute_dreg(const ContractArgs& a,
     for (int q = 0; q < DR::PMAX; ++q) acc[q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
     // Every u operand is read before the first MFMA, without branches
     // (reads past the last step are in bounds and zero-selected), so the
-    // reads overlap one another and the wave waits once.  The MFMAs run to
-    // the compiled bound under uniform guards, with constant register
-    // indices throughout.
-    auto mma_all = [&](int s, const Frag<PREC>& uf) {
+    // reads overlap one another and the wave waits once.  MFMAs run for
+    // every held pair (a pair past the last one holds a duplicate and is
+    // never stored), so the only branches are one per k-step group, with
+    // constant register indices throughout.
+    auto mma_all = [&](const Frag<PREC> (&df)[DR::PMAX], const Frag<PREC>& uf) {
 #pragma unroll
         for (int q = 0; q < DR::PMAX; ++q) {
-            if (part + q * WPE < npairs) {
-                if constexpr (LAYOUT == LPX_ELEMENT_MAJOR)
-                    acc[q] = mma(d.f[q][s], uf, acc[q]);
-                else
-                    acc[q] = mma(uf, d.f[q][s], acc[q]);
-            }
+            if constexpr (LAYOUT == LPX_ELEMENT_MAJOR)
+                acc[q] = mma(df[q], uf, acc[q]);
+            else
+                acc[q] = mma(uf, df[q], acc[q]);
         }
     };
     if constexpr (PREC == LPX_FP32) {
@@ -810,7 +814,7 @@ __device__ __forceinline__ void block_compute_dreg(const ContractArgs& a,
         const int nq = a.nsteps >> 2;
         const int ntail = a.nsteps - 4 * nq;  // 0..3 steps after the last quad
         f4 uq[NQ];
-        Frag<PREC> ut3[3];
+        Frag<PREC> ut3[DR::NT];
 #pragma unroll
         for (int Q = 0; Q < NQ; ++Q) {
             if constexpr (PF_U)
@@ -819,7 +823,7 @@ __device__ __forceinline__ void block_compute_dreg(const ContractArgs& a,
                 uq[Q] = u_quad_global<LAYOUT>(a, eb0, Q, lane);
         }
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
+        for (int m = 0; m < DR::NT; ++m) {
             if constexpr (PF_U)
                 ut3[m] = u_frag_lds<PREC, LAYOUT, TILE_E>(ut, a.Np, a.np_vec, row0, 4 * nq + m,
                                                           4 * nq, lane);
@@ -830,17 +834,21 @@ __device__ __forceinline__ void block_compute_dreg(const ContractArgs& a,
         for (int Q = 0; Q < NQ; ++Q) {
             if (Q < nq) {
 #pragma unroll
-                for (int m = 0; m < 4; ++m) mma_all(4 * Q + m, Frag<PREC>{uq[Q][m]});
+                for (int m = 0; m < 4; ++m) {
+                    Frag<PREC> df[DR::PMAX];
+#pragma unroll
+                    for (int q = 0; q < DR::PMAX; ++q) df[q] = d.f[q][4 * Q + m];
+                    mma_all(df, Frag<PREC>{uq[Q][m]});
+                }
             }
         }
-        // tail steps 4*nq + m: one branch per possible nq keeps the
-        // register index of D constant
 #pragma unroll
-        for (int Q0 = 0; Q0 < NQ; ++Q0) {
-            if (nq == Q0) {
+        for (int m = 0; m < DR::NT; ++m) {
+            if (m < ntail) {
+                Frag<PREC> df[DR::PMAX];
 #pragma unroll
-                for (int m = 0; m < 3; ++m)
-                    if (m < ntail && 4 * Q0 + m < DR::NS) mma_all(4 * Q0 + m, ut3[m]);
+                for (int q = 0; q < DR::PMAX; ++q) df[q] = d.t[q][m];
+                mma_all(df, ut3[m]);
             }
         }
     } else {
@@ -853,8 +861,14 @@ __device__ __forceinline__ void block_compute_dreg(const ContractArgs& a,
                 uf[s] = u_frag_global<PREC, LAYOUT>(a, eb0, s, lane);
         }
 #pragma unroll
-        for (int s = 0; s < DR::NS; ++s)
-            if (s < a.nsteps) mma_all(s, uf[s]);
+        for (int s = 0; s < DR::NS; ++s) {
+            if (s < a.nsteps) {
+                Frag<PREC> df[DR::PMAX];
+#pragma unroll
+                for (int q = 0; q < DR::PMAX; ++q) df[q] = d.f[q][s];
+                mma_all(df, uf[s]);
+            }
+        }
     }
     if constexpr (PF_O)
         stage_pairs<LAYOUT, DR::PMAX, WPE, TILE_E>(a, acc, part, row0, os, lane);
@@ -870,8 +884,8 @@ __device__ __forceinline__ void block_compute_dreg(const ContractArgs& a,
 template <int TILE_E, int NTMAX, int PREFETCH>
 struct Shape {
     static constexpr ContractShape CS = contract_shape(TILE_E, NTMAX, PREFETCH);
-    static constexpr int NCW = CS.ncw, WPE = CS.wpe, NLW = CS.nlw, NSW = CS.nsw,
-                         THREADS = CS.threads;
+    static constexpr int NCW = CS.ncw, WPE = CS.wpe, BPW = CS.bpw, NLW = CS.nlw,
+                         NSW = CS.nsw, THREADS = CS.threads;
 };
 
 template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PREFETCH, int UNROLL>
@@ -981,28 +995,45 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
                 __builtin_amdgcn_s_barrier();
             }
         } else {
-            const int eblk = wave / S::WPE, part = wave % S::WPE;
+            // Compute wave: part `part` of blocks eblk0, eblk0 + NCW/WPE, ...
+            // (BPW blocks of each tile).
+            const int eblk0 = wave / S::WPE, part = wave % S::WPE;
+            constexpr int BSTRIDE = S::NCW / S::WPE;
+            auto tile_work = [&](auto&& block, int64_t n) {
+                const int64_t tile = t0 + n * g;
+                const int nv = nvalid_of(tile);
+                if (nv == TILE_E) {  // uniform: whole tile, no per-block test
+#pragma unroll
+                    for (int b = 0; b < S::BPW; ++b) block(tile, n, 16 * (eblk0 + b * BSTRIDE));
+                } else {
+#pragma unroll
+                    for (int b = 0; b < S::BPW; ++b)
+                        if (16 * (eblk0 + b * BSTRIDE) < nv)
+                            block(tile, n, 16 * (eblk0 + b * BSTRIDE));
+                }
+            };
             if constexpr (D_REG) {
                 DRegs<PREC, NTMAX, S::WPE> d;
                 load_dregs<PREC, NTMAX, S::WPE>(a, part, lane, d);
+                auto block = [&](int64_t tile, int64_t n, int row0) {
+                    block_compute_dreg<PREC, LAYOUT, NTMAX, true, TILE_E, S::WPE, PF_O>(
+                        a, d, ring + (n & 3) * a.ldu, row0, tile * TILE_E + row0, part, lane,
+                        oring + (n & 1) * a.ldo);
+                };
                 __syncthreads();
                 for (int64_t n = 0; n < niter; ++n) {
-                    const int64_t tile = t0 + n * g;
-                    if (n < nmine && 16 * eblk < nvalid_of(tile))
-                        block_compute_dreg<PREC, LAYOUT, NTMAX, true, TILE_E, S::WPE, PF_O>(
-                            a, d, ring + (n & 3) * a.ldu, 16 * eblk, tile * TILE_E + 16 * eblk,
-                            part, lane, oring + (n & 1) * a.ldo);
+                    if (n < nmine) tile_work(block, n);
                     __syncthreads();
                 }
             } else {
+                auto block = [&](int64_t tile, int64_t n, int row0) {
+                    block_compute<PREC, LAYOUT, NTMAX, PF_D, true, TILE_E, S::WPE, UNROLL, PF_O>(
+                        a, lds, ring + (n & 3) * a.ldu, row0, tile * TILE_E + row0, part, lane,
+                        oring + (n & 1) * a.ldo);
+                };
                 __syncthreads();
                 for (int64_t n = 0; n < niter; ++n) {
-                    const int64_t tile = t0 + n * g;
-                    if (n < nmine && 16 * eblk < nvalid_of(tile))
-                        block_compute<PREC, LAYOUT, NTMAX, PF_D, true, TILE_E, S::WPE, UNROLL,
-                                      PF_O>(a, lds, ring + (n & 3) * a.ldu, 16 * eblk,
-                                            tile * TILE_E + 16 * eblk, part, lane,
-                                            oring + (n & 1) * a.ldo);
+                    if (n < nmine) tile_work(block, n);
                     __syncthreads();
                 }
             }

@@ -29,14 +29,15 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // Work-group shape of a contraction kernel instance (host and device agree
 // on it through this one function).  Without a staged u tile (prefetch bit
 // 1 clear): four waves per 16-element block, splitting its (k, i-block)
-// pairs.  With one: min(4 * tile_e/16, 8) compute waves, wpe of them per
-// block, plus nlw loader waves (1, or tile_e * ntmax / 128 when larger,
-// so that a loader wave loads at most 8 16-byte chunks per lane and tile),
-// and with a staged output tile (bit 3) four store waves: the write-back
-// is three quarters of the traffic and needs that many waves issuing
-// stores to keep HBM busy.
+// pairs.  With one: min(4 * tile_e/16, 8) compute waves, four per block,
+// each taking bpw = tile_e / (4 * ncw) blocks of every tile (two at
+// tile_e = 64, so a wave does more MFMA work per work-group barrier); nlw
+// loader waves (1, or tile_e * ntmax / 128 when larger, so that a loader
+// wave loads at most 8 16-byte chunks per lane and tile); and with a staged
+// output tile (bit 3) four store waves: the write-back is three quarters
+// of the traffic and needs that many waves issuing stores to keep HBM busy.
 struct ContractShape {
-    int ncw, wpe, nlw, nsw, threads;
+    int ncw, wpe, bpw, nlw, nsw, threads;
 };
 constexpr ContractShape contract_shape(int tile_e, int ntmax, int prefetch) {
     const bool pf_u = (prefetch & 2) != 0;
@@ -45,7 +46,7 @@ constexpr ContractShape contract_shape(int tile_e, int ntmax, int prefetch) {
     const int ncw = pf_u ? (4 * nb < 8 ? 4 * nb : 8) : 4 * nb;
     const int nlw = pf_u ? (tile_e * ntmax / 128 > 1 ? tile_e * ntmax / 128 : 1) : 0;
     const int nsw = pf_o ? 4 : 0;
-    return ContractShape{ncw, ncw / nb, nlw, nsw, 64 * (ncw + nlw + nsw)};
+    return ContractShape{ncw, 4, 4 * nb / ncw, nlw, nsw, 64 * (ncw + nlw + nsw)};
 }
 // 16-byte chunks one loader wave loads per u tile (nlw loader waves; a
 // tile holds at most tile_e * 16 * ntmax floats).

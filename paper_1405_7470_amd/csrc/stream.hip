@@ -9,15 +9,16 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 // y[r*n + t] = x[t] for r < fanout: one read stream, `fanout` write streams
-// (fanout 1 is a plain copy).  n4 = n / 4 float4 chunks.
+// (fanout 1 is a plain copy).  n4 = n / 4 float4 chunks, one per thread:
+// the grid covers the array, which streams faster on this GPU than a
+// persistent grid-stride loop.
 __global__ __launch_bounds__(256) void stream_kernel(const f4* __restrict__ x,
                                                      f4* __restrict__ y, int64_t n4,
                                                      int fanout) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n4; t += stride) {
-        const f4 v = x[t];
-        for (int r = 0; r < fanout; ++r) y[r * n4 + t] = v;
-    }
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n4) return;
+    const f4 v = x[t];
+    for (int r = 0; r < fanout; ++r) y[r * n4 + t] = v;
 }
 
 }  // namespace
@@ -43,9 +44,8 @@ extern "C" lpx_status lpx_stream_probe(const float* x, float* y, int64_t n, int3
     lpx_status s = current_device_info(&dev);
     if (s != LPX_OK) return s;
     const int64_t n4 = n / 4;
-    int64_t blocks = (n4 + 255) / 256;
-    const int64_t cap = (int64_t)dev.num_cu * 8;
-    if (blocks > cap) blocks = cap;
+    const int64_t blocks = (n4 + 255) / 256;
+    if (blocks > 0x7fffffff) return set_error(LPX_ERR_INVALID_ARG, "n too large for one launch");
     hipLaunchKernelGGL(stream_kernel, dim3((unsigned)blocks), dim3(256), 0,
                        reinterpret_cast<hipStream_t>(stream),
                        reinterpret_cast<const f4*>(x), reinterpret_cast<f4*>(y), n4, fanout);

@@ -93,9 +93,8 @@ def status(d, rec=None):
 def test_validate_accepts_well_formed():
     assert status(desc()) == lpx.OK
     for r in lpx.enumerate_records(3, 56, 1000, "dm", "bf16x3"):
-        # (64, 6/14): two waves per block cannot hold D in registers;
         # (64, 11): D fragments + u ring + DOF-major output ring exceed LDS
-        bad = ((64, 6), (64, 14), (64, 11))
+        bad = ((64, 11),)
         want = lpx.ERR_UNSUPPORTED if (r.tile_e, r.prefetch) in bad else lpx.OK
         assert status(desc(layout=1), r) == want, lpx.describe(r)
 
@@ -141,8 +140,8 @@ def test_register_d_limits():
     assert status(desc(Np=56), lpx.record("bf16x3", 32, 6, 1)) == lpx.OK
     assert status(desc(Np=84), lpx.record("fp32", 32, 4, 1)) == lpx.ERR_UNSUPPORTED
     assert status(desc(K=4, Np=56), lpx.record("fp32", 32, 4, 1)) == lpx.ERR_UNSUPPORTED
-    # a staged 64-element tile leaves two waves per block: not enough registers
-    assert status(desc(Np=56), lpx.record("fp32", 64, 6, 1)) == lpx.ERR_UNSUPPORTED
+    assert status(desc(Np=56), lpx.record("fp32", 64, 6, 1)) == lpx.OK
+    assert status(desc(Np=56), lpx.record("fp32", 64, 14, 1)) == lpx.OK
     assert status(desc(Np=56), lpx.record("fp32", 64, 4, 1)) == lpx.OK
     s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", lpx.record("fp32", 32, 6, 1))
     assert s == lpx.OK and b == 4 * (32 * 64 + 32) * 4  # only the u ring
