@@ -444,29 +444,32 @@ __device__ __forceinline__ bool loader_issue(const ContractArgs& a, float* slot,
         }
         return false;
     } else {
+        // 64 lanes cover whole rows (CPR and TILE_E divide 64), so lane l of
+        // instruction w reads row  l / CPR + w * (64 / CPR)  at a column that
+        // does not depend on w: one base address per lane plus a uniform
+        // row stride per instruction.
         constexpr int CPR = TILE_E / 4;
         if (a.e_vec) {  // uniform: E % 4 == 0, so nvalid % 4 == 0 and rows are aligned
-            const int nch = a.Np * CPR;
+            int col = 4 * (lane % CPR);
+            col = col < nvalid ? col : nvalid - 4;  // columns >= nvalid are never used
+            const float* base = a.u + e0 + col;
 #pragma unroll
             for (int q = 0; q < PL; ++q) {
                 const int w = lw + NLW * q;
-                int c = lane + 64 * w;
-                c = c < nch ? c : nch - 1;
-                int col = 4 * (c % CPR);
-                col = col < nvalid ? col : nvalid - 4;  // columns >= nvalid are never used
-                dma16(a.u + (int64_t)(c / CPR) * a.E + e0 + col, slot + 256 * w);
+                int j = lane / CPR + w * (64 / CPR);
+                j = j < a.Np ? j : a.Np - 1;  // rows past Np land in the slot's slack
+                dma16(base + (int64_t)j * a.E, slot + 256 * w);
             }
             return true;
         }
-        const int nf = a.Np * TILE_E;
+        const int r = lane % TILE_E;
+        const float* base = a.u + e0 + (r < nvalid ? r : nvalid - 1);
 #pragma unroll
         for (int q = 0; q < 4 * PL; ++q) {
             const int w = lw + NLW * q;
-            int f = lane + 64 * w;
-            f = f < nf ? f : nf - 1;
-            const int r = f % TILE_E;
-            dma4(a.u + (int64_t)(f / TILE_E) * a.E + e0 + (r < nvalid ? r : nvalid - 1),
-                 slot + 64 * w);
+            int j = lane / TILE_E + w * (64 / TILE_E);
+            j = j < a.Np ? j : a.Np - 1;
+            dma4(base + (int64_t)j * a.E, slot + 64 * w);
         }
         return false;
     }

@@ -121,13 +121,70 @@ def lookup_traffic(path, kernel):
     return table.get(kernel)
 
 
-def write_stats(csv_path, out, cmd, title, top=25):
+_REC = re.compile(r"(\w+) tile_e=(\d+) prefetch=(\d+) unroll=(\d+)")
+
+
+class _Rec:
+    def __init__(self, desc):
+        m = _REC.match(desc)
+        self.precision, self.tile_e, self.prefetch, self.unroll = (
+            m.group(1), int(m.group(2)), int(m.group(3)), int(m.group(4)))
+
+
+def timed_region(trace_csv, kernels, steps):
+    """Average duration (us) of each kernel over the last `steps` complete
+    cycles in which the given kernels were dispatched back to back in this
+    order (the timed steps of bench.py launch its problems round-robin)."""
+    with open(trace_csv, newline="") as fh:
+        rows = list(csv.DictReader(fh))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    names = [r["Kernel_Name"] for r in rows]
+    n = len(kernels)
+    cycles = [i for i in range(len(names) - n + 1) if names[i:i + n] == kernels]
+    # the longest chain of cycles that follow one another directly
+    best, cur = [], []
+    for i in cycles:
+        cur = cur + [i] if cur and i == cur[-1] + n else [i]
+        if len(cur) >= len(best):
+            best = cur
+    use = best[-steps:]
+    avg = []
+    for k in range(n):
+        d = [int(rows[i + k]["End_Timestamp"]) - int(rows[i + k]["Start_Timestamp"]) for i in use]
+        avg.append(sum(d) / len(d) / 1e3 if d else float("nan"))
+    return avg, len(use)
+
+
+def write_stats(csv_path, out, cmd, title, top=25, trace_csv=None, bench_json=None):
     with open(csv_path, newline="") as fh:
         rows = list(csv.DictReader(fh))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     with open(out, "w") as fh:
         fh.write(f"# {title}\n\n")
         fh.write(f"Command: `{cmd}`\n\n")
+        if trace_csv and bench_json:
+            import json
+            b = json.load(open(bench_json))
+            sel = b["config"]["selection"]
+            per = b["variants"][sel]["per_problem"]
+            keys = list(per)
+            Np = int(re.search(r"Np=(\d+)", b["config"]["workload"]).group(1))
+            kern = [contraction_kernel_name(_Rec(per[k]["record"]).precision, k.split("/")[0], Np,
+                                            _Rec(per[k]["record"])) for k in keys]
+            avg, ncyc = timed_region(trace_csv, kern, b["steps"])
+            fh.write(f"Timed steps of the {sel} records ({ncyc} cycles of the round-robin "
+                     "launch sequence found in the per-dispatch trace), against the same run's "
+                     "own HIP-event timing:\n\n")
+            fh.write("| problem | record | kernel | trace average us | bench event us |\n"
+                     "|---|---|---|---|---|\n")
+            for k, name, a in zip(keys, kern, avg):
+                fh.write(f"| {k} | {per[k]['record'].split(' gemm')[0]} | `{name}` | {a:.1f} | "
+                         f"{per[k]['us']:.1f} |\n")
+            fh.write(f"\nbench line of this run: value {b['value']:.2f} {b['unit']}, "
+                     f"{b['ms_per_step']:.4f} ms per step; dominant kernel "
+                     f"{b['roofline']['kernel']}\n\n")
+        fh.write("All kernels of the run (an instance's average mixes every shape it was "
+                 "launched on, including the ragged batch's separate launches):\n\n")
         fh.write("| kernel | calls | average us | total us | % |\n|---|---|---|---|---|\n")
         for r in rows[:top]:
             fh.write(f"| `{r['Name']}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
@@ -142,6 +199,8 @@ def main():
     a.add_argument("--out", required=True)
     a.add_argument("--cmd", required=True)
     a.add_argument("--title", default="rocprofv3 kernel statistics")
+    a.add_argument("--trace", default=None, help="the run's *_kernel_trace.csv")
+    a.add_argument("--bench-json", default=None, help="the bench.py line of the same run")
     b = sub.add_parser("traffic")
     b.add_argument("--fetch", required=True)
     b.add_argument("--write", required=True)
@@ -152,7 +211,8 @@ def main():
     b.add_argument("--title", default="HBM traffic per dispatch")
     args = ap.parse_args()
     if args.what == "stats":
-        write_stats(args.csv, args.out, args.cmd, args.title)
+        write_stats(args.csv, args.out, args.cmd, args.title, trace_csv=args.trace,
+                    bench_json=args.bench_json)
     else:
         rows, ff, fw = traffic(args.fetch, args.write, args.copy_bytes)
         write_traffic(args.out, rows, ff, fw, args.copy_bytes, args.cmd_fetch, args.cmd_write,
