@@ -45,6 +45,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "lpx_internal.h"
 
@@ -330,7 +331,10 @@ __device__ __forceinline__ void d_frag_store_lds(unsigned char* lds, int64_t nfr
 // (j >= Np, up to the next multiple of 32) stay inside it; those values are
 // replaced by zero with a select, never multiplied.  Compute waves convert
 // what they read to the operand precision.
-template <int PREC, int LAYOUT, int TILE_E>
+// MASK: zero the columns j >= Np.  Without it the caller guarantees that
+// every column it uses is below Np (the values read for other columns may
+// belong to the next element or to the slot's slack).
+template <int PREC, int LAYOUT, int TILE_E, bool MASK = true>
 __device__ __forceinline__ Frag<PREC> u_frag_lds(const float* ut, int Np, bool np_vec, int row0,
                                                  int s, int nquad_steps, int lane) {
     const int r = row0 + (lane & 15);
@@ -338,7 +342,8 @@ __device__ __forceinline__ Frag<PREC> u_frag_lds(const float* ut, int Np, bool n
         const int j0 = fp32_col(s, lane >> 4, nquad_steps);
         const int jc = j0 < Np ? j0 : Np - 1;  // callers may read steps past the last
         const float x = LAYOUT == LPX_ELEMENT_MAJOR ? ut[r * Np + jc] : ut[jc * TILE_E + r];
-        return {j0 < Np ? x : 0.0f};
+        if constexpr (MASK) return {j0 < Np ? x : 0.0f};
+        return {x};
     } else {
         const int j0 = s * Traits<PREC>::KSTEP + (lane >> 4) * Traits<PREC>::KPL;
         float v[8];
@@ -355,14 +360,16 @@ __device__ __forceinline__ Frag<PREC> u_frag_lds(const float* ut, int Np, bool n
             for (int t = 0; t < 8; ++t)
                 v[t] = LAYOUT == LPX_ELEMENT_MAJOR ? ut[r * Np + j0 + t] : ut[(j0 + t) * TILE_E + r];
         }
+        if constexpr (MASK) {
 #pragma unroll
-        for (int t = 0; t < 8; ++t) v[t] = j0 + t < Np ? v[t] : 0.0f;
+            for (int t = 0; t < 8; ++t) v[t] = j0 + t < Np ? v[t] : 0.0f;
+        }
         return make_frag8<PREC>(v);
     }
 }
 
-// fp32 quad Q of the staged tile (see u_frag_lds for the layout).
-template <int LAYOUT, int TILE_E>
+// fp32 quad Q of the staged tile (see u_frag_lds for the layout and MASK).
+template <int LAYOUT, int TILE_E, bool MASK = true>
 __device__ __forceinline__ f4 u_quad_lds(const float* ut, int Np, bool np_vec, int row0, int Q,
                                          int lane) {
     const int r = row0 + (lane & 15);
@@ -375,8 +382,10 @@ __device__ __forceinline__ f4 u_quad_lds(const float* ut, int Np, bool np_vec, i
         for (int t = 0; t < 4; ++t)
             v[t] = LAYOUT == LPX_ELEMENT_MAJOR ? ut[r * Np + j0 + t] : ut[(j0 + t) * TILE_E + r];
     }
+    if constexpr (MASK) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) v[t] = j0 + t < Np ? v[t] : 0.0f;
+        for (int t = 0; t < 4; ++t) v[t] = j0 + t < Np ? v[t] : 0.0f;
+    }
     return v;
 }
 
@@ -659,8 +668,13 @@ __device__ __forceinline__ void store_tile(const ContractArgs& a, const float* o
 // staged tile `ut` at row `row0` (PF_U) or global memory.  The summation
 // order of every output depends only on PREC: all records of a precision
 // give bit-identical results.
+// MASK (fp32): zero u columns j >= Np.  It is needed only when Np % 4 != 0:
+// otherwise the quads and the steps after them cover exactly j < Np, and
+// dropping the selects keeps their lane masks out of the scalar registers.
+// bf16/bf16x3 mask their last k-step only (it straddles Np unless
+// Np % 32 == 0); the other steps lie below Np.
 template <int PREC, int LAYOUT, int NTMAX, bool PF_D, bool PF_U, int TILE_E, int WPE, int UNROLL,
-          bool PF_O = false>
+          bool PF_O = false, bool MASK = true>
 __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsigned char* lds,
                                               const float* ut, int row0, int64_t eb0, int part,
                                               int lane, float* os = nullptr) {
@@ -680,10 +694,11 @@ __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsig
             pk[q] = p / a.nt;
             pt[q] = p - pk[q] * a.nt;
         }
-        auto step = [&](int s) {
+        auto step = [&](int s, auto masked) {
             Frag<PREC> uf;
             if constexpr (PF_U)
-                uf = u_frag_lds<PREC, LAYOUT, TILE_E>(ut, a.Np, a.np_vec, row0, s, a.nsteps & ~3, lane);
+                uf = u_frag_lds<PREC, LAYOUT, TILE_E, decltype(masked)::value>(
+                    ut, a.Np, a.np_vec, row0, s, a.nsteps & ~3, lane);
             else
                 uf = u_frag_global<PREC, LAYOUT>(a, eb0, s, lane);
             // every held pair runs: a pair past the last one holds a clamped
@@ -709,7 +724,7 @@ __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsig
             auto quad = [&](int Q) {
                 f4 uq;
                 if constexpr (PF_U)
-                    uq = u_quad_lds<LAYOUT, TILE_E>(ut, a.Np, a.np_vec, row0, Q, lane);
+                    uq = u_quad_lds<LAYOUT, TILE_E, MASK>(ut, a.Np, a.np_vec, row0, Q, lane);
                 else
                     uq = u_quad_global<LAYOUT>(a, eb0, Q, lane);
                 f4 dq[PMAX];
@@ -739,14 +754,16 @@ __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsig
                 for (int uu = 0; uu < UNROLL; ++uu) quad(Q + uu);
             }
             for (; Q < nq; ++Q) quad(Q);
-            s = 4 * nq;
+            for (s = 4 * nq; s < a.nsteps; ++s) step(s, std::integral_constant<bool, MASK>());
         } else {
-            for (; s + UNROLL <= a.nsteps; s += UNROLL) {
+            const int last = a.nsteps - 1;  // the only step that can straddle Np
+            for (; s + UNROLL <= last; s += UNROLL) {
 #pragma unroll
-                for (int uu = 0; uu < UNROLL; ++uu) step(s + uu);
+                for (int uu = 0; uu < UNROLL; ++uu) step(s + uu, std::false_type());
             }
+            for (; s < last; ++s) step(s, std::false_type());
+            step(last, std::true_type());
         }
-        for (; s < a.nsteps; ++s) step(s);
         if constexpr (PF_O)
             stage_pairs<LAYOUT, PMAX, WPE, TILE_E>(a, acc, pc, row0, os, lane);
         else
@@ -787,7 +804,8 @@ __device__ __forceinline__ void load_dregs(const ContractArgs& a, int part, int 
     }
 }
 
-template <int PREC, int LAYOUT, int NTMAX, bool PF_U, int TILE_E, int WPE, bool PF_O = false>
+template <int PREC, int LAYOUT, int NTMAX, bool PF_U, int TILE_E, int WPE, bool PF_O = false,
+          bool MASK = true>
 __device__ __forceinline__ void block_compute_dreg(const ContractArgs& a,
                                                    const DRegs<PREC, NTMAX, WPE>& d,
                                                    const float* ut, int row0, int64_t eb0,
@@ -821,15 +839,15 @@ __device__ __forceinline__ void block_compute_dreg(const ContractArgs& a,
 #pragma unroll
         for (int Q = 0; Q < NQ; ++Q) {
             if constexpr (PF_U)
-                uq[Q] = u_quad_lds<LAYOUT, TILE_E>(ut, a.Np, a.np_vec, row0, Q, lane);
+                uq[Q] = u_quad_lds<LAYOUT, TILE_E, MASK>(ut, a.Np, a.np_vec, row0, Q, lane);
             else
                 uq[Q] = u_quad_global<LAYOUT>(a, eb0, Q, lane);
         }
 #pragma unroll
         for (int m = 0; m < DR::NT; ++m) {
             if constexpr (PF_U)
-                ut3[m] = u_frag_lds<PREC, LAYOUT, TILE_E>(ut, a.Np, a.np_vec, row0, 4 * nq + m,
-                                                          4 * nq, lane);
+                ut3[m] = u_frag_lds<PREC, LAYOUT, TILE_E, MASK>(ut, a.Np, a.np_vec, row0,
+                                                                4 * nq + m, 4 * nq, lane);
             else
                 ut3[m] = u_frag_global<PREC, LAYOUT>(a, eb0, 4 * nq + m, lane);
         }
@@ -859,7 +877,14 @@ __device__ __forceinline__ void block_compute_dreg(const ContractArgs& a,
 #pragma unroll
         for (int s = 0; s < DR::NS; ++s) {
             if constexpr (PF_U)
-                uf[s] = u_frag_lds<PREC, LAYOUT, TILE_E>(ut, a.Np, a.np_vec, row0, s, 0, lane);
+                // nsteps == NS for every Np of the NTMAX bucket, so only the
+                // last compiled step straddles Np
+                if (s == DR::NS - 1)
+                    uf[s] = u_frag_lds<PREC, LAYOUT, TILE_E, true>(ut, a.Np, a.np_vec, row0, s, 0,
+                                                                   lane);
+                else
+                    uf[s] = u_frag_lds<PREC, LAYOUT, TILE_E, false>(ut, a.Np, a.np_vec, row0, s, 0,
+                                                                    lane);
             else
                 uf[s] = u_frag_global<PREC, LAYOUT>(a, eb0, s, lane);
         }
@@ -1019,9 +1044,16 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
                 DRegs<PREC, NTMAX, S::WPE> d;
                 load_dregs<PREC, NTMAX, S::WPE>(a, part, lane, d);
                 auto block = [&](int64_t tile, int64_t n, int row0) {
-                    block_compute_dreg<PREC, LAYOUT, NTMAX, true, TILE_E, S::WPE, PF_O>(
-                        a, d, ring + (n & 3) * a.ldu, row0, tile * TILE_E + row0, part, lane,
-                        oring + (n & 1) * a.ldo);
+                    auto run = [&](auto mask) {
+                        block_compute_dreg<PREC, LAYOUT, NTMAX, true, TILE_E, S::WPE, PF_O,
+                                           decltype(mask)::value>(
+                            a, d, ring + (n & 3) * a.ldu, row0, tile * TILE_E + row0, part, lane,
+                            oring + (n & 1) * a.ldo);
+                    };
+                    if (PREC == LPX_FP32 && a.np_vec)  // uniform
+                        run(std::false_type());
+                    else
+                        run(std::true_type());
                 };
                 __syncthreads();
                 for (int64_t n = 0; n < niter; ++n) {
@@ -1030,9 +1062,16 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
                 }
             } else {
                 auto block = [&](int64_t tile, int64_t n, int row0) {
-                    block_compute<PREC, LAYOUT, NTMAX, PF_D, true, TILE_E, S::WPE, UNROLL, PF_O>(
-                        a, lds, ring + (n & 3) * a.ldu, row0, tile * TILE_E + row0, part, lane,
-                        oring + (n & 1) * a.ldo);
+                    auto run = [&](auto mask) {
+                        block_compute<PREC, LAYOUT, NTMAX, PF_D, true, TILE_E, S::WPE, UNROLL, PF_O,
+                                      decltype(mask)::value>(
+                            a, lds, ring + (n & 3) * a.ldu, row0, tile * TILE_E + row0, part, lane,
+                            oring + (n & 1) * a.ldo);
+                    };
+                    if (PREC == LPX_FP32 && a.np_vec)  // uniform
+                        run(std::false_type());
+                    else
+                        run(std::true_type());
                 };
                 __syncthreads();
                 for (int64_t n = 0; n < niter; ++n) {
