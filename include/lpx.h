@@ -258,12 +258,16 @@ typedef struct lpx_batch lpx_batch;
  * of one precision), or NULL to take each item's FP32 winner from the
  * tuning cache, else the FP32 default.
  *   *h == NULL: builds the batch -- instances ordered largest first (cost
- *     K*Np^2*E), cut into 16-element tiles that persistent work-groups pull
- *     from an atomic counter; a record's D-prefetch bit is honoured when
- *     its staged D fits 48 KiB of LDS (else D is read from global memory);
- *     the tile is fixed at 16 elements and u is streamed from global memory
- *     -- captures [counter reset, persistent kernel] into a graph, launches
- *     it on `stream`, and returns the handle in *h.
+ *     K*Np^2*E) and cut into element tiles -- captures the persistent
+ *     launch into a graph, launches it on `stream`, and returns the handle
+ *     in *h.  The records fix the precision; the batch runs one tile
+ *     routine for all instances: when its LDS rings fit (160 KiB), the
+ *     staged pipeline of prefetch bits 1 and 3 on 32-element tiles dealt
+ *     round-robin to the work-groups (u tiles and outputs staged in LDS,
+ *     D read from global memory); otherwise 16-element tiles pulled from
+ *     an atomic counter with u read from global memory and D staged in
+ *     LDS when a record asks for it and it fits 48 KiB (the graph then
+ *     holds [counter reset, kernel]).
  *   *h != NULL: items must have the batch's n and per-item K, Np, E and
  *     layout (pointers may change); copies the updated descriptor table and
  *     replays the graph on `stream`.
@@ -273,10 +277,11 @@ typedef struct lpx_batch lpx_batch;
 lpx_status lpx_batch_submit(const lpx_contract_desc* items, const lpx_record* recs,
                             int32_t n, lpx_batch** h, void* stream);
 
-/* Tiles in the batch, persistent grid size and dynamic LDS per work-group
- * (any output pointer may be NULL). */
-lpx_status lpx_batch_info(const lpx_batch* b, int64_t* total_tiles, int32_t* grid,
-                          int64_t* lds_bytes);
+/* Tiles in the batch, elements per tile (32 staged, 16 direct), persistent
+ * grid size and dynamic LDS per work-group (any output pointer may be
+ * NULL). */
+lpx_status lpx_batch_info(const lpx_batch* b, int64_t* total_tiles, int32_t* tile_e,
+                          int32_t* grid, int64_t* lds_bytes);
 
 /* Frees the batch; the caller must first make sure no submitted replay is
  * still running.  NULL is a no-op. */

@@ -1,18 +1,27 @@
 // Ragged batch of contractions in one persistent, graph-captured launch.
 //
-// Each instance i (its own K, Np, E, pointers, record) is cut into 16-element
-// tiles; the tiles of all instances form one list, largest instances first
-// (longest-processing-time order, cost K*Np^2*E).  Persistent work-groups of
-// four waves pull chunks of tiles from one atomic counter, find each tile's
-// instance by binary search over the instances' first-tile indices, and run
-// the same per-block routine as lpx_contract (four waves split the block's
-// (k, i-block) pairs).  D is staged in LDS when the instance's record asks
-// for it and it fits the batch's LDS budget; otherwise D fragments are read
-// from global memory.  Every output's summation order depends only on the
-// precision, so the batch is bit-identical to separate lpx_contract calls.
+// Each instance i (its own K, Np, E, pointers) is cut into element tiles;
+// the tiles of all instances form one list, largest instances first
+// (longest-processing-time order, cost K*Np^2*E).
 //
-// The counter reset (a one-thread kernel, not a memset node) and the batch
-// kernel are captured once into a HIP graph on a library-owned stream;
+// Staged kernel (the default): 32-element tiles dealt round-robin to the
+// persistent work-groups (work-group w takes tiles w, w + G, w + 2G, ...,
+// which spreads every instance over all of them).  Each work-group runs the
+// contraction's staged pipeline -- loader waves filling a four-slot LDS ring
+// of u tiles with direct global-to-LDS loads, eight compute waves (D
+// fragments from global memory, L2-resident), four store waves writing the
+// previous tile's staged output with contiguous stores -- and every wave
+// follows the instance table with its own cursor (tiles of a work-group
+// come in increasing order, so the cursor only moves forward).
+//
+// Direct kernel (when the staged rings do not fit in LDS): 16-element tiles
+// pulled in chunks from one atomic counter by four-wave work-groups that
+// read u straight from global memory, D staged in LDS when it fits.
+//
+// Both run the same per-block MFMA routine as lpx_contract, so every output
+// is bit-identical to a separate lpx_contract call of the same precision.
+// The kernel (after a one-thread counter reset for the direct kernel; no
+// memset node) is captured once into a HIP graph on a library-owned stream;
 // lpx_batch_submit replays it on the caller's stream after copying the
 // (possibly updated) descriptor table.
 #include <hip/hip_runtime.h>
@@ -29,8 +38,10 @@ namespace lpx {
 namespace batchk {
 
 constexpr int kThreadsB = 256;
-constexpr int kChunk = 8;                         // tiles per counter fetch
-constexpr int64_t kLdsBudget = 48 * 1024;         // D staging budget per work-group
+constexpr int kChunk = 8;                         // tiles per counter fetch (direct kernel)
+constexpr int64_t kLdsBudget = 48 * 1024;         // D staging budget per work-group (direct)
+constexpr int kTileS = 32;                        // staged kernel: elements per tile
+constexpr int kPfS = 10;                          // staged u tile + staged output, D global
 
 struct Item {
     kern::ContractArgs a;
@@ -44,6 +55,7 @@ struct BatchArgs {
     unsigned long long* counter;
     int64_t total_tiles;
     int n;
+    int ldu, ldo;  // staged kernel: u and output ring slot strides (floats)
 };
 
 __global__ void reset_counter(unsigned long long* c) { *c = 0ull; }
@@ -90,18 +102,111 @@ __global__ __launch_bounds__(kThreadsB) void batch_kernel(BatchArgs b) {
     }
 }
 
+// Instance of tile t, starting the search at instance `cur` (a wave's tiles
+// come in increasing order).
+__device__ __forceinline__ int advance(const Item* items, int n, int64_t t, int cur) {
+    while (cur + 1 < n && items[cur + 1].tile_begin <= t) ++cur;
+    return cur;
+}
+
+template <int NTMAX>
+using ShapeS = kern::Shape<kTileS, NTMAX, kPfS>;
+
+template <int PREC, int LAYOUT, int NTMAX>
+__global__ __launch_bounds__((ShapeS<NTMAX>::THREADS)) void batch_staged(BatchArgs b) {
+    using S = ShapeS<NTMAX>;
+    static_assert(S::BPW == 1, "one block per compute wave and tile");
+    extern __shared__ __align__(16) unsigned char lds[];
+    float* ring = reinterpret_cast<float*>(lds);
+    float* oring = ring + 4 * b.ldu;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t t0 = blockIdx.x, g = gridDim.x;
+    const int64_t nmine = t0 < b.total_tiles ? (b.total_tiles - 1 - t0) / g + 1 : 0;
+    const int64_t niter = nmine + 1;  // store waves trail by one tile
+    struct Tile {
+        int inst, nvalid;
+        int64_t e0;
+    };
+    auto tile_at = [&](int64_t n, int& cur) {
+        const int64_t t = t0 + n * g;
+        cur = advance(b.items, b.n, t, cur);
+        const int64_t e0 = (t - b.items[cur].tile_begin) * kTileS;
+        const int64_t rest = b.items[cur].a.E - e0;
+        return Tile{cur, (int)(rest < kTileS ? rest : kTileS), e0};
+    };
+    int cur = 0;
+    if (wave >= S::NCW + S::NLW) {
+        const int sw = wave - S::NCW - S::NLW;
+        __syncthreads();
+        for (int64_t n = 0; n < niter; ++n) {
+            if (n >= 1) {
+                const Tile tt = tile_at(n - 1, cur);
+                kern::store_tile<LAYOUT, kTileS, S::NSW>(b.items[tt.inst].a,
+                                                         oring + ((n - 1) & 1) * b.ldo, tt.e0,
+                                                         tt.nvalid, sw, lane);
+            }
+            __syncthreads();
+        }
+    } else if (wave >= S::NCW) {
+        const int lw = wave - S::NCW;
+        kern::loader_loop<kern::Loader<kTileS, NTMAX, S::NLW>::PER_LANE>(
+            nmine, niter, [&](int64_t n) {
+                const Tile tt = tile_at(n, cur);
+                return kern::loader_issue<LAYOUT, kTileS, NTMAX, S::NLW>(
+                    b.items[tt.inst].a, ring + (n & 3) * b.ldu, tt.e0, tt.nvalid, lw, lane);
+            });
+    } else {
+        const int row0 = 16 * (wave / S::WPE), part = wave % S::WPE;
+        __syncthreads();
+        for (int64_t n = 0; n < niter; ++n) {
+            if (n < nmine) {
+                const Tile tt = tile_at(n, cur);
+                const kern::ContractArgs& a = b.items[tt.inst].a;
+                if (row0 < tt.nvalid) {
+                    auto run = [&](auto mask) {
+                        kern::block_compute<PREC, LAYOUT, NTMAX, false, true, kTileS, S::WPE, 2,
+                                            true, decltype(mask)::value>(
+                            a, nullptr, ring + (n & 3) * b.ldu, row0, tt.e0 + row0, part, lane,
+                            oring + (n & 1) * b.ldo);
+                    };
+                    if (PREC == LPX_FP32 && a.np_vec)  // uniform
+                        run(std::false_type());
+                    else
+                        run(std::true_type());
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 using BatchFn = void (*)(BatchArgs);
 
-template <int PREC>
+template <int PREC, bool STAGED, int LAYOUT, int NTMAX>
+BatchFn kernel_of() {
+    if constexpr (STAGED)
+        return &batch_staged<PREC, LAYOUT, NTMAX>;
+    else
+        return &batch_kernel<PREC, LAYOUT, NTMAX>;
+}
+
+template <int PREC, bool STAGED>
 BatchFn pick(int layout, int ntmax) {
     if (layout == LPX_ELEMENT_MAJOR) {
-        if (ntmax == 2) return &batch_kernel<PREC, LPX_ELEMENT_MAJOR, 2>;
-        if (ntmax == 4) return &batch_kernel<PREC, LPX_ELEMENT_MAJOR, 4>;
-        return &batch_kernel<PREC, LPX_ELEMENT_MAJOR, 8>;
+        if (ntmax == 2) return kernel_of<PREC, STAGED, LPX_ELEMENT_MAJOR, 2>();
+        if (ntmax == 4) return kernel_of<PREC, STAGED, LPX_ELEMENT_MAJOR, 4>();
+        return kernel_of<PREC, STAGED, LPX_ELEMENT_MAJOR, 8>();
     }
-    if (ntmax == 2) return &batch_kernel<PREC, LPX_DOF_MAJOR, 2>;
-    if (ntmax == 4) return &batch_kernel<PREC, LPX_DOF_MAJOR, 4>;
-    return &batch_kernel<PREC, LPX_DOF_MAJOR, 8>;
+    if (ntmax == 2) return kernel_of<PREC, STAGED, LPX_DOF_MAJOR, 2>();
+    if (ntmax == 4) return kernel_of<PREC, STAGED, LPX_DOF_MAJOR, 4>();
+    return kernel_of<PREC, STAGED, LPX_DOF_MAJOR, 8>();
+}
+
+template <bool STAGED>
+BatchFn pick_any(int precision, int layout, int ntmax) {
+    return precision == LPX_FP32 ? pick<LPX_FP32, STAGED>(layout, ntmax)
+         : precision == LPX_BF16 ? pick<LPX_BF16, STAGED>(layout, ntmax)
+                                 : pick<LPX_BF16X3, STAGED>(layout, ntmax);
 }
 
 }  // namespace batchk
@@ -122,6 +227,9 @@ struct lpx_batch {
     unsigned long long* counter = nullptr;
     int64_t total_tiles = 0, lds = 0;
     int grid = 0;
+    bool staged = false;  // staged kernel (32-element tiles) or direct kernel (16)
+    int tile_e = 16;
+    int ldu = 0, ldo = 0;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -150,6 +258,7 @@ void free_batch(lpx_batch* b) {
 // Fills the pinned table from the descriptors (shapes already validated).
 lpx_status fill_table(lpx_batch* b, const lpx_contract_desc* items, const lpx_record* recs) {
     int64_t tile = 0;
+    b->lds = b->staged ? 4 * (int64_t)b->ldu * 4 + 2 * (int64_t)b->ldo * 4 : 0;
     for (int32_t slot = 0; slot < b->n; ++slot) {
         const int32_t i = b->order[slot];
         const lpx_contract_desc& c = items[i];
@@ -165,7 +274,7 @@ lpx_status fill_table(lpx_batch* b, const lpx_contract_desc* items, const lpx_re
         it.a.u = c.u;
         it.a.out = c.out;
         it.a.E = c.E;
-        it.a.ntiles = ceil_div(c.E, 16);
+        it.a.ntiles = ceil_div(c.E, b->tile_e);
         it.a.K = c.K;
         it.a.Np = c.Np;
         it.a.nt = g.nt;
@@ -177,8 +286,9 @@ lpx_status fill_table(lpx_batch* b, const lpx_contract_desc* items, const lpx_re
         it.tile_begin = tile;
         const int64_t frag_bytes = b->precision == LPX_FP32 ? 4 : (b->precision == LPX_BF16 ? 16 : 32);
         const int64_t dbytes = g.nfrag * frag_bytes;
-        // D staged in LDS when the record keeps D on chip (LDS or registers)
-        it.d_lds = (r.prefetch & 5) != 0 && dbytes <= kLdsBudget;
+        // direct kernel: D staged in LDS when the record keeps D on chip
+        // (LDS or registers); the staged kernel reads D from global memory
+        it.d_lds = !b->staged && (r.prefetch & 5) != 0 && dbytes <= kLdsBudget;
         if (it.d_lds) b->lds = std::max(b->lds, dbytes);
         tile += it.a.ntiles;
     }
@@ -229,6 +339,34 @@ lpx_status create(const lpx_contract_desc* items, const lpx_record* recs, int32_
         b->Np.push_back(items[i].Np);
         b->E.push_back(items[i].E);
     }
+    // Staged kernel when its rings fit in LDS for every instance.
+    {
+        int64_t ldu = 0, ldo = 0;
+        lpx_record rs = default_record(precision);
+        rs.tile_e = kTileS;
+        rs.prefetch = kPfS;
+        bool fits = true;
+        for (int32_t i = 0; i < n && fits; ++i) {
+            ContractGeom g;
+            lpx_problem p{items[i].K, items[i].Np, items[i].E, layout, precision};
+            (void)p;
+            if (contract_geometry(items[i].K, items[i].Np, items[i].E, layout, rs, &g) != LPX_OK) {
+                fits = false;
+                break;
+            }
+            // the batch kernel is compiled for the batch's largest i-block
+            // count: its loader rounds set the u slot size
+            const ContractShape cs = contract_shape(kTileS, ntmax, kPfS);
+            const int64_t rounds = 256LL * cs.nlw * loader_per_lane(kTileS, ntmax, cs.nlw);
+            ldu = std::max({ldu, (int64_t)g.ldu, rounds});
+            ldo = std::max(ldo, (int64_t)g.ldo);
+        }
+        clear_error();
+        b->staged = fits && 4 * ldu * 4 + 2 * ldo * 4 <= kMaxLdsPerWorkgroup;
+        b->tile_e = b->staged ? kTileS : 16;
+        b->ldu = (int)ldu;
+        b->ldo = (int)ldo;
+    }
     b->order.resize(n);
     std::iota(b->order.begin(), b->order.end(), 0);
     std::stable_sort(b->order.begin(), b->order.end(), [&](int32_t x, int32_t y) {
@@ -246,28 +384,34 @@ lpx_status create(const lpx_contract_desc* items, const lpx_record* recs, int32_
         free_batch(b);
         return hip_err(e, "batch allocation");
     }
-    BatchFn fn = precision == LPX_FP32 ? pick<LPX_FP32>(layout, ntmax)
-               : precision == LPX_BF16 ? pick<LPX_BF16>(layout, ntmax)
-                                       : pick<LPX_BF16X3>(layout, ntmax);
+    BatchFn fn = b->staged ? pick_any<true>(precision, layout, ntmax)
+                           : pick_any<false>(precision, layout, ntmax);
+    const int threads = b->staged ? contract_shape(kTileS, ntmax, kPfS).threads : kThreadsB;
     DeviceInfo dev;
     if ((s = current_device_info(&dev)) != LPX_OK) { free_batch(b); return s; }
+    if (b->lds > 64 * 1024) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds);
+        if (e != hipSuccess) { free_batch(b); return hip_err(e, "batch LDS attribute"); }
+    }
     int nb = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(fn),
-                                                     kThreadsB, (size_t)b->lds);
+                                                     threads, (size_t)b->lds);
     if (e != hipSuccess) { free_batch(b); return hip_err(e, "batch occupancy"); }
     if (nb <= 0) { free_batch(b); return set_error(LPX_ERR_UNSUPPORTED, "batch kernel cannot be resident"); }
     int64_t grid = (int64_t)nb * dev.num_cu;
-    const int64_t need = ceil_div(b->total_tiles, kChunk);
+    const int64_t need = b->staged ? b->total_tiles : ceil_div(b->total_tiles, kChunk);
     b->grid = (int)std::max<int64_t>(1, std::min(grid, need));
 
-    // Capture [reset counter, batch kernel] once.
-    BatchArgs args{b->dev_items, b->counter, b->total_tiles, n};
+    // Capture the launch once: the direct kernel after its counter reset.
+    BatchArgs args{b->dev_items, b->counter, b->total_tiles, n, b->ldu, b->ldo};
     e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, b->cap_stream, b->counter);
+        if (!b->staged)
+            hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, b->cap_stream, b->counter);
         void* kargs[] = {&args};
         hipError_t le = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(b->grid),
-                                        dim3(kThreadsB), kargs, (size_t)b->lds, b->cap_stream);
+                                        dim3(threads), kargs, (size_t)b->lds, b->cap_stream);
         e = hipStreamEndCapture(b->cap_stream, &b->graph);
         if (e == hipSuccess && le != hipSuccess) e = le;
     }
@@ -346,11 +490,12 @@ lpx_status lpx_batch_submit(const lpx_contract_desc* items, const lpx_record* re
     }
 }
 
-lpx_status lpx_batch_info(const lpx_batch* b, int64_t* total_tiles, int32_t* grid,
-                          int64_t* lds_bytes) {
+lpx_status lpx_batch_info(const lpx_batch* b, int64_t* total_tiles, int32_t* tile_e,
+                          int32_t* grid, int64_t* lds_bytes) {
     clear_error();
     if (!b) return set_error(LPX_ERR_INVALID_ARG, "batch is NULL");
     if (total_tiles) *total_tiles = b->total_tiles;
+    if (tile_e) *tile_e = b->tile_e;
     if (grid) *grid = b->grid;
     if (lds_bytes) *lds_bytes = b->lds;
     return LPX_OK;

@@ -484,6 +484,43 @@ __device__ __forceinline__ bool loader_issue(const ContractArgs& a, float* slot,
     }
 }
 
+// Loader-wave loop, shared by the contraction and batch kernels.  issue(n)
+// starts the loads of the work-group's n-th tile into u slot n & 3 and
+// returns whether the tile was regular (PL 16-byte loads).  Three tiles are
+// in flight: in iteration n the loader starts tile n+3 (its slot was read by
+// the compute waves in iteration n-1), then waits until tile n+1 has landed;
+// one barrier per iteration, `niter` iterations after a prologue barrier.
+// The waits and barriers are explicit: a loader wave touches no other LDS.
+template <int PL, typename Issue>
+__device__ __forceinline__ void loader_loop(int64_t nmine, int64_t niter, Issue&& issue) {
+    unsigned regular = 0xf;  // bit s: the tile in slot s was regular
+    auto start = [&](int64_t n) {
+        const bool r = issue(n);
+        regular = (regular & ~(1u << (n & 3))) | ((unsigned)r << (n & 3));
+    };
+    // Wait for tile m: the tiles after it that are in flight must all be
+    // regular for a partial wait; otherwise wait for everything.
+    auto wait_for = [&](int64_t m) {
+        const int64_t later = (nmine - 1 - m) < 2 ? (nmine - 1 - m) : 2;
+        const bool reg = (later < 1 || ((regular >> ((m + 1) & 3)) & 1)) &&
+                         (later < 2 || ((regular >> ((m + 2) & 3)) & 1));
+        if (reg && later == 2)
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm(2 * PL));
+        else if (reg && later == 1)
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm(PL));
+        else
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    };
+    for (int64_t n = 0; n < 3 && n < nmine; ++n) start(n);
+    if (nmine > 0) wait_for(0);
+    __builtin_amdgcn_s_barrier();
+    for (int64_t n = 0; n < niter; ++n) {
+        if (n + 3 < nmine) start(n + 3);
+        if (n + 1 < nmine) wait_for(n + 1);
+        __builtin_amdgcn_s_barrier();
+    }
+}
+
 // ------------------------------------------------------ building blocks
 // D in MFMA operand order, converted to the operand precision, written to
 // LDS by the NTHREADS threads of a work-group (caller adds the barrier).
@@ -811,7 +848,6 @@ __device__ __forceinline__ void block_compute_dreg(const ContractArgs& a,
                                                    const float* ut, int row0, int64_t eb0,
                                                    int part, int lane, float* os = nullptr) {
     using DR = DRegs<PREC, NTMAX, WPE>;
-    const int npairs = a.K * a.nt;
     f4 acc[DR::PMAX];
 #pragma unroll
     for (int q = 0; q < DR::PMAX; ++q) acc[q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -988,40 +1024,12 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
                 }
             }
         } else if (wave >= S::NCW) {
-            // Three tiles in flight: at iteration n the loader issues tile
-            // n+3 into slot (n+3)&3 (read by the compute waves in iteration
-            // n-1), then waits until tile n+1 has landed.  The waits and
-            // barriers are explicit: nothing else here touches LDS.
-            constexpr int PL = Loader<TILE_E, NTMAX, S::NLW>::PER_LANE;
             const int lw = wave - S::NCW;
-            unsigned regular = 0xf;  // bit s: the tile in slot s was regular
-            auto issue = [&](int64_t n) {
+            loader_loop<Loader<TILE_E, NTMAX, S::NLW>::PER_LANE>(nmine, niter, [&](int64_t n) {
                 const int64_t tile = t0 + n * g;
-                const bool r = loader_issue<LAYOUT, TILE_E, NTMAX, S::NLW>(
+                return loader_issue<LAYOUT, TILE_E, NTMAX, S::NLW>(
                     a, ring + (n & 3) * a.ldu, tile * TILE_E, nvalid_of(tile), lw, lane);
-                regular = (regular & ~(1u << (n & 3))) | ((unsigned)r << (n & 3));
-            };
-            // Wait for tile m: the tiles after it that are in flight must all
-            // be regular for a partial wait; otherwise wait for everything.
-            auto wait_for = [&](int64_t m) {
-                const int64_t later = (nmine - 1 - m) < 2 ? (nmine - 1 - m) : 2;
-                const bool reg = (later < 1 || ((regular >> ((m + 1) & 3)) & 1)) &&
-                                 (later < 2 || ((regular >> ((m + 2) & 3)) & 1));
-                if (reg && later == 2)
-                    __builtin_amdgcn_s_waitcnt(vmcnt_imm(2 * PL));
-                else if (reg && later == 1)
-                    __builtin_amdgcn_s_waitcnt(vmcnt_imm(PL));
-                else
-                    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
-            };
-            for (int64_t n = 0; n < 3 && n < nmine; ++n) issue(n);
-            if (nmine > 0) wait_for(0);
-            __builtin_amdgcn_s_barrier();
-            for (int64_t n = 0; n < niter; ++n) {
-                if (n + 3 < nmine) issue(n + 3);
-                if (n + 1 < nmine) wait_for(n + 1);
-                __builtin_amdgcn_s_barrier();
-            }
+            });
         } else {
             // Compute wave: part `part` of blocks eblk0, eblk0 + NCW/WPE, ...
             // (BPW blocks of each tile).

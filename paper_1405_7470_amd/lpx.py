@@ -152,6 +152,7 @@ def lib():
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), vp]
         L.lpx_batch_submit.restype = st
         L.lpx_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
         L.lpx_batch_info.restype = st
         L.lpx_batch_destroy.argtypes = [vp]
@@ -420,9 +421,10 @@ class Batch:
         self._submit(items if items is not None else self._keep, None, stream)
 
     def info(self):
-        t, g, l = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
-        _check(lib().lpx_batch_info(self.handle, ctypes.byref(t), ctypes.byref(g), ctypes.byref(l)))
-        return {"tiles": t.value, "grid": g.value, "lds_bytes": l.value}
+        t, te, g, l = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().lpx_batch_info(self.handle, ctypes.byref(t), ctypes.byref(te), ctypes.byref(g),
+                                    ctypes.byref(l)))
+        return {"tiles": t.value, "tile_e": te.value, "grid": g.value, "lds_bytes": l.value}
 
     def destroy(self):
         if self.handle:

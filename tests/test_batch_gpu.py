@@ -54,7 +54,9 @@ def test_batch_replay_with_new_buffers_and_sentinel():
     b = lpx.Batch(items, None)
     torch.cuda.synchronize()
     info = b.info()
-    assert info["tiles"] == sum((E + 15) // 16 for _, E in shapes)
+    te = info["tile_e"]
+    assert te == 32  # element-major, K = 3, Np <= 120: the staged rings fit
+    assert info["tiles"] == sum((E + te - 1) // te for _, E in shapes)
     # new inputs and NaN-filled outputs, same shapes: replay the graph
     host2, items2 = make_items(shapes, seed=6)
     for (_, _, out, _) in items2:
@@ -100,4 +102,24 @@ def test_batch_512_instances_sampled():
         Dh, uh = host[i]
         n = min(64, uh.shape[0])
         check_against_oracle(Dh, uh, as_em(out[:, :n, :], "em"), "em", "fp32", e0=0)
+    b.destroy()
+
+
+def test_direct_kernel_when_staged_rings_do_not_fit():
+    """K = 6 at Np = 120 needs 2 x 6 x 32 x 120 floats of output ring, more
+    than LDS holds with the u ring: the batch falls back to 16-element tiles
+    pulled from a counter, still bit-identical to separate calls."""
+    shapes = [(120, 700), (56, 333), (10, 1500), (84, 65)]
+    host, items = make_items(shapes, seed=9, K=6)
+    recs = [lpx.record("fp32", 32, 1, 2)] * len(shapes)
+    b = lpx.Batch(items, recs)
+    torch.cuda.synchronize()
+    info = b.info()
+    assert info["tile_e"] == 16
+    assert info["tiles"] == sum((E + 15) // 16 for _, E in shapes)
+    for (D, u, out, lay), rec, (Dh, uh) in zip(items, recs, host):
+        ref = lpx.contract(D, u, layout=lay, record=lpx.record("fp32", 16, 0, 1))
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+        check_against_oracle(Dh, uh, as_em(out, lay), lay, "fp32")
     b.destroy()
