@@ -116,7 +116,7 @@ def extras(stream, learned_picker=None):
         B = torch.randn((Kd, N), device="cuda", generator=g)
         C = torch.empty((M, N), device="cuda")
         for prec, tiles in (("fp32", (128, 128, 64)), ("bf16", (128, 128, 64)),
-                            ("bf16x3", (128, 128, 32))):
+                            ("bf16x3", (128, 128, 64))):
             rec = lpx.record(prec, gemm=tiles)
             t = _event_time(lambda: lpx.gemm(A, B, C, record=rec, stream=stream), 5, stream)
             tf = 2 * M * N * Kd / t / 1e12

@@ -230,11 +230,16 @@ lpx_status lpx_contract_validate(const lpx_contract_desc* c, const lpx_record* r
  * `stream`.  The record supplies the precision (as for lpx_contract; the
  * products follow the same FP32 / BF16 / BF16X3 rules, FP32 accumulation)
  * and the tiling: gemm_tm x gemm_tn tile of C per work-group, gemm_tk-deep
- * k slabs staged in LDS (0 = 128 x 128 x 32).  Built tilings: 64x64x32,
- * 64x64x64, 128x128x32, 128x128x64, 128x64x32, 64x128x32, and for FP32/BF16
- * also 256x128x32, 128x256x32, 256x256x32; others return
- * LPX_ERR_UNSUPPORTED.  C is overwritten (no alpha/beta).  rec = NULL means
- * FP32 with the default tiling.  Errors as for lpx_contract. */
+ * k slabs staged in LDS (0 = 128 x 128 x 32 for FP32, 128 x 128 x 64 for
+ * BF16 / BF16X3).  Built tilings: 64x64x32, 64x64x64, 128x128x32,
+ * 128x128x64, 128x64x32, 64x128x32, and for FP32/BF16 also 256x128x32,
+ * 128x256x32, 256x256x32; others return LPX_ERR_UNSUPPORTED.  BF16 / BF16X3
+ * at 128x128x64 (with K > 0) first split both operands once into
+ * K-contiguous bf16 planes (B transposed) in stream-ordered workspace
+ * (hipMallocAsync on `stream`, freed the same way), then stream the planes
+ * into LDS with direct global-to-LDS loads; the other tilings convert the
+ * FP32 operands slab by slab.  C is overwritten (no alpha/beta).  rec = NULL
+ * means FP32 with the default tiling.  Errors as for lpx_contract. */
 lpx_status lpx_gemm(const lpx_gemm_desc* g, const lpx_record* rec, void* stream);
 
 /* Every pre-launch check of lpx_gemm, without any HIP call. */

@@ -254,9 +254,11 @@ GemmFn pick(int tm, int tn, int tk, int* lds) {
 }  // namespace gemm
 
 lpx_status gemm_tiles(const lpx_record& r, int* tm, int* tn, int* tk) {
+    // default: 128 x 128 x 64 for the reduced precisions (the pre-split
+    // path), 128 x 128 x 32 for fp32
     *tm = r.gemm_tm ? r.gemm_tm : 128;
     *tn = r.gemm_tn ? r.gemm_tn : 128;
-    *tk = r.gemm_tk ? r.gemm_tk : 32;
+    *tk = r.gemm_tk ? r.gemm_tk : (r.precision == LPX_FP32 ? 32 : 64);
     int lds = 0;
     void* fn = nullptr;
     switch (r.precision) {
@@ -273,10 +275,16 @@ lpx_status gemm_tiles(const lpx_record& r, int* tm, int* tn, int* tk) {
     return LPX_OK;
 }
 
+lpx_status launch_gemm_split(const lpx_gemm_desc& d, int precision, void* stream);
+
 lpx_status launch_gemm(const lpx_gemm_desc& d, const lpx_record& r, void* stream) {
     int tm, tn, tk, lds = 0;
     lpx_status s = gemm_tiles(r, &tm, &tn, &tk);
     if (s != LPX_OK) return s;
+    // bf16 / bf16x3 at 128 x 128 x 64: operands split once into bf16 planes,
+    // then the direct-to-LDS kernel (nothing to split when K == 0)
+    if (r.precision != LPX_FP32 && tm == 128 && tn == 128 && tk == 64 && d.K > 0)
+        return launch_gemm_split(d, r.precision, stream);
     gemm::GemmFn fn = nullptr;
     switch (r.precision) {
         case LPX_FP32: fn = gemm::pick<LPX_FP32>(tm, tn, tk, &lds); break;

@@ -77,11 +77,30 @@ def test_gemm_full_size_sampled_rows(shape):
     A, B = inputs.gemm_inputs(M, N, K, seed=0)
     Ad, Bd = to_dev(A), to_dev(B)
     rows = [0, 1, M // 2 + 17, M - 1]
-    for precision in ("fp32", "bf16", "bf16x3"):
-        rec = lpx.record(precision, gemm=(128, 128, 32))
-        print(f"case: gemm full {shape} {precision}", flush=True)
+    for precision, tiles in (("fp32", (128, 128, 32)), ("bf16", (128, 128, 32)),
+                             ("bf16x3", (128, 128, 32)), ("bf16", (128, 128, 64)),
+                             ("bf16x3", (128, 128, 64))):
+        rec = lpx.record(precision, gemm=tiles)
+        print(f"case: gemm full {shape} {lpx.describe(rec)}", flush=True)
         C = lpx.gemm(Ad, Bd, record=rec)
         torch.cuda.synchronize()
         for m in rows:
             check(C[m:m + 1].double().cpu().numpy(), A, B, precision, m0=m)
         del C
+
+
+@pytest.mark.parametrize("precision", ("bf16", "bf16x3"))
+def test_gemm_presplit_strided_and_default(precision):
+    """The pre-split path (the reduced precisions' default tiling) with row
+    strides that are not multiples of 4 and a ragged K, and the untouched
+    columns of C past N."""
+    A, B = inputs.gemm_inputs(130, 70, 45, seed=4)
+    Ab = torch.zeros((130, 47), device="cuda")
+    Ab[:, :45] = to_dev(A)
+    Bb = torch.zeros((45, 73), device="cuda")
+    Bb[:, :70] = to_dev(B)
+    Cb = torch.full((130, 75), 7.0, device="cuda")
+    lpx.gemm(Ab[:, :45], Bb[:, :70], C=Cb[:, :70], record=lpx.record(precision))
+    torch.cuda.synchronize()
+    check(Cb[:, :70].double().cpu().numpy(), A, B, precision)
+    assert bool((Cb[:, 70:] == 7.0).all())
