@@ -841,22 +841,76 @@ __device__ __forceinline__ void load_dregs(const ContractArgs& a, int part, int 
     }
 }
 
-template <int PREC, int LAYOUT, int NTMAX, bool PF_U, int TILE_E, int WPE, bool PF_O = false,
-          bool MASK = true>
-__device__ __forceinline__ void block_compute_dreg(const ContractArgs& a,
-                                                   const DRegs<PREC, NTMAX, WPE>& d,
-                                                   const float* ut, int row0, int64_t eb0,
-                                                   int part, int lane, float* os = nullptr) {
+// u operands of one 16-element block for the register-D routine: fp32 quads
+// and the steps after the last quad, or bf16 steps.
+template <int PREC, int NTMAX, int WPE>
+struct UOps {
+    using DR = DRegs<PREC, NTMAX, WPE>;
+    static constexpr int NQ = PREC == LPX_FP32 ? DR::NS / 4 : 1;
+    static constexpr int NSB = PREC == LPX_FP32 ? 1 : DR::NS;
+    f4 uq[NQ];
+    Frag<PREC> ut3[DR::NT];
+    Frag<PREC> uf[NSB];
+};
+
+// Every u operand of a block is read at once, without branches (reads past
+// the last step are in bounds and, where they can reach j >= Np, masked),
+// so the reads overlap one another and the wave waits once.
+template <int PREC, int LAYOUT, int NTMAX, bool PF_U, int TILE_E, int WPE, bool MASK>
+__device__ __forceinline__ UOps<PREC, NTMAX, WPE> dreg_read(const ContractArgs& a, const float* ut,
+                                                            int row0, int64_t eb0, int lane) {
+    using DR = DRegs<PREC, NTMAX, WPE>;
+    UOps<PREC, NTMAX, WPE> o;
+    if constexpr (PREC == LPX_FP32) {
+        const int nq = a.nsteps >> 2;
+#pragma unroll
+        for (int Q = 0; Q < o.NQ; ++Q) {
+            if constexpr (PF_U)
+                o.uq[Q] = u_quad_lds<LAYOUT, TILE_E, MASK>(ut, a.Np, a.np_vec, row0, Q, lane);
+            else
+                o.uq[Q] = u_quad_global<LAYOUT>(a, eb0, Q, lane);
+        }
+#pragma unroll
+        for (int m = 0; m < DR::NT; ++m) {
+            if constexpr (PF_U)
+                o.ut3[m] = u_frag_lds<PREC, LAYOUT, TILE_E, MASK>(ut, a.Np, a.np_vec, row0,
+                                                                  4 * nq + m, 4 * nq, lane);
+            else
+                o.ut3[m] = u_frag_global<PREC, LAYOUT>(a, eb0, 4 * nq + m, lane);
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < DR::NS; ++s) {
+            // nsteps == NS for every Np of the NTMAX bucket, so only the last
+            // compiled step straddles Np
+            if constexpr (PF_U) {
+                if (s == DR::NS - 1)
+                    o.uf[s] = u_frag_lds<PREC, LAYOUT, TILE_E, true>(ut, a.Np, a.np_vec, row0, s,
+                                                                     0, lane);
+                else
+                    o.uf[s] = u_frag_lds<PREC, LAYOUT, TILE_E, false>(ut, a.Np, a.np_vec, row0,
+                                                                      s, 0, lane);
+            } else {
+                o.uf[s] = u_frag_global<PREC, LAYOUT>(a, eb0, s, lane);
+            }
+        }
+    }
+    return o;
+}
+
+// The MFMA chains of one block from its u operands, then the write-back.
+// MFMAs run for every held pair (a pair past the last one holds a
+// duplicate and is never stored), so the only branches are one per k-step
+// group, with constant register indices throughout.
+template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int WPE, bool PF_O>
+__device__ __forceinline__ void dreg_mma_store(const ContractArgs& a,
+                                               const DRegs<PREC, NTMAX, WPE>& d,
+                                               const UOps<PREC, NTMAX, WPE>& o, int row0,
+                                               int64_t eb0, int part, int lane, float* os) {
     using DR = DRegs<PREC, NTMAX, WPE>;
     f4 acc[DR::PMAX];
 #pragma unroll
     for (int q = 0; q < DR::PMAX; ++q) acc[q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-    // Every u operand is read before the first MFMA, without branches
-    // (reads past the last step are in bounds and zero-selected), so the
-    // reads overlap one another and the wave waits once.  MFMAs run for
-    // every held pair (a pair past the last one holds a duplicate and is
-    // never stored), so the only branches are one per k-step group, with
-    // constant register indices throughout.
     auto mma_all = [&](const Frag<PREC> (&df)[DR::PMAX], const Frag<PREC>& uf) {
 #pragma unroll
         for (int q = 0; q < DR::PMAX; ++q) {
@@ -867,35 +921,17 @@ __device__ __forceinline__ void block_compute_dreg(const ContractArgs& a,
         }
     };
     if constexpr (PREC == LPX_FP32) {
-        constexpr int NQ = DR::NS / 4;  // quads of the compiled bound
         const int nq = a.nsteps >> 2;
         const int ntail = a.nsteps - 4 * nq;  // 0..3 steps after the last quad
-        f4 uq[NQ];
-        Frag<PREC> ut3[DR::NT];
 #pragma unroll
-        for (int Q = 0; Q < NQ; ++Q) {
-            if constexpr (PF_U)
-                uq[Q] = u_quad_lds<LAYOUT, TILE_E, MASK>(ut, a.Np, a.np_vec, row0, Q, lane);
-            else
-                uq[Q] = u_quad_global<LAYOUT>(a, eb0, Q, lane);
-        }
-#pragma unroll
-        for (int m = 0; m < DR::NT; ++m) {
-            if constexpr (PF_U)
-                ut3[m] = u_frag_lds<PREC, LAYOUT, TILE_E, MASK>(ut, a.Np, a.np_vec, row0,
-                                                                4 * nq + m, 4 * nq, lane);
-            else
-                ut3[m] = u_frag_global<PREC, LAYOUT>(a, eb0, 4 * nq + m, lane);
-        }
-#pragma unroll
-        for (int Q = 0; Q < NQ; ++Q) {
+        for (int Q = 0; Q < o.NQ; ++Q) {
             if (Q < nq) {
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     Frag<PREC> df[DR::PMAX];
 #pragma unroll
                     for (int q = 0; q < DR::PMAX; ++q) df[q] = d.f[q][4 * Q + m];
-                    mma_all(df, Frag<PREC>{uq[Q][m]});
+                    mma_all(df, Frag<PREC>{o.uq[Q][m]});
                 }
             }
         }
@@ -905,32 +941,17 @@ __device__ __forceinline__ void block_compute_dreg(const ContractArgs& a,
                 Frag<PREC> df[DR::PMAX];
 #pragma unroll
                 for (int q = 0; q < DR::PMAX; ++q) df[q] = d.t[q][m];
-                mma_all(df, ut3[m]);
+                mma_all(df, o.ut3[m]);
             }
         }
     } else {
-        Frag<PREC> uf[DR::NS];
-#pragma unroll
-        for (int s = 0; s < DR::NS; ++s) {
-            if constexpr (PF_U)
-                // nsteps == NS for every Np of the NTMAX bucket, so only the
-                // last compiled step straddles Np
-                if (s == DR::NS - 1)
-                    uf[s] = u_frag_lds<PREC, LAYOUT, TILE_E, true>(ut, a.Np, a.np_vec, row0, s, 0,
-                                                                   lane);
-                else
-                    uf[s] = u_frag_lds<PREC, LAYOUT, TILE_E, false>(ut, a.Np, a.np_vec, row0, s, 0,
-                                                                    lane);
-            else
-                uf[s] = u_frag_global<PREC, LAYOUT>(a, eb0, s, lane);
-        }
 #pragma unroll
         for (int s = 0; s < DR::NS; ++s) {
             if (s < a.nsteps) {
                 Frag<PREC> df[DR::PMAX];
 #pragma unroll
                 for (int q = 0; q < DR::PMAX; ++q) df[q] = d.f[q][s];
-                mma_all(df, uf[s]);
+                mma_all(df, o.uf[s]);
             }
         }
     }
@@ -938,6 +959,16 @@ __device__ __forceinline__ void block_compute_dreg(const ContractArgs& a,
         stage_pairs<LAYOUT, DR::PMAX, WPE, TILE_E>(a, acc, part, row0, os, lane);
     else
         store_pairs<LAYOUT, DR::PMAX, WPE>(a, acc, part, eb0, lane);
+}
+
+template <int PREC, int LAYOUT, int NTMAX, bool PF_U, int TILE_E, int WPE, bool PF_O = false,
+          bool MASK = true>
+__device__ __forceinline__ void block_compute_dreg(const ContractArgs& a,
+                                                   const DRegs<PREC, NTMAX, WPE>& d,
+                                                   const float* ut, int row0, int64_t eb0,
+                                                   int part, int lane, float* os = nullptr) {
+    const auto o = dreg_read<PREC, LAYOUT, NTMAX, PF_U, TILE_E, WPE, MASK>(a, ut, row0, eb0, lane);
+    dreg_mma_store<PREC, LAYOUT, NTMAX, TILE_E, WPE, PF_O>(a, d, o, row0, eb0, part, lane, os);
 }
 
 // ------------------------------------------------------------ the kernel
@@ -1063,9 +1094,43 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
                     else
                         run(std::true_type());
                 };
+                // Four blocks per tile (one compute wave per SIMD): block b+1's
+                // operands are read before block b's MFMAs, so the wave's own
+                // MFMAs hide its LDS latency.
+                auto pipelined = [&](int64_t n) {
+                    const int64_t tile = t0 + n * g;
+                    const int nv = nvalid_of(tile);
+                    auto run = [&](auto mask) {
+                        constexpr bool M = decltype(mask)::value;
+                        const float* ut = ring + (n & 3) * a.ldu;
+                        float* os = oring + (n & 1) * a.ldo;
+                        auto row = [&](int b) { return 16 * (eblk0 + b * BSTRIDE); };
+                        auto o = dreg_read<PREC, LAYOUT, NTMAX, true, TILE_E, S::WPE, M>(
+                            a, ut, row(0), tile * TILE_E + row(0), lane);
+#pragma unroll
+                        for (int b = 0; b < S::BPW; ++b) {
+                            const auto cur = o;
+                            if (b + 1 < S::BPW)
+                                o = dreg_read<PREC, LAYOUT, NTMAX, true, TILE_E, S::WPE, M>(
+                                    a, ut, row(b + 1), tile * TILE_E + row(b + 1), lane);
+                            if (row(b) < nv)
+                                dreg_mma_store<PREC, LAYOUT, NTMAX, TILE_E, S::WPE, PF_O>(
+                                    a, d, cur, row(b), tile * TILE_E + row(b), part, lane, os);
+                        }
+                    };
+                    if (PREC == LPX_FP32 && a.np_vec)  // uniform
+                        run(std::false_type());
+                    else
+                        run(std::true_type());
+                };
                 __syncthreads();
                 for (int64_t n = 0; n < niter; ++n) {
-                    if (n < nmine) tile_work(block, n);
+                    if (n < nmine) {
+                        if constexpr (S::BPW == 4)
+                            pipelined(n);
+                        else
+                            tile_work(block, n);
+                    }
                     __syncthreads();
                 }
             } else {

@@ -29,9 +29,10 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // Work-group shape of a contraction kernel instance (host and device agree
 // on it through this one function).  Without a staged u tile (prefetch bit
 // 1 clear): four waves per 16-element block, splitting its (k, i-block)
-// pairs.  With one: min(4 * tile_e/16, 8) compute waves, four per block,
-// each taking bpw = tile_e / (4 * ncw) blocks of every tile (two at
-// tile_e = 64, so a wave does more MFMA work per work-group barrier); nlw
+// pairs.  With one: min(4 * tile_e/16, 8) compute waves (4 when D is in
+// registers and tile_e = 64), four per block, each taking bpw = 4 * nb /
+// ncw blocks of every tile (two or four at tile_e = 64, so a wave does more
+// MFMA work per work-group barrier); nlw
 // loader waves (1, or tile_e * ntmax / 128 when larger, so that a loader
 // wave loads at most 8 16-byte chunks per lane and tile); and with a staged
 // output tile (bit 3) four store waves: the write-back is three quarters
@@ -43,7 +44,11 @@ constexpr ContractShape contract_shape(int tile_e, int ntmax, int prefetch) {
     const bool pf_u = (prefetch & 2) != 0;
     const bool pf_o = (prefetch & 8) != 0;
     const int nb = tile_e / 16;
-    const int ncw = pf_u ? (4 * nb < 8 ? 4 * nb : 8) : 4 * nb;
+    // D in registers at tile_e = 64: one compute wave per SIMD taking all
+    // four blocks of its part (its registers allow reading the next block's
+    // operands during the current block's MFMAs)
+    const int ncw_cap = (prefetch & 4) && tile_e == 64 ? 4 : 8;
+    const int ncw = pf_u ? (4 * nb < ncw_cap ? 4 * nb : ncw_cap) : 4 * nb;
     const int nlw = pf_u ? (tile_e * ntmax / 128 > 1 ? tile_e * ntmax / 128 : 1) : 0;
     const int nsw = pf_o ? 4 : 0;
     return ContractShape{ncw, 4, 4 * nb / ncw, nlw, nsw, 64 * (ncw + nlw + nsw)};
