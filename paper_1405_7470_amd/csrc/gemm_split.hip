@@ -54,13 +54,25 @@ __global__ __launch_bounds__(256) void split_rows(const float* __restrict__ A, i
     if (t >= M * nc) return;
     const int64_t m = t / nc, k0 = (t % nc) * 8;
     const float* row = A + m * lda;
+    float x[8];
+    if ((lda & 3) == 0 && k0 + 8 <= K) {  // two 16-byte loads (rows 16-byte aligned)
+        const f4 a = *reinterpret_cast<const f4*>(row + k0);
+        const f4 b = *reinterpret_cast<const f4*>(row + k0 + 4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            x[q] = a[q];
+            x[q + 4] = b[q];
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) x[q] = k0 + q < K ? row[k0 + q] : 0.0f;
+    }
     bf16x8 h, l;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        const float x = k0 + q < K ? row[k0 + q] : 0.0f;
-        const __bf16 hq = (__bf16)x;
+        const __bf16 hq = (__bf16)x[q];
         h[q] = hq;
-        l[q] = (__bf16)(x - (float)hq);
+        l[q] = (__bf16)(x[q] - (float)hq);
     }
     *reinterpret_cast<bf16x8*>(out + m * Kp + k0) = h;
     if constexpr (PLANES == 2) *reinterpret_cast<bf16x8*>(out + M * Kp + m * Kp + k0) = l;
@@ -140,14 +152,37 @@ __device__ __forceinline__ bf16x8 frag(const unsigned char* slab, int r0, int s2
     return *reinterpret_cast<const bf16x8*>(slab + 16 * slab_pos(r, c));
 }
 
+// Work-group -> C tile.  Work-groups are dispatched to the eight XCDs in
+// turn (work-group b to XCD b % 8), each with its own L2.  Work-group b gets
+// tile t = (b % 8) * (ntiles / 8) + b / 8, so an XCD works through one
+// contiguous eighth of the tiles; inside it, tiles go in groups of eight
+// tile rows, column by column, so the work-groups resident on one XCD at a
+// time cover a square patch of C and share their A rows and B columns in
+// that XCD's L2.  (Identity mapping when the tile count is not a multiple
+// of 8.)
+constexpr int kXcds = 8, kGroupM = 8;
+__device__ __forceinline__ void tile_of(int64_t b, int64_t ntiles, int64_t tiles_n, int64_t* tm,
+                                        int64_t* tn) {
+    int64_t t = b;
+    if (ntiles % kXcds == 0) t = (b % kXcds) * (ntiles / kXcds) + b / kXcds;
+    const int64_t tiles_m = ntiles / tiles_n;
+    const int64_t per_group = kGroupM * tiles_n;
+    const int64_t first_m = (t / per_group) * kGroupM;
+    const int64_t gsize = tiles_m - first_m < kGroupM ? tiles_m - first_m : kGroupM;
+    const int64_t r = t % per_group;
+    *tm = first_m + r % gsize;
+    *tn = r / gsize;
+}
+
 template <int PLANES>
 __global__ __launch_bounds__(256) void gemm_split_kernel(Args g) {
     extern __shared__ __align__(16) unsigned char lds[];
     // stage s: A planes then B planes, SLAB_BYTES each
     constexpr int STAGE = 2 * PLANES * SLAB_BYTES;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t m0 = (int64_t)(blockIdx.x / g.tiles_n) * TM;
-    const int64_t n0 = (int64_t)(blockIdx.x % g.tiles_n) * TN;
+    int64_t tm, tn;
+    tile_of(blockIdx.x, gridDim.x, g.tiles_n, &tm, &tn);
+    const int64_t m0 = tm * TM, n0 = tn * TN;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
 
     auto issue = [&](int64_t kt) {
