@@ -99,9 +99,9 @@ typedef int32_t lpx_status;
  *              that keep two tiles in flight (a two-slot LDS ring, one
  *              work-group barrier per tile);
  *              bit 2: D is precomputed into private memory -- each wave
- *              keeps the D fragments of its own (k, i-block) pairs in
- *              registers for the whole kernel (Np <= 64 and K*ceil(Np/16)
- *              <= 12, else LPX_ERR_UNSUPPORTED; unroll does not apply, the
+ *              keeps the D fragments of its own 16-row blocks of the
+ *              stacked operators in registers for the whole kernel
+ *              (Np <= 64 and ceil(K*Np/16) <= 12, else LPX_ERR_UNSUPPORTED; unroll does not apply, the
  *              k-step loop is fully unrolled);
  *              bit 3 (needs bit 1): each output tile is staged in LDS and
  *              written back by dedicated store waves with contiguous
@@ -330,8 +330,8 @@ lpx_status lpx_tune_cache_clear(void);
 /* The 12 features of (problem, record), into the host array out[12]:
  * log2 Np, log2 E, K, layout, log2 tile_e, D storage, staging (0 none,
  * 1 u tile, 2 u and output tiles),
- * log2 unroll, precision code, MFMA row padding (16*ceil(Np/16) - Np) /
- * (16*ceil(Np/16)), log2 of the element-tile count, dynamic LDS bytes per
+ * log2 unroll, precision code, MFMA row padding of the stacked operator
+ * rows (16*ceil(K*Np/16) - K*Np) / (16*ceil(K*Np/16)), log2 of the element-tile count, dynamic LDS bytes per
  * work-group / 160 KiB.  The D-prefetch feature is the storage of D:
  * 0 global, 1 LDS, 2 registers.  Needs 0 < K, 0 < Np <= 128, 0 < E. */
 lpx_status lpx_features(const lpx_problem* p, const lpx_record* r, float* out);

@@ -84,7 +84,11 @@ lpx_status contract_geometry(int K, int Np, int64_t E, int layout,
     g->threads = contract_shape(r.tile_e, g->ntmax, r.prefetch).threads;
     g->nsteps = (int)ceil_div(Np, g->kstep);
     g->ntiles = ceil_div(E, r.tile_e);
-    g->nfrag = (int64_t)K * g->nt * g->nsteps * 64;
+    if ((int64_t)K * Np > (int64_t)INT32_MAX - 16)
+        return set_error(LPX_ERR_UNSUPPORTED, "K*Np = %lld stacked operator rows exceed 2^31 - 16",
+                         (long long)K * Np);
+    g->nrb = (int)ceil_div((int64_t)K * Np, 16);
+    g->nfrag = (int64_t)g->nrb * g->nsteps * 64;
     // A staged u tile is a raw copy of the tile (tile_e * Np floats) plus
     // slack for reads of padding columns up to the next multiple of 32.
     // u ring slot stride in floats: a raw tile copy with slack for reads of
@@ -104,14 +108,14 @@ lpx_status contract_geometry(int K, int Np, int64_t E, int layout,
                                                     : (int64_t)K * Np * (r.tile_e + 4);
     g->ldo = (r.prefetch & 8) && ldo <= kMaxLdsPerWorkgroup ? (int)ldo : 0;
     if (r.prefetch & 4) {
-        // D in registers: each wave holds the fragments of its pairs, which
-        // needs Np <= 64, four waves per 16-element block and all of a
-        // block's pairs in one chunk.
+        // D in registers: each wave holds the fragments of its row blocks,
+        // which needs Np <= 64, four waves per 16-element block and all of
+        // the row blocks in one chunk.
         const ContractShape cs = contract_shape(r.tile_e, g->ntmax, r.prefetch);
         const int pmax = (3 * g->ntmax + cs.wpe - 1) / cs.wpe;
-        if (g->ntmax > 4 || cs.wpe != 4 || (int64_t)K * g->nt > (int64_t)cs.wpe * pmax)
+        if (g->ntmax > 4 || cs.wpe != 4 || g->nrb > cs.wpe * pmax)
             return set_error(LPX_ERR_UNSUPPORTED,
-                             "prefetch=%u (D in registers) needs Np <= 64 and K*ceil(Np/16) <= %d "
+                             "prefetch=%u (D in registers) needs Np <= 64 and ceil(K*Np/16) <= %d "
                              "(K=%d Np=%d)",
                              r.prefetch, cs.wpe * pmax, K, Np);
     }

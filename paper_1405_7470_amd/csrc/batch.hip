@@ -278,6 +278,8 @@ lpx_status fill_table(lpx_batch* b, const lpx_contract_desc* items, const lpx_re
         it.a.K = c.K;
         it.a.Np = c.Np;
         it.a.nt = g.nt;
+        it.a.nrb = g.nrb;
+        it.a.np_div = make_divider(c.Np);
         it.a.nsteps = g.nsteps;
         it.a.ldu = g.ldu;
         it.a.ldo = g.ldo;

@@ -14,6 +14,13 @@
 //   UNROLL    split of the MFMA k-step loop with the inner part unrolled
 //             (tag "unr", sec. 2.4.2)
 //
+// Row blocks.  The K operators are stacked into one (K*Np) x Np matrix
+// (D[k][i][j] is row k*Np + i of D viewed as [K*Np][Np]) and cut into
+// nrb = ceil(K*Np/16) blocks of 16 rows: one MFMA row block covers rows of
+// consecutive operators, so only the last block is padded (K = 3, Np = 56:
+// 11 blocks instead of 12 per-operator ones).  Each output keeps the same
+// reduction over j, whichever block its row lands in.
+//
 // Work decomposition.  A work-group (4 wave64s per 16 elements of the
 // tile) walks the element tiles
 // tile = blockIdx.x, blockIdx.x + gridDim.x, ... (grid sized to the
@@ -62,10 +69,17 @@ struct ContractArgs {
     int64_t E;
     int64_t ntiles;
     int K, Np, nt, nsteps, ldu;
+    int nrb;     // stacked row blocks: ceil(K * Np / 16)
+    Divider np_div;  // stacked row R -> operator R / Np
     int ldo;     // staged output slot stride (floats), prefetch bit 3
     int np_vec;  // Np % 4 == 0: 16-byte row accesses are aligned
     int e_vec;   // E % 4 == 0
 };
+
+// Operator index of stacked row R (0 <= R < 2^31).
+__device__ __forceinline__ int row_op(const ContractArgs& a, int R) {
+    return (int)(((uint64_t)(uint32_t)R * a.np_div.m) >> a.np_div.sh);
+}
 
 template <int PREC>
 struct Frag;
@@ -170,23 +184,23 @@ __device__ __forceinline__ void load_row8(const float* __restrict__ row, int j0,
     }
 }
 
-// D fragment of pair (k, t), step s, read from global memory.
+// D fragment of row block p, step s, read from global memory.
 template <int PREC>
-__device__ __forceinline__ Frag<PREC> d_frag_global(const ContractArgs& a, int k, int t,
-                                                    int s, int lane) {
-    const int i = 16 * t + (lane & 15);
-    const int ic = i < a.Np ? i : a.Np - 1;
-    const float* row = a.D + ((int64_t)k * a.Np + ic) * a.Np;
+__device__ __forceinline__ Frag<PREC> d_frag_global(const ContractArgs& a, int p, int s,
+                                                    int lane) {
+    const int rows = a.K * a.Np;
+    const int R = 16 * p + (lane & 15);
+    const float* row = a.D + (int64_t)(R < rows ? R : rows - 1) * a.Np;
     if constexpr (PREC == LPX_FP32) {
         const int j0 = fp32_col(s, lane >> 4, a.nsteps & ~3);
         const float x = row[j0 < a.Np ? j0 : a.Np - 1];
-        return make_frag_fp32(i < a.Np && j0 < a.Np ? x : 0.0f);
+        return make_frag_fp32(R < rows && j0 < a.Np ? x : 0.0f);
     } else {
         const int j0 = s * Traits<PREC>::KSTEP + (lane >> 4) * Traits<PREC>::KPL;
         float v[8];
         load_row8(row, j0, a.Np, a.np_vec, v);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = i < a.Np ? v[q] : 0.0f;
+        for (int q = 0; q < 8; ++q) v[q] = R < rows ? v[q] : 0.0f;
         return make_frag8<PREC>(v);
     }
 }
@@ -242,14 +256,13 @@ __device__ __forceinline__ f4 load_row4(const float* __restrict__ row, int j0, i
     return v;
 }
 
-__device__ __forceinline__ f4 d_quad_global(const ContractArgs& a, int k, int t, int Q,
-                                            int lane) {
-    const int i = 16 * t + (lane & 15);
-    const int ic = i < a.Np ? i : a.Np - 1;
-    const f4 v = load_row4(a.D + ((int64_t)k * a.Np + ic) * a.Np, 16 * Q + 4 * (lane >> 4),
-                           a.Np, a.np_vec);
+__device__ __forceinline__ f4 d_quad_global(const ContractArgs& a, int p, int Q, int lane) {
+    const int rows = a.K * a.Np;
+    const int R = 16 * p + (lane & 15);
+    const f4 v = load_row4(a.D + (int64_t)(R < rows ? R : rows - 1) * a.Np,
+                           16 * Q + 4 * (lane >> 4), a.Np, a.np_vec);
     const f4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-    return i < a.Np ? v : z;
+    return R < rows ? v : z;
 }
 
 template <int LAYOUT>
@@ -529,7 +542,7 @@ __device__ __forceinline__ void stage_d(const ContractArgs& a, unsigned char* ld
     // Fragments are built in batches of U per thread so that U loads are in
     // flight together (D is small and read from L2 after the first touch).
     constexpr int U = PREC == LPX_FP32 ? 8 : 4;
-    const int64_t nfrag = (int64_t)a.K * a.nt * a.nsteps * 64;
+    const int64_t nfrag = (int64_t)a.nrb * a.nsteps * 64;
     for (int64_t base = 0; base < nfrag; base += (int64_t)NTHREADS * U) {
         Frag<PREC> f[U];
 #pragma unroll
@@ -545,9 +558,7 @@ __device__ __forceinline__ void stage_d(const ContractArgs& a, unsigned char* ld
                 l = w >> 2;
                 s = (sb & ~3) + (w & 3);
             }
-            const int k = p / a.nt;
-            const int t = p - k * a.nt;
-            f[b] = d_frag_global<PREC>(a, k, t, s, l);
+            f[b] = d_frag_global<PREC>(a, p, s, l);
         }
 #pragma unroll
         for (int b = 0; b < U; ++b) {
@@ -557,34 +568,40 @@ __device__ __forceinline__ void stage_d(const ContractArgs& a, unsigned char* ld
     }
 }
 
-// Write-back of one chunk of a wave's pairs (p = pc + q*WPE, q < PMAX).
+// Write-back of one chunk of a wave's row blocks (p = pc + q*WPE, q < PMAX).
+// Element-major: lane l holds stacked rows R0 .. R0+3 (R0 = 16p + 4(l/16))
+// of element e; with Np % 4 == 0 they belong to one operator k = R0 / Np.
+// DOF-major: lane l holds stacked row R = 16p + l%16 of four elements, and
+// out[k][i][.] is row R of out viewed as [K*Np][E].
 template <int LAYOUT, int PMAX, int WPE>
 __device__ __forceinline__ void store_pairs(const ContractArgs& a, const f4 (&acc)[PMAX], int pc,
                                             int64_t eb0, int lane) {
-    const int npairs = a.K * a.nt;
+    const int rows = a.K * a.Np;
 #pragma unroll
     for (int q = 0; q < PMAX; ++q) {
         const int p = pc + q * WPE;
-        if (p >= npairs) continue;
-        const int k = p / a.nt, t = p - (p / a.nt) * a.nt;
+        if (p >= a.nrb) continue;
         if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
             const int64_t e = eb0 + (lane & 15);
-            const int i0 = 16 * t + 4 * (lane >> 4);
-            if (e < a.E && i0 < a.Np) {
-                float* dst = a.out + ((int64_t)k * a.E + e) * a.Np + i0;
+            const int R0 = 16 * p + 4 * (lane >> 4);
+            int k = row_op(a, R0), i = R0 - k * a.Np;
+            if (e < a.E) {
                 if (a.np_vec) {
-                    *reinterpret_cast<f4*>(dst) = acc[q];
+                    if (R0 < rows)
+                        *reinterpret_cast<f4*>(a.out + ((int64_t)k * a.E + e) * a.Np + i) = acc[q];
                 } else {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (i0 + r < a.Np) dst[r] = acc[q][r];
+                    for (int r = 0; r < 4; ++r) {  // rows may run into the next operator
+                        if (R0 + r < rows) a.out[((int64_t)k * a.E + e) * a.Np + i] = acc[q][r];
+                        if (++i == a.Np) i = 0, ++k;
+                    }
                 }
             }
         } else {
-            const int i = 16 * t + (lane & 15);
+            const int R = 16 * p + (lane & 15);
             const int64_t e = eb0 + 4 * (lane >> 4);
-            if (i < a.Np && e < a.E) {
-                float* dst = a.out + ((int64_t)k * a.Np + i) * a.E + e;
+            if (R < rows && e < a.E) {
+                float* dst = a.out + (int64_t)R * a.E + e;
                 if (a.e_vec) {
                     *reinterpret_cast<f4*>(dst) = acc[q];
                 } else {
@@ -608,28 +625,28 @@ __device__ __forceinline__ void store_pairs(const ContractArgs& a, const f4 (&ac
 template <int LAYOUT, int PMAX, int WPE, int TILE_E>
 __device__ __forceinline__ void stage_pairs(const ContractArgs& a, const f4 (&acc)[PMAX], int pc,
                                             int row0, float* os, int lane) {
-    const int npairs = a.K * a.nt;
+    const int rows = a.K * a.Np;
 #pragma unroll
     for (int q = 0; q < PMAX; ++q) {
         const int p = pc + q * WPE;
-        if (p >= npairs) continue;
-        const int k = p / a.nt, t = p - (p / a.nt) * a.nt;
+        if (p >= a.nrb) continue;
         if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
             const int r = row0 + (lane & 15);
-            const int i0 = 16 * t + 4 * (lane >> 4);
-            float* dst = os + (k * TILE_E + r) * a.Np + i0;
+            const int R0 = 16 * p + 4 * (lane >> 4);
+            int k = row_op(a, R0), i = R0 - k * a.Np;
             if (a.np_vec) {
-                if (i0 < a.Np) *reinterpret_cast<f4*>(dst) = acc[q];
+                if (R0 < rows) *reinterpret_cast<f4*>(os + (k * TILE_E + r) * a.Np + i) = acc[q];
             } else {
 #pragma unroll
-                for (int r2 = 0; r2 < 4; ++r2)
-                    if (i0 + r2 < a.Np) dst[r2] = acc[q][r2];
+                for (int r2 = 0; r2 < 4; ++r2) {  // rows may run into the next operator
+                    if (R0 + r2 < rows) os[(k * TILE_E + r) * a.Np + i] = acc[q][r2];
+                    if (++i == a.Np) i = 0, ++k;
+                }
             }
         } else {
-            const int i = 16 * t + (lane & 15);
-            if (i < a.Np)
-                *reinterpret_cast<f4*>(os + (k * a.Np + i) * (TILE_E + 4) + row0 +
-                                       4 * (lane >> 4)) = acc[q];
+            const int R = 16 * p + (lane & 15);
+            if (R < rows)
+                *reinterpret_cast<f4*>(os + R * (TILE_E + 4) + row0 + 4 * (lane >> 4)) = acc[q];
         }
     }
 }
@@ -718,18 +735,16 @@ __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsig
     // Pairs held per wave and chunk: a three-operator block's share, at
     // most 6 (larger shares run in several chunks, re-reading u).
     constexpr int PMAX = (3 * NTMAX + WPE - 1) / WPE < 6 ? (3 * NTMAX + WPE - 1) / WPE : 6;
-    const int npairs = a.K * a.nt;
+    const int npairs = a.nrb;
     const int64_t nfrag = (int64_t)npairs * a.nsteps * 64;
     for (int pc = part; pc < npairs; pc += WPE * PMAX) {
         f4 acc[PMAX];
-        int pk[PMAX], pt[PMAX];
+        int pp[PMAX];
 #pragma unroll
         for (int q = 0; q < PMAX; ++q) {
             acc[q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-            int p = pc + q * WPE;
-            p = p < npairs ? p : npairs - 1;  // clamped: a duplicate pair is loaded, never used
-            pk[q] = p / a.nt;
-            pt[q] = p - pk[q] * a.nt;
+            const int p = pc + q * WPE;
+            pp[q] = p < npairs ? p : npairs - 1;  // clamped: a duplicate block is loaded, never used
         }
         auto step = [&](int s, auto masked) {
             Frag<PREC> uf;
@@ -744,10 +759,9 @@ __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsig
             for (int q = 0; q < PMAX; ++q) {
                 Frag<PREC> df;
                 if constexpr (PF_D)
-                    df = d_frag_lds<PREC>(lds, nfrag,
-                                          ((pk[q] * a.nt + pt[q]) * a.nsteps + s) * 64 + lane);
+                    df = d_frag_lds<PREC>(lds, nfrag, (pp[q] * a.nsteps + s) * 64 + lane);
                 else
-                    df = d_frag_global<PREC>(a, pk[q], pt[q], s, lane);
+                    df = d_frag_global<PREC>(a, pp[q], s, lane);
                 if constexpr (LAYOUT == LPX_ELEMENT_MAJOR)
                     acc[q] = mma(df, uf, acc[q]);  // rows i, columns e
                 else
@@ -768,9 +782,9 @@ __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsig
 #pragma unroll
                 for (int q = 0; q < PMAX; ++q) {
                     if constexpr (PF_D)
-                        dq[q] = d_quad_lds(lds, pk[q] * a.nt + pt[q], Q, a.nsteps, lane);
+                        dq[q] = d_quad_lds(lds, pp[q], Q, a.nsteps, lane);
                     else
-                        dq[q] = d_quad_global(a, pk[q], pt[q], Q, lane);
+                        dq[q] = d_quad_global(a, pp[q], Q, lane);
                 }
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
@@ -825,18 +839,16 @@ template <int PREC, int NTMAX, int WPE>
 __device__ __forceinline__ void load_dregs(const ContractArgs& a, int part, int lane,
                                            DRegs<PREC, NTMAX, WPE>& d) {
     using DR = DRegs<PREC, NTMAX, WPE>;
-    const int npairs = a.K * a.nt;
 #pragma unroll
     for (int q = 0; q < DR::PMAX; ++q) {
         int p = part + q * WPE;
-        p = p < npairs ? p : npairs - 1;  // clamped: the duplicate is never used
-        const int k = p / a.nt, t = p - (p / a.nt) * a.nt;
+        p = p < a.nrb ? p : a.nrb - 1;  // clamped: the duplicate is never used
 #pragma unroll
-        for (int s = 0; s < DR::NS; ++s) d.f[q][s] = d_frag_global<PREC>(a, k, t, s, lane);
+        for (int s = 0; s < DR::NS; ++s) d.f[q][s] = d_frag_global<PREC>(a, p, s, lane);
         if constexpr (PREC == LPX_FP32) {
 #pragma unroll
             for (int m = 0; m < DR::NT; ++m)
-                d.t[q][m] = d_frag_global<PREC>(a, k, t, (a.nsteps & ~3) + m, lane);
+                d.t[q][m] = d_frag_global<PREC>(a, p, (a.nsteps & ~3) + m, lane);
         }
     }
 }
@@ -996,7 +1008,7 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int64_t nfrag = (int64_t)a.K * a.nt * a.nsteps * 64;
+    const int64_t nfrag = (int64_t)a.nrb * a.nsteps * 64;
     float* ring = reinterpret_cast<float*>(
         lds + (PF_D ? nfrag * Lds<PREC>::DFRAG_BYTES * Lds<PREC>::PLANES : 0));
     float* oring = ring + 4 * a.ldu;  // staged output slots follow the u slots

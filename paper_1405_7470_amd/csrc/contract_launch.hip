@@ -84,6 +84,8 @@ lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g, vo
     a.K = c.K;
     a.Np = c.Np;
     a.nt = g.nt;
+    a.nrb = g.nrb;
+    a.np_div = make_divider(c.Np);
     a.nsteps = g.nsteps;
     a.ldu = g.ldu;
     a.ldo = g.ldo;

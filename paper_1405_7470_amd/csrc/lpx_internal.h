@@ -60,6 +60,24 @@ constexpr int loader_per_lane(int tile_e, int ntmax, int nlw) {
 }
 inline int64_t ceil_div(int64_t x, int64_t m) { return (x + m - 1) / m; }
 
+// Exact n / d for 0 <= n < 2^31 and 1 <= d <= 2^16 as one 32x32-bit
+// multiply and a shift (division by an invariant integer, Granlund and
+// Montgomery 1994): with l = ceil(log2 d) and m = ceil(2^(31+l) / d), the
+// error of n*m / 2^(31+l) against n/d stays below 2^-l <= 1/d, so the floor
+// is exact.
+struct Divider {
+    uint32_t m;
+    int sh;
+};
+inline Divider make_divider(int d) {
+    int l = 0;
+    while ((1 << l) < d) ++l;
+    Divider v;
+    v.m = (uint32_t)(((1ULL << (31 + l)) + (uint64_t)d - 1) / (uint64_t)d);
+    v.sh = 31 + l;
+    return v;
+}
+
 // Geometry of one contraction launch, derived from (problem, record) on the
 // host.  Every quantity the kernel's indexing assumes is computed here.
 struct ContractGeom {
@@ -70,10 +88,11 @@ struct ContractGeom {
     int nt = 0;        // i-blocks of 16 rows: ceil(Np / 16)
     int ntmax = 2;     // compiled bound on nt: 2, 4 or 8
     int nsteps = 0;    // MFMA k-steps: ceil(Np / kstep)
+    int nrb = 0;       // stacked row blocks of 16 rows of D as [K*Np][Np]: ceil(K*Np / 16)
     int ldu = 0;       // LDS ring slot stride of a staged u tile (floats)
     int ldo = 0;       // LDS ring slot stride of a staged output tile (floats)
     int64_t ntiles = 0;
-    int64_t nfrag = 0;     // staged D fragments: K*nt*nsteps*64 lanes
+    int64_t nfrag = 0;     // staged D fragments: nrb*nsteps*64 lanes
     int64_t lds_bytes = 0; // dynamic LDS per work-group (0 if no prefetch)
 };
 

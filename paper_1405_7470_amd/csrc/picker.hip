@@ -42,7 +42,7 @@ lpx_status features(const lpx_problem& p, const lpx_record& r, float* f) {
     ContractGeom g;
     lpx_status s = contract_geometry(p.K, p.Np, p.E, p.layout, r, &g);
     if (s != LPX_OK && s != LPX_ERR_UNSUPPORTED) return s;
-    const double pad16 = 16.0 * ceil_div(p.Np, 16);
+    const double rows16 = 16.0 * ceil_div((int64_t)p.K * p.Np, 16);  // stacked row blocks
     f[0] = (float)std::log2((double)p.Np);
     f[1] = (float)std::log2((double)p.E);
     f[2] = (float)p.K;
@@ -52,7 +52,7 @@ lpx_status features(const lpx_problem& p, const lpx_record& r, float* f) {
     f[6] = (float)(((r.prefetch >> 1) & 1) + ((r.prefetch >> 3) & 1));  // u, u + output staged
     f[7] = (float)std::log2((double)r.unroll);
     f[8] = (float)r.precision;
-    f[9] = (float)((pad16 - p.Np) / pad16);
+    f[9] = (float)((rows16 - (double)p.K * p.Np) / rows16);
     f[10] = (float)std::log2((double)ceil_div(p.E, r.tile_e));
     f[11] = (float)((double)g.lds_bytes / (double)kMaxLdsPerWorkgroup);
     return LPX_OK;

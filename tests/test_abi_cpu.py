@@ -135,7 +135,7 @@ def test_assumption_checked():
 
 
 def test_register_d_limits():
-    # D in registers: fits Np <= 64 with K*ceil(Np/16) <= 12
+    # D in registers: fits Np <= 64 with ceil(K*Np/16) <= 12 row blocks
     assert status(desc(Np=56), lpx.record("fp32", 32, 4, 1)) == lpx.OK
     assert status(desc(Np=56), lpx.record("bf16x3", 32, 6, 1)) == lpx.OK
     assert status(desc(Np=84), lpx.record("fp32", 32, 4, 1)) == lpx.ERR_UNSUPPORTED
@@ -149,7 +149,7 @@ def test_register_d_limits():
 
 def test_lds_budget():
     # prefetch bit 0 stages all of D in LDS: Np = 128, K = 3 in FP32 needs
-    # 3*8*32*64*4 bytes of D fragments, above the 160 KiB per work-group
+    # 24 row blocks * 32 k-steps * 64 lanes * 4 bytes, above 160 KiB
     r = lpx.record("fp32", 64, 1, 1)
     assert status(desc(Np=128), r) == lpx.ERR_UNSUPPORTED
     s, b = lpx.lds_bytes(3, 128, 4096, "em", r)
@@ -162,12 +162,13 @@ def test_lds_budget():
     # write whole rounds of 64 chunks each: 4 waves * 8 rounds * 256 floats
     s, b = lpx.lds_bytes(3, 72, 4096, "em", lpx.record("fp32", 64, 2, 1))
     assert s == lpx.OK and b == 4 * (4 * 8 * 256) * 4
-    # the full-scale shape fits both: D 3*4*14*64*4 bytes + ring 4*(64*64+32)*4
+    # the full-scale shape fits both: the 3 stacked operators are 168 rows,
+    # 11 row blocks of D (11*14*64*4 bytes) + ring 4*(64*64+32)*4
     s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", lpx.record("fp32", 64, 3, 1))
-    assert s == lpx.OK and b == 3 * 4 * 14 * 64 * 4 + 4 * (64 * 64 + 32) * 4
+    assert s == lpx.OK and b == 11 * 14 * 64 * 4 + 4 * (64 * 64 + 32) * 4
     # bf16x3: two bf16 planes of D fragments (16 B per lane each)
     s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", lpx.record("bf16x3", 32, 3, 1))
-    assert s == lpx.OK and b == 3 * 4 * 2 * 64 * 32 + 4 * (32 * 64 + 32) * 4
+    assert s == lpx.OK and b == 11 * 2 * 64 * 32 + 4 * (32 * 64 + 32) * 4
     s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", lpx.record("fp32", 64, 0, 1))
     assert s == lpx.OK and b == 0
     # bit 3 adds a two-slot output ring: element-major K*tile_e*Np floats per
@@ -175,7 +176,7 @@ def test_lds_budget():
     s, b = lpx.lds_bytes(3, 56, 1 << 20, "em", lpx.record("fp32", 32, 14, 1))
     assert s == lpx.OK and b == 4 * (32 * 64 + 32) * 4 + 2 * 3 * 32 * 56 * 4
     s, b = lpx.lds_bytes(3, 56, 1 << 20, "dm", lpx.record("bf16x3", 32, 11, 1))
-    assert s == lpx.OK and b == (3 * 4 * 2 * 64 * 32 + 4 * (32 * 64 + 32) * 4
+    assert s == lpx.OK and b == (11 * 2 * 64 * 32 + 4 * (32 * 64 + 32) * 4
                                  + 2 * 3 * 56 * 36 * 4)
     # K = 8 at Np = 120 with a 64-element tile: the output ring alone needs
     # 2*8*64*120*4 bytes

@@ -72,6 +72,28 @@ def test_edge_shapes(precision, layout):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
+def test_row_blocks_across_operators(layout):
+    """The K operators are stacked into K*Np rows cut in blocks of 16: blocks
+    that start in one operator and end in the next (Np not a multiple of 4
+    or 16), a partial last block, and K up to 7."""
+    recs = ((16, 0, 1), (32, 1, 1), (64, 3, 2), (32, 4, 1), (32, 6, 1), (32, 10, 1),
+            (64, 11, 1), (32, 14, 1))
+    E = 203
+    for K, Np in ((1, 5), (3, 5), (5, 6), (7, 10), (3, 13), (4, 20), (5, 36), (3, 56),
+                  (2, 120)):
+        D, u = inputs.contraction_inputs(K, Np, E, seed=K * 1000 + Np, layout=layout)
+        for precision in PRECS:
+            for t, p, un in recs:
+                rec = lpx.record(precision, t, p, un)
+                if not supported(K, Np, E, layout, rec):
+                    continue
+                print(f"case: row blocks {precision} {layout} K={K} Np={Np} {lpx.describe(rec)}",
+                      flush=True)
+                out = run(D, u, layout, rec)
+                check_against_oracle(D, u, as_em(out, layout), layout, precision)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
 def test_many_tiles_per_work_group(layout):
     """E large enough that every work-group walks several tiles (the
     staged pipelines' steady state and drain) with a ragged last tile.  All

@@ -70,8 +70,9 @@ def test_missing_model_rejected(tmp_path):
 def test_features_by_hand():
     r = lpx.record("bf16x3", 32, 3, 4)
     f = lpx.features(3, 56, 1 << 20, "dm", r)
-    lds = 3 * 4 * 2 * 64 * 32 + 4 * (32 * 64 + 32) * 4
-    expect = [math.log2(56), 20.0, 3.0, 1.0, 5.0, 1.0, 1.0, 2.0, 2.0, 8 / 64,
+    # the 3 operators stacked are 168 rows: 11 row blocks of 16, 8 rows padding
+    lds = 11 * 2 * 64 * 32 + 4 * (32 * 64 + 32) * 4
+    expect = [math.log2(56), 20.0, 3.0, 1.0, 5.0, 1.0, 1.0, 2.0, 2.0, 8 / 176,
               math.log2((1 << 20) / 32), lds / (160 * 1024)]
     assert np.allclose(f, expect, rtol=1e-6)
     f = lpx.features(3, 56, 1000, "em", lpx.record("fp32", 16, 6, 1))
@@ -79,7 +80,7 @@ def test_features_by_hand():
     f = lpx.features(3, 56, 1000, "em", lpx.record("fp32", 16, 14, 1))
     assert f[5] == 2.0 and f[6] == 2.0               # ... and the output staged too
     f = lpx.features(3, 10, 1000, "em", lpx.default_record("fp32"))
-    assert f[9] == pytest.approx(6 / 16) and f[10] == pytest.approx(math.log2(63))
+    assert f[9] == pytest.approx(2 / 32) and f[10] == pytest.approx(math.log2(63))
     assert f[5] == 0 and f[6] == 0 and f[11] == 0
 
 
