@@ -1,6 +1,7 @@
 """Build liblpx.so (all HIP sources for gfx950) in-tree.
 
-Every source under csrc/ is compiled with hipcc for gfx950 into
+Every source under csrc/ is compiled with hipcc for gfx950 (the kernel
+instance units once per i-block bound) into
 ``_build/`` at the repository root, then linked into
 ``paper_1405_7470_amd/liblpx.so``.  Run as ``python -m
 paper_1405_7470_amd.build``.
@@ -28,9 +29,15 @@ CFLAGS = [
 ]
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+INSTANCE_UNIT = re.compile(r"contract_\w+_(em|dm)\.hip$")
+NT_BOUNDS = (8, 4, 2)  # each instance unit is compiled once per i-block bound
+
+
+def _compile(job):
+    src, defs = job
+    tag = "".join("." + d.split("=")[1] for d in defs)
+    obj = os.path.join(BUILD, os.path.basename(src) + tag + ".o")
+    cmd = [HIPCC, *CFLAGS, *("-D" + d for d in defs), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     # hipcc's host pass warns that it does not know the packed-fp32 feature;
     # that line is expected and dropped.
@@ -47,10 +54,11 @@ def build(verbose: bool = True, jobs: int = 0) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     # the kernel-instance units take longest: start them first
-    srcs.sort(key=lambda f: not re.search(r"contract_\w+_(em|dm)\.hip$", f))
-    jobs = jobs or min(len(srcs), os.cpu_count() or 4, 16)
+    units = [(f, (f"LPX_NT={nt}",)) for nt in NT_BOUNDS for f in srcs if INSTANCE_UNIT.search(f)]
+    units += [(f, ()) for f in srcs if not INSTANCE_UNIT.search(f)]
+    jobs = jobs or min(len(units), os.cpu_count() or 4, 16)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(_compile, units))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     subprocess.run(cmd, check=True)

@@ -92,12 +92,16 @@ __global__ __launch_bounds__(kThreadsB) void batch_kernel(BatchArgs b) {
                 }
             }
             const int64_t eb0 = (t - b.items[lo].tile_begin) * 16;
-            if (dl)
-                kern::block_compute<PREC, LAYOUT, NTMAX, true, false, 16, 4, 2>(a, lds, nullptr, 0,
-                                                                             eb0, wave, lane);
-            else
-                kern::block_compute<PREC, LAYOUT, NTMAX, false, false, 16, 4, 2>(a, lds, nullptr, 0,
-                                                                              eb0, wave, lane);
+            constexpr int CAP = kern::pmax_cap<NTMAX, 4>();
+            kern::with_pmax<CAP, 4, PREC == LPX_FP32 ? 2 : 0>(a.nrb, [&](auto pm) {
+                constexpr int P = decltype(pm)::value;
+                if (dl)
+                    kern::block_compute<PREC, LAYOUT, NTMAX, true, false, 16, 4, 2, false, true, P>(
+                        a, lds, nullptr, 0, eb0, wave, lane);
+                else
+                    kern::block_compute<PREC, LAYOUT, NTMAX, false, false, 16, 4, 2, false, true, P>(
+                        a, lds, nullptr, 0, eb0, wave, lane);
+            });
         }
     }
 }
@@ -163,16 +167,23 @@ __global__ __launch_bounds__((ShapeS<NTMAX>::THREADS)) void batch_staged(BatchAr
                 const Tile tt = tile_at(n, cur);
                 const kern::ContractArgs& a = b.items[tt.inst].a;
                 if (row0 < tt.nvalid) {
-                    auto run = [&](auto mask) {
-                        kern::block_compute<PREC, LAYOUT, NTMAX, false, true, kTileS, S::WPE, 2,
-                                            true, decltype(mask)::value>(
-                            a, nullptr, ring + (n & 3) * b.ldu, row0, tt.e0 + row0, part, lane,
-                            oring + (n & 1) * b.ldo);
-                    };
-                    if (PREC == LPX_FP32 && a.np_vec)  // uniform
-                        run(std::false_type());
-                    else
-                        run(std::true_type());
+                    // the instance's own row-block count: small instances in
+                    // a batch built for Np up to 16 * NTMAX run no duplicate
+                    // MFMA chains (every size for FP32)
+                    constexpr int CAP = kern::pmax_cap<NTMAX, S::WPE>();
+                    kern::with_pmax<CAP, S::WPE, PREC == LPX_FP32 ? 2 : 0>(a.nrb, [&](auto pm) {
+                        auto run = [&](auto mask) {
+                            kern::block_compute<PREC, LAYOUT, NTMAX, false, true, kTileS, S::WPE,
+                                                2, true, decltype(mask)::value,
+                                                decltype(pm)::value>(
+                                a, nullptr, ring + (n & 3) * b.ldu, row0, tt.e0 + row0, part,
+                                lane, oring + (n & 1) * b.ldo);
+                        };
+                        if (PREC == LPX_FP32 && a.np_vec)  // uniform
+                            run(std::false_type());
+                        else
+                            run(std::true_type());
+                    });
                 }
             }
             __syncthreads();

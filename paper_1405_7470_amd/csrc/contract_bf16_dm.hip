@@ -1,10 +1,13 @@
-// Instances of the contraction kernel family: bf16, DOF-major layout.
+// Instances of the contraction kernel family: bf16, DOF-major layout,
+// i-block bound LPX_NT (this unit is compiled once for each of 2, 4 and 8).
 #include "contract_dispatch.h"
+
+#ifndef LPX_NT
+#error "compile with -DLPX_NT=2, 4 or 8"
+#endif
 
 namespace lpx {
 
-ContractFn contract_kernel_bf16_dm(int ntmax, int tile, int pf, int un) {
-    return dispatch::by_nt<LPX_BF16, LPX_DOF_MAJOR>(ntmax, tile, pf, un);
-}
+template ContractFn contract_instances<LPX_BF16, LPX_DOF_MAJOR, LPX_NT>(int, int, int);
 
 }  // namespace lpx

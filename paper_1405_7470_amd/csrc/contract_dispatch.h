@@ -1,6 +1,5 @@
-// Record -> kernel instance table of the contraction family, one
-// translation unit per (precision, layout) so that the instances compile in
-// parallel.  Records outside what is built map to nullptr.
+// Record -> kernel instance table of the contraction family.  Records
+// outside what is built map to nullptr.
 #pragma once
 
 #include "contract_kernels.h"
@@ -55,23 +54,37 @@ ContractFn by_tile(int tile, int pf, int un) {
     }
 }
 
-template <int PREC, int LAYOUT>
-ContractFn by_nt(int ntmax, int tile, int pf, int un) {
-    switch (ntmax) {
-        case 2: return by_tile<PREC, LAYOUT, 2>(tile, pf, un);
-        case 4: return by_tile<PREC, LAYOUT, 4>(tile, pf, un);
-        default: return by_tile<PREC, LAYOUT, 8>(tile, pf, un);
-    }
-}
-
 }  // namespace dispatch
 
-// One definition per (precision, layout) translation unit.
-ContractFn contract_kernel_fp32_em(int ntmax, int tile, int pf, int un);
-ContractFn contract_kernel_fp32_dm(int ntmax, int tile, int pf, int un);
-ContractFn contract_kernel_bf16_em(int ntmax, int tile, int pf, int un);
-ContractFn contract_kernel_bf16_dm(int ntmax, int tile, int pf, int un);
-ContractFn contract_kernel_bf16x3_em(int ntmax, int tile, int pf, int un);
-ContractFn contract_kernel_bf16x3_dm(int ntmax, int tile, int pf, int un);
+// The instances of one (precision, layout, i-block bound NTMAX): each
+// instance unit (contract_<precision>_<layout>.hip) is compiled once per
+// bound, 2, 4 and 8, with -DLPX_NT, so that the instances compile in
+// parallel; everywhere else these are extern.
+template <int PREC, int LAYOUT, int NTMAX>
+ContractFn contract_instances(int tile, int pf, int un) {
+    return dispatch::by_tile<PREC, LAYOUT, NTMAX>(tile, pf, un);
+}
+
+#define LPX_EXTERN_INSTANCES(P, L)                                               \
+    extern template ContractFn contract_instances<P, L, 2>(int, int, int);    \
+    extern template ContractFn contract_instances<P, L, 4>(int, int, int);    \
+    extern template ContractFn contract_instances<P, L, 8>(int, int, int);
+LPX_EXTERN_INSTANCES(LPX_FP32, LPX_ELEMENT_MAJOR)
+LPX_EXTERN_INSTANCES(LPX_FP32, LPX_DOF_MAJOR)
+LPX_EXTERN_INSTANCES(LPX_BF16, LPX_ELEMENT_MAJOR)
+LPX_EXTERN_INSTANCES(LPX_BF16, LPX_DOF_MAJOR)
+LPX_EXTERN_INSTANCES(LPX_BF16X3, LPX_ELEMENT_MAJOR)
+LPX_EXTERN_INSTANCES(LPX_BF16X3, LPX_DOF_MAJOR)
+#undef LPX_EXTERN_INSTANCES
+
+// Record -> instance for a run-time bound.
+template <int PREC, int LAYOUT>
+ContractFn contract_instance(int ntmax, int tile, int pf, int un) {
+    switch (ntmax) {
+        case 2: return contract_instances<PREC, LAYOUT, 2>(tile, pf, un);
+        case 4: return contract_instances<PREC, LAYOUT, 4>(tile, pf, un);
+        default: return contract_instances<PREC, LAYOUT, 8>(tile, pf, un);
+    }
+}
 
 }  // namespace lpx

@@ -727,14 +727,49 @@ __device__ __forceinline__ void store_tile(const ContractArgs& a, const float* o
 // dropping the selects keeps their lane masks out of the scalar registers.
 // bf16/bf16x3 mask their last k-step only (it straddles Np unless
 // Np % 32 == 0); the other steps lie below Np.
+// Row blocks a wave holds per chunk: a three-operator block's share, at
+// most 6 (larger shares run in several chunks, re-reading u).
+template <int NTMAX, int WPE>
+constexpr int pmax_cap() {
+    return (3 * NTMAX + WPE - 1) / WPE < 6 ? (3 * NTMAX + WPE - 1) / WPE : 6;
+}
+
+// Calls f(std::integral_constant<int, P>()) with P row blocks per wave and
+// chunk, P <= CAP, enough to cover all nrb row blocks in one chunk when CAP
+// is: a problem with fewer operators or rows than the kernel is built for
+// then runs fewer MFMA chains on duplicate blocks.  MODE 0 builds P = CAP
+// only; MODE 1 adds one smaller size (1 of 2, 2 of 3, 4 of 6); MODE 2
+// builds every P in 1..CAP (for one kernel serving many shapes).  The modes
+// bound the code built per kernel.  nrb is uniform, so is the branch.
+template <int CAP, int WPE, int MODE, class F>
+__device__ __forceinline__ void with_pmax(int nrb, F&& f) {
+    const int need = (nrb + WPE - 1) / WPE;
+    if constexpr (MODE == 2) {
+        if constexpr (CAP > 1) if (need <= 1) return f(std::integral_constant<int, 1>());
+        if constexpr (CAP > 2) if (need <= 2) return f(std::integral_constant<int, 2>());
+        if constexpr (CAP > 3) if (need <= 3) return f(std::integral_constant<int, 3>());
+        if constexpr (CAP > 4) if (need <= 4) return f(std::integral_constant<int, 4>());
+        if constexpr (CAP > 5) if (need <= 5) return f(std::integral_constant<int, 5>());
+    } else if constexpr (MODE == 1) {
+        constexpr int SMALL = CAP == 6 ? 4 : CAP - 1;
+        if constexpr (SMALL >= 1) if (need <= SMALL) return f(std::integral_constant<int, SMALL>());
+    }
+    f(std::integral_constant<int, CAP>());
+}
+
+// FP32 MFMAs cost about five times the bf16x3 triple per output, so only
+// the FP32 kernels past 32 rows are built with a smaller row-block size.
+template <int PREC, int NTMAX>
+constexpr int pmax_mode() {
+    return PREC == LPX_FP32 && NTMAX >= 4 ? 1 : 0;
+}
+
 template <int PREC, int LAYOUT, int NTMAX, bool PF_D, bool PF_U, int TILE_E, int WPE, int UNROLL,
-          bool PF_O = false, bool MASK = true>
+          bool PF_O = false, bool MASK = true, int PM = pmax_cap<NTMAX, WPE>()>
 __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsigned char* lds,
                                               const float* ut, int row0, int64_t eb0, int part,
                                               int lane, float* os = nullptr) {
-    // Pairs held per wave and chunk: a three-operator block's share, at
-    // most 6 (larger shares run in several chunks, re-reading u).
-    constexpr int PMAX = (3 * NTMAX + WPE - 1) / WPE < 6 ? (3 * NTMAX + WPE - 1) / WPE : 6;
+    constexpr int PMAX = PM;
     const int npairs = a.nrb;
     const int64_t nfrag = (int64_t)npairs * a.nsteps * 64;
     for (int pc = part; pc < npairs; pc += WPE * PMAX) {
@@ -1028,12 +1063,15 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
                     a, d, nullptr, 0, e0 + 16 * eblk, part, lane);
             }
         } else {
-            for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-                const int64_t e0 = tile * TILE_E;
-                if (e0 + 16 * eblk >= a.E) continue;  // uniform per wave; no barrier below
-                block_compute<PREC, LAYOUT, NTMAX, PF_D, false, TILE_E, S::WPE, UNROLL>(
-                    a, lds, nullptr, 0, e0 + 16 * eblk, part, lane);
-            }
+            with_pmax<pmax_cap<NTMAX, S::WPE>(), S::WPE, pmax_mode<PREC, NTMAX>()>(a.nrb, [&](auto pm) {
+                for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+                    const int64_t e0 = tile * TILE_E;
+                    if (e0 + 16 * eblk >= a.E) continue;  // uniform per wave; no barrier below
+                    block_compute<PREC, LAYOUT, NTMAX, PF_D, false, TILE_E, S::WPE, UNROLL, false,
+                                  true, decltype(pm)::value>(a, lds, nullptr, 0, e0 + 16 * eblk,
+                                                             part, lane);
+                }
+            });
         }
     } else {
         // The work-group's n-th tile is blockIdx.x + n * gridDim.x, n < nmine.
@@ -1146,23 +1184,27 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
                     __syncthreads();
                 }
             } else {
-                auto block = [&](int64_t tile, int64_t n, int row0) {
-                    auto run = [&](auto mask) {
-                        block_compute<PREC, LAYOUT, NTMAX, PF_D, true, TILE_E, S::WPE, UNROLL, PF_O,
-                                      decltype(mask)::value>(
-                            a, lds, ring + (n & 3) * a.ldu, row0, tile * TILE_E + row0, part, lane,
-                            oring + (n & 1) * a.ldo);
+                // every compute wave takes the same branch of with_pmax, so
+                // the barrier count is that of the other roles
+                with_pmax<pmax_cap<NTMAX, S::WPE>(), S::WPE, pmax_mode<PREC, NTMAX>()>(a.nrb, [&](auto pm) {
+                    auto block = [&](int64_t tile, int64_t n, int row0) {
+                        auto run = [&](auto mask) {
+                            block_compute<PREC, LAYOUT, NTMAX, PF_D, true, TILE_E, S::WPE, UNROLL,
+                                          PF_O, decltype(mask)::value, decltype(pm)::value>(
+                                a, lds, ring + (n & 3) * a.ldu, row0, tile * TILE_E + row0, part,
+                                lane, oring + (n & 1) * a.ldo);
+                        };
+                        if (PREC == LPX_FP32 && a.np_vec)  // uniform
+                            run(std::false_type());
+                        else
+                            run(std::true_type());
                     };
-                    if (PREC == LPX_FP32 && a.np_vec)  // uniform
-                        run(std::false_type());
-                    else
-                        run(std::true_type());
-                };
-                __syncthreads();
-                for (int64_t n = 0; n < niter; ++n) {
-                    if (n < nmine) tile_work(block, n);
                     __syncthreads();
-                }
+                    for (int64_t n = 0; n < niter; ++n) {
+                        if (n < nmine) tile_work(block, n);
+                        __syncthreads();
+                    }
+                });
             }
         }
     }

@@ -13,16 +13,17 @@ namespace {
 
 ContractFn select(const ContractGeom& g) {
     const bool em = g.layout == LPX_ELEMENT_MAJOR;
+    const int nt = g.ntmax, t = g.tile_e, pf = g.prefetch, un = g.unroll;
     switch (g.prec) {
         case LPX_FP32:
-            return em ? contract_kernel_fp32_em(g.ntmax, g.tile_e, g.prefetch, g.unroll)
-                      : contract_kernel_fp32_dm(g.ntmax, g.tile_e, g.prefetch, g.unroll);
+            return em ? contract_instance<LPX_FP32, LPX_ELEMENT_MAJOR>(nt, t, pf, un)
+                      : contract_instance<LPX_FP32, LPX_DOF_MAJOR>(nt, t, pf, un);
         case LPX_BF16:
-            return em ? contract_kernel_bf16_em(g.ntmax, g.tile_e, g.prefetch, g.unroll)
-                      : contract_kernel_bf16_dm(g.ntmax, g.tile_e, g.prefetch, g.unroll);
+            return em ? contract_instance<LPX_BF16, LPX_ELEMENT_MAJOR>(nt, t, pf, un)
+                      : contract_instance<LPX_BF16, LPX_DOF_MAJOR>(nt, t, pf, un);
         default:
-            return em ? contract_kernel_bf16x3_em(g.ntmax, g.tile_e, g.prefetch, g.unroll)
-                      : contract_kernel_bf16x3_dm(g.ntmax, g.tile_e, g.prefetch, g.unroll);
+            return em ? contract_instance<LPX_BF16X3, LPX_ELEMENT_MAJOR>(nt, t, pf, un)
+                      : contract_instance<LPX_BF16X3, LPX_DOF_MAJOR>(nt, t, pf, un);
     }
 }
 
