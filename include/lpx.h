@@ -329,9 +329,10 @@ lpx_status lpx_tune_cache_clear(void);
 
 /* The 12 features of (problem, record), into the host array out[12]:
  * log2 Np, log2 E, K, layout, log2 tile_e, D storage, staging (0 none,
- * 1 u tile, 2 u and output tiles),
- * log2 unroll, precision code, MFMA row padding of the stacked operator
- * rows (16*ceil(K*Np/16) - K*Np) / (16*ceil(K*Np/16)), log2 of the element-tile count, dynamic LDS bytes per
+ * 1 u tile, 2 u and output tiles), log2 unroll, precision code, MFMA row
+ * padding of the stacked operator rows (16*ceil(K*Np/16) - K*Np) /
+ * (16*ceil(K*Np/16)), alignment class 2*(Np % 4 == 0) + (E % 4 == 0)
+ * (vector or scalar row and element accesses), dynamic LDS bytes per
  * work-group / 160 KiB.  The D-prefetch feature is the storage of D:
  * 0 global, 1 LDS, 2 registers.  Needs 0 < K, 0 < Np <= 128, 0 < E. */
 lpx_status lpx_features(const lpx_problem* p, const lpx_record* r, float* out);

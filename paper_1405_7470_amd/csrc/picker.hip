@@ -53,7 +53,10 @@ lpx_status features(const lpx_problem& p, const lpx_record& r, float* f) {
     f[7] = (float)std::log2((double)r.unroll);
     f[8] = (float)r.precision;
     f[9] = (float)((rows16 - (double)p.K * p.Np) / rows16);
-    f[10] = (float)std::log2((double)ceil_div(p.E, r.tile_e));
+    // 16-byte alignment of rows (Np % 4 == 0) and of element runs
+    // (E % 4 == 0): they switch the kernels between vector and scalar
+    // accesses, which log2 Np and log2 E cannot express
+    f[10] = (float)(2 * (p.Np % 4 == 0) + (p.E % 4 == 0));
     f[11] = (float)((double)g.lds_bytes / (double)kMaxLdsPerWorkgroup);
     return LPX_OK;
 }

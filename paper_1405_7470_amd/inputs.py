@@ -83,13 +83,19 @@ def ragged_batch_inputs(shapes, K=3, seed=0):
 
 def picker_shapes(n, seed, precisions=("fp32", "bf16x3", "bf16")):
     """Random problem shapes for cost-model training/evaluation:
-    Np uniform integer in [8, 128], E = floor(2^U(10, 21)), layout and
-    precision uniform, K = 3."""
+    Np uniform integer in [8, 128], E = floor(2^U(10, 21)), each rounded up
+    (Np) or down (E) to a multiple of 4 with probability 1/2, so that the
+    four 16-byte alignment classes of rows and element runs are equally
+    common; layout and precision uniform, K = 3."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(n):
         Np = int(rng.integers(8, 129))
+        if rng.random() < 0.5:
+            Np = 4 * ((Np + 3) // 4)
         E = int(math.floor(2.0 ** rng.uniform(10.0, 21.0)))
+        if rng.random() < 0.5:
+            E = 4 * (E // 4)
         layout = ("em", "dm")[int(rng.integers(0, 2))]
         prec = precisions[int(rng.integers(0, len(precisions)))]
         out.append({"K": 3, "Np": Np, "E": E, "layout": layout, "precision": prec})

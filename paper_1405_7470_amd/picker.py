@@ -104,12 +104,14 @@ def _group(rows):
     return groups
 
 
-def train(rows, epochs=300, batch=256, lr=1e-3, seed=0, val_frac=0.15, patience=40, log=print):
+def train(rows, epochs=300, batch=256, lr=1e-3, seed=0, val_frac=0.15, patience=40, log=print,
+          split_seed=0):
     """Trains the cost model with the library's kernels; returns
-    (params, mean, std, history)."""
+    (params, mean, std, history).  split_seed fixes the validation shapes,
+    seed the initialisation and minibatch order."""
     rng = np.random.default_rng(seed)
     shape_ids = sorted({r["shape_id"] for r in rows})
-    rng.shuffle(shape_ids)
+    np.random.default_rng(split_seed).shuffle(shape_ids)
     nval = max(1, int(len(shape_ids) * val_frac))
     val_ids = set(shape_ids[:nval])
     tr = [r for r in rows if r["shape_id"] not in val_ids]
@@ -214,6 +216,8 @@ def main():
     ap.add_argument("--eval-shapes", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--model", default=MODEL_PATH)
+    ap.add_argument("--seeds", type=int, default=3,
+                    help="initialisations trained; the lowest validation regret is kept")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     os.makedirs(os.path.dirname(args.model), exist_ok=True)
@@ -223,7 +227,14 @@ def main():
     if os.path.exists(db):
         os.remove(db)
     rows = collect(train_shapes, db_path=db)
-    params, mean, std, hist = train(rows, epochs=args.epochs)
+    best = None
+    for seed in range(args.seeds):
+        params, mean, std, hist = train(rows, epochs=args.epochs, seed=seed)
+        reg = min(h["val_regret"] for h in hist)
+        print(f"seed {seed}: best val regret {reg:.4f}", flush=True)
+        if best is None or reg < best[0]:
+            best = (reg, params, mean, std, hist)
+    _, params, mean, std, hist = best
     lpx.picker_save(args.model, params, mean, std)
     json.dump(hist, open(os.path.join(args.out, "train_history.json"), "w"))
     print(f"saved {args.model}; best val regret {min(h['val_regret'] for h in hist):.4f}",
