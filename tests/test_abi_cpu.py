@@ -134,6 +134,15 @@ def test_assumption_checked():
     assert "assumes" in lpx.last_error()
 
 
+def test_stacked_rows_limit():
+    # the K operators are stacked into K*Np MFMA rows indexed with 32-bit
+    # integers: K*Np beyond 2^31 - 16 is refused before any HIP call
+    far = dict(u=A + (1 << 44), out=A + (1 << 45))  # D of 2^41 bytes does not overlap them
+    assert status(desc(K=(1 << 24) - 1, Np=128, **far)) == lpx.OK  # 2^31 - 128 rows
+    assert status(desc(K=1 << 24, Np=128, **far)) == lpx.ERR_UNSUPPORTED  # 2^31 rows
+    assert "stacked operator rows" in lpx.last_error()
+
+
 def test_register_d_limits():
     # D in registers: fits Np <= 64 with ceil(K*Np/16) <= 12 row blocks
     assert status(desc(Np=56), lpx.record("fp32", 32, 4, 1)) == lpx.OK
