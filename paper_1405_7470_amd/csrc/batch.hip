@@ -98,11 +98,25 @@ __global__ __launch_bounds__(kThreadsB) void batch_kernel(BatchArgs b) {
                 if (dl)
                     kern::block_compute<PREC, LAYOUT, NTMAX, true, false, 16, 4, 2, false, true, P>(
                         a, lds, nullptr, 0, eb0, wave, lane);
-                else
-                    kern::block_compute<PREC, LAYOUT, NTMAX, false, false, 16, 4, 2, false, true, P>(
-                        a, lds, nullptr, 0, eb0, wave, lane);
+                else  // D arranged in global memory
+                    kern::block_compute<PREC, LAYOUT, NTMAX, true, false, 16, 4, 2, false, true, P>(
+                        a, a.Darr, nullptr, 0, eb0, wave, lane);
             });
         }
+    }
+}
+
+// D of every instance in MFMA operand order, written to its slice of the
+// batch's arrangement buffer (the first node of the graph, so updated D
+// pointers are followed on every replay).
+template <int PREC>
+__global__ __launch_bounds__(kern::kArrangeThreads) void arrange_all(const Item* __restrict__ items,
+                                                                    int n) {
+    for (int i = blockIdx.y; i < n; i += gridDim.y) {
+        const kern::ContractArgs a = items[i].a;
+        kern::stage_d<PREC, kern::kArrangeThreads * kern::kArrangeBlocks>(
+            a, const_cast<unsigned char*>(a.Darr),
+            blockIdx.x * kern::kArrangeThreads + threadIdx.x);
     }
 }
 
@@ -173,10 +187,11 @@ __global__ __launch_bounds__((ShapeS<NTMAX>::THREADS)) void batch_staged(BatchAr
                     constexpr int CAP = kern::pmax_cap<NTMAX, S::WPE>();
                     kern::with_pmax<CAP, S::WPE, PREC == LPX_FP32 ? 2 : 0>(a.nrb, [&](auto pm) {
                         auto run = [&](auto mask) {
-                            kern::block_compute<PREC, LAYOUT, NTMAX, false, true, kTileS, S::WPE,
+                            // D from its arrangement in global memory
+                            kern::block_compute<PREC, LAYOUT, NTMAX, true, true, kTileS, S::WPE,
                                                 2, true, decltype(mask)::value,
                                                 decltype(pm)::value>(
-                                a, nullptr, ring + (n & 3) * b.ldu, row0, tt.e0 + row0, part,
+                                a, a.Darr, ring + (n & 3) * b.ldu, row0, tt.e0 + row0, part,
                                 lane, oring + (n & 1) * b.ldo);
                         };
                         if (PREC == LPX_FP32 && a.np_vec)  // uniform
@@ -236,6 +251,9 @@ struct lpx_batch {
     Item* host_items = nullptr;       // pinned host copy of the table
     Item* dev_items = nullptr;
     unsigned long long* counter = nullptr;
+    unsigned char* darr = nullptr;    // every instance's D in MFMA operand order
+    std::vector<int64_t> darr_off;    // byte offset of each slot's arrangement
+    int64_t darr_bytes = 0;
     int64_t total_tiles = 0, lds = 0;
     int grid = 0;
     bool staged = false;  // staged kernel (32-element tiles) or direct kernel (16)
@@ -262,6 +280,7 @@ void free_batch(lpx_batch* b) {
     if (b->copied) (void)hipEventDestroy(b->copied);
     if (b->dev_items) (void)hipFree(b->dev_items);
     if (b->counter) (void)hipFree(b->counter);
+    if (b->darr) (void)hipFree(b->darr);
     if (b->host_items) (void)hipHostFree(b->host_items);
     delete b;
 }
@@ -299,6 +318,8 @@ lpx_status fill_table(lpx_batch* b, const lpx_contract_desc* items, const lpx_re
         it.tile_begin = tile;
         const int64_t frag_bytes = b->precision == LPX_FP32 ? 4 : (b->precision == LPX_BF16 ? 16 : 32);
         const int64_t dbytes = g.nfrag * frag_bytes;
+        b->darr_off.push_back(b->darr_bytes);
+        b->darr_bytes += round_up(dbytes, 256);
         // direct kernel: D staged in LDS when the record keeps D on chip
         // (LDS or registers); the staged kernel reads D from global memory
         it.d_lds = !b->staged && (r.prefetch & 5) != 0 && dbytes <= kLdsBudget;
@@ -391,6 +412,7 @@ lpx_status create(const lpx_contract_desc* items, const lpx_record* recs, int32_
     if (e != hipSuccess) { free_batch(b); return hip_err(e, "batch host table"); }
     if ((s = fill_table(b, items, recs)) != LPX_OK) { free_batch(b); return s; }
     if ((e = hipMalloc((void**)&b->dev_items, sizeof(Item) * n)) != hipSuccess ||
+        (e = hipMalloc((void**)&b->darr, (size_t)b->darr_bytes)) != hipSuccess ||
         (e = hipMalloc((void**)&b->counter, sizeof(unsigned long long))) != hipSuccess ||
         (e = hipEventCreateWithFlags(&b->copied, hipEventDisableTiming)) != hipSuccess ||
         (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
@@ -416,10 +438,20 @@ lpx_status create(const lpx_contract_desc* items, const lpx_record* recs, int32_
     const int64_t need = b->staged ? b->total_tiles : ceil_div(b->total_tiles, kChunk);
     b->grid = (int)std::max<int64_t>(1, std::min(grid, need));
 
-    // Capture the launch once: the direct kernel after its counter reset.
+    for (int32_t slot = 0; slot < n; ++slot) b->host_items[slot].a.Darr = b->darr + b->darr_off[slot];
+
+    // Capture the launches once: the D arrangement, then the direct kernel
+    // after its counter reset or the staged kernel.
     BatchArgs args{b->dev_items, b->counter, b->total_tiles, n, b->ldu, b->ldo};
     e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
+        const dim3 ag(kern::kArrangeBlocks, (unsigned)std::min(n, 65535)), ab(kern::kArrangeThreads);
+        if (precision == LPX_FP32)
+            hipLaunchKernelGGL(arrange_all<LPX_FP32>, ag, ab, 0, b->cap_stream, b->dev_items, n);
+        else if (precision == LPX_BF16)
+            hipLaunchKernelGGL(arrange_all<LPX_BF16>, ag, ab, 0, b->cap_stream, b->dev_items, n);
+        else
+            hipLaunchKernelGGL(arrange_all<LPX_BF16X3>, ag, ab, 0, b->cap_stream, b->dev_items, n);
         if (!b->staged)
             hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, b->cap_stream, b->counter);
         void* kargs[] = {&args};

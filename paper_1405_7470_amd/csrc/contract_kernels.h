@@ -66,6 +66,9 @@ struct ContractArgs {
     const float* __restrict__ D;
     const float* __restrict__ u;
     float* __restrict__ out;
+    // D in MFMA operand order in global memory, written by arrange_d_kernel
+    // for kernels that read D from memory (prefetch bits 0 and 2 clear)
+    const unsigned char* __restrict__ Darr;
     int64_t E;
     int64_t ntiles;
     int K, Np, nt, nsteps, ldu;
@@ -568,6 +571,17 @@ __device__ __forceinline__ void stage_d(const ContractArgs& a, unsigned char* ld
     }
 }
 
+// The same arrangement written to global memory once per call, for kernels
+// that read D from memory: a wave's D loads are then lane-contiguous 16-byte
+// (FP32 quads, bf16 planes) or 4-byte runs instead of 16 rows of 64 bytes.
+constexpr int kArrangeThreads = 256, kArrangeBlocks = 64;
+template <int PREC>
+__global__ __launch_bounds__(kArrangeThreads) void arrange_d_kernel(ContractArgs a,
+                                                                    unsigned char* dst) {
+    stage_d<PREC, kArrangeThreads * kArrangeBlocks>(a, dst,
+                                                    blockIdx.x * kArrangeThreads + threadIdx.x);
+}
+
 // Write-back of one chunk of a wave's row blocks (p = pc + q*WPE, q < PMAX).
 // Element-major: lane l holds stacked rows R0 .. R0+3 (R0 = 16p + 4(l/16))
 // of element e; with Np % 4 == 0 they belong to one operator k = R0 / Np.
@@ -1067,9 +1081,10 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
                 for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
                     const int64_t e0 = tile * TILE_E;
                     if (e0 + 16 * eblk >= a.E) continue;  // uniform per wave; no barrier below
-                    block_compute<PREC, LAYOUT, NTMAX, PF_D, false, TILE_E, S::WPE, UNROLL, false,
-                                  true, decltype(pm)::value>(a, lds, nullptr, 0, e0 + 16 * eblk,
-                                                             part, lane);
+                    // D from LDS, or from its arrangement in global memory
+                    block_compute<PREC, LAYOUT, NTMAX, true, false, TILE_E, S::WPE, UNROLL, false,
+                                  true, decltype(pm)::value>(a, PF_D ? lds : a.Darr, nullptr, 0,
+                                                             e0 + 16 * eblk, part, lane);
                 }
             });
         }
@@ -1189,10 +1204,11 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
                 with_pmax<pmax_cap<NTMAX, S::WPE>(), S::WPE, pmax_mode<PREC, NTMAX>()>(a.nrb, [&](auto pm) {
                     auto block = [&](int64_t tile, int64_t n, int row0) {
                         auto run = [&](auto mask) {
-                            block_compute<PREC, LAYOUT, NTMAX, PF_D, true, TILE_E, S::WPE, UNROLL,
+                            // D from LDS, or from its arrangement in global memory
+                            block_compute<PREC, LAYOUT, NTMAX, true, true, TILE_E, S::WPE, UNROLL,
                                           PF_O, decltype(mask)::value, decltype(pm)::value>(
-                                a, lds, ring + (n & 3) * a.ldu, row0, tile * TILE_E + row0, part,
-                                lane, oring + (n & 1) * a.ldo);
+                                a, PF_D ? lds : a.Darr, ring + (n & 3) * a.ldu, row0,
+                                tile * TILE_E + row0, part, lane, oring + (n & 1) * a.ldo);
                         };
                         if (PREC == LPX_FP32 && a.np_vec)  // uniform
                             run(std::false_type());

@@ -78,6 +78,7 @@ lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g, vo
 
     kern::ContractArgs a;
     a.D = c.D;
+    a.Darr = nullptr;
     a.u = c.u;
     a.out = c.out;
     a.E = c.E;
@@ -92,11 +93,36 @@ lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g, vo
     a.ldo = g.ldo;
     a.np_vec = (c.Np % 4) == 0;
     a.e_vec = (c.E % 4) == 0;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    // Kernels that read D from memory read its MFMA-order arrangement,
+    // written by a pre-pass into a stream-ordered workspace.
+    unsigned char* darr = nullptr;
+    const bool arrange = (g.prefetch & 5) == 0;
+    if (arrange) {
+        if ((s = keep_pool()) != LPX_OK) return s;
+        const int64_t frag_bytes = g.prec == LPX_FP32 ? 4 : (g.prec == LPX_BF16 ? 16 : 32);
+        hipError_t e = hipMallocAsync((void**)&darr, (size_t)(g.nfrag * frag_bytes), st);
+        if (e != hipSuccess)
+            return set_error(LPX_ERR_HIP, "D arrangement workspace: %s", hipGetErrorString(e));
+        a.Darr = darr;
+        const dim3 ag(kern::kArrangeBlocks), ab(kern::kArrangeThreads);
+        if (g.prec == LPX_FP32)
+            hipLaunchKernelGGL(kern::arrange_d_kernel<LPX_FP32>, ag, ab, 0, st, a, darr);
+        else if (g.prec == LPX_BF16)
+            hipLaunchKernelGGL(kern::arrange_d_kernel<LPX_BF16>, ag, ab, 0, st, a, darr);
+        else
+            hipLaunchKernelGGL(kern::arrange_d_kernel<LPX_BF16X3>, ag, ab, 0, st, a, darr);
+    }
     void* args[] = {&a};
-    hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)grid),
-                                   dim3(g.threads), args, (size_t)g.lds_bytes,
-                                   reinterpret_cast<hipStream_t>(stream));
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)grid),
+                            dim3(g.threads), args, (size_t)g.lds_bytes, st);
     if (e == hipSuccess) e = hipGetLastError();
+    if (arrange) {
+        const hipError_t ef = hipFreeAsync(darr, st);
+        if (e == hipSuccess) e = ef;
+    }
     if (e != hipSuccess)
         return set_error(LPX_ERR_HIP, "contraction launch: %s", hipGetErrorString(e));
     return LPX_OK;

@@ -259,6 +259,8 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(Args g) {
         }
 }
 
+}  // namespace gsplit
+
 // The device's default memory pool keeps freed workspace for reuse (its
 // release threshold is raised once per device); otherwise every call would
 // pay for a fresh allocation after each synchronisation.
@@ -279,6 +281,8 @@ lpx_status keep_pool() {
     done.insert(dev);
     return LPX_OK;
 }
+
+namespace gsplit {
 
 template <int PLANES>
 lpx_status run(const lpx_gemm_desc& d, hipStream_t st) {

@@ -113,6 +113,10 @@ lpx_status tuned_lookup(const lpx_problem& p, lpx_record* out);
 lpx_status tuned_store(const lpx_problem& p, const lpx_record& r);
 
 // Launches the contraction kernel for a validated problem.
+// Makes the device's default memory pool keep freed blocks (stream-ordered
+// workspaces are then reused without returning to the driver).
+lpx_status keep_pool();
+
 lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g,
                            void* stream);
 
