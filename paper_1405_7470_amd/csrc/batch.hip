@@ -64,7 +64,8 @@ template <int PREC, int LAYOUT, int NTMAX>
 __global__ __launch_bounds__(kThreadsB) void batch_kernel(BatchArgs b) {
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ long long s_t0;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // scalar: uniform per wave
     int cur = -1;
     for (;;) {
         if (tid == 0) s_t0 = (long long)atomicAdd(b.counter, (unsigned long long)kChunk);
@@ -137,7 +138,8 @@ __global__ __launch_bounds__((ShapeS<NTMAX>::THREADS)) void batch_staged(BatchAr
     extern __shared__ __align__(16) unsigned char lds[];
     float* ring = reinterpret_cast<float*>(lds);
     float* oring = ring + 4 * b.ldu;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // scalar: uniform per wave
     const int64_t t0 = blockIdx.x, g = gridDim.x;
     const int64_t nmine = t0 < b.total_tiles ? (b.total_tiles - 1 - t0) / g + 1 : 0;
     const int64_t niter = nmine + 1;  // store waves trail by one tile

@@ -1056,7 +1056,9 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    // the same in every lane of a wave: scalar, so role branches and
+    // per-wave LDS addresses stay in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t nfrag = (int64_t)a.nrb * a.nsteps * 64;
     float* ring = reinterpret_cast<float*>(
         lds + (PF_D ? nfrag * Lds<PREC>::DFRAG_BYTES * Lds<PREC>::PLANES : 0));
