@@ -5,6 +5,10 @@ they support:
 
 * ``stats``: the top kernels of a ``--kernel-trace --stats`` run (calls,
   average and total duration) from its ``*_kernel_stats.csv``.
+* ``counters``: per-dispatch averages of SQ/GRBM counters from one
+  ``--pmc`` run for the contraction kernels a bench.py line names, with the
+  MFMA utilisation they imply (SQ_VALU_MFMA_BUSY_CYCLES over four SIMDs
+  times SQ_BUSY_CU_CYCLES).
 * ``traffic``: HBM bytes per launch of every contraction kernel from two
   ``--pmc`` runs (``FETCH_SIZE``, then ``WRITE_SIZE``; KiB per dispatch).
   Each counter is scaled by what it reads for the plain copy kernel
@@ -155,6 +159,42 @@ def timed_region(trace_csv, kernels, steps):
     return avg, len(use)
 
 
+def counters(csv_path):
+    """{kernel name: {counter: average per dispatch}} from a --pmc run."""
+    vals = defaultdict(lambda: defaultdict(list))
+    with open(csv_path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            vals[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in vals.items()}
+
+
+def write_counters(csv_path, bench_json, out, cmd, title):
+    import json
+    b = json.load(open(bench_json))
+    sel = b["config"]["selection"]
+    per = b["variants"][sel]["per_problem"]
+    Np = int(re.search(r"Np=(\d+)", b["config"]["workload"]).group(1))
+    table = counters(csv_path)
+    names = sorted({c for k in table for c in table[k]})
+    with open(out, "w") as fh:
+        fh.write(f"# {title}\n\nCommand: `{cmd}`\n\n")
+        fh.write("Per-dispatch averages (counters summed over the device) for the kernels of "
+                 f"the {sel} records; MFMA utilisation = SQ_VALU_MFMA_BUSY_CYCLES / "
+                 "(4 SIMDs x SQ_BUSY_CU_CYCLES).\n\n")
+        fh.write("| problem | kernel | MFMA utilisation | " + " | ".join(names) + " |\n")
+        fh.write("|---|---|---|" + "---|" * len(names) + "\n")
+        for key, v in per.items():
+            rec = _Rec(v["record"])
+            kname = contraction_kernel_name(rec.precision, key.split("/")[0], Np, rec)
+            row = table.get(kname)
+            if row is None:
+                continue
+            util = (row.get("SQ_VALU_MFMA_BUSY_CYCLES", float("nan")) /
+                    (4.0 * row.get("SQ_BUSY_CU_CYCLES", float("nan"))))
+            fh.write(f"| {key} | `{kname}` | {util:.3f} | " +
+                     " | ".join(f"{row.get(c, float('nan')):.4g}" for c in names) + " |\n")
+
+
 def write_stats(csv_path, out, cmd, title, top=25, trace_csv=None, bench_json=None):
     with open(csv_path, newline="") as fh:
         rows = list(csv.DictReader(fh))
@@ -201,6 +241,12 @@ def main():
     a.add_argument("--title", default="rocprofv3 kernel statistics")
     a.add_argument("--trace", default=None, help="the run's *_kernel_trace.csv")
     a.add_argument("--bench-json", default=None, help="the bench.py line of the same run")
+    c = sub.add_parser("counters")
+    c.add_argument("--csv", required=True)
+    c.add_argument("--bench-json", required=True)
+    c.add_argument("--out", required=True)
+    c.add_argument("--cmd", required=True)
+    c.add_argument("--title", default="SQ counters of the contraction kernels")
     b = sub.add_parser("traffic")
     b.add_argument("--fetch", required=True)
     b.add_argument("--write", required=True)
@@ -213,6 +259,8 @@ def main():
     if args.what == "stats":
         write_stats(args.csv, args.out, args.cmd, args.title, trace_csv=args.trace,
                     bench_json=args.bench_json)
+    elif args.what == "counters":
+        write_counters(args.csv, args.bench_json, args.out, args.cmd, args.title)
     else:
         rows, ff, fw = traffic(args.fetch, args.write, args.copy_bytes)
         write_traffic(args.out, rows, ff, fw, args.copy_bytes, args.cmd_fetch, args.cmd_write,
