@@ -109,7 +109,11 @@ typedef int32_t lpx_status;
  *              touch no global memory at all.
  *              Bits 0 and 2 are exclusive.  A clear bit means that array's
  *              MFMA operands are loaded from global memory straight into
- *              registers (or, for the output, stored straight from them).
+ *              registers (or, for the output, stored straight from them);
+ *              with bits 0 and 2 both clear, D is read from an MFMA-order
+ *              copy that a pre-pass kernel writes once per call into a
+ *              stream-ordered workspace (nrb*nsteps*64 fragments; taken
+ *              from and returned to the device's default memory pool).
  *   unroll   : 1, 2 or 4; the reduction loop over MFMA k-steps is split by
  *              `unroll` and the inner part unrolled (tag "unr", sec. 2.4.2).
  *   precision: LPX_FP32 / LPX_BF16 / LPX_BF16X3.
@@ -214,7 +218,9 @@ lpx_status lpx_contract_lds_bytes(const lpx_problem* p, const lpx_record* rec,
  * written exactly once; nothing outside `out` is written.  Summation order
  * is the variant's own (the programming model is unordered, sec. 2.3), so
  * results of different records agree to rounding, and bit for bit when all
- * partial sums are exact. */
+ * partial sums are exact.  Records that read D from memory (prefetch bits 0
+ * and 2 clear) allocate a workspace on `stream` (hipMallocAsync) and free it
+ * after the kernel; the others allocate nothing. */
 lpx_status lpx_contract(const lpx_contract_desc* c, const lpx_record* rec,
                         void* stream);
 
