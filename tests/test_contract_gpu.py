@@ -94,6 +94,26 @@ def test_row_blocks_across_operators(layout):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
+def test_arranged_d_matches_lds_staged_d(layout):
+    """Records that read D from memory read its MFMA-order arrangement
+    written by a pre-pass; the same fragments staged in LDS (prefetch bit 0)
+    must give identical bits, at shapes where both exist (FP32 and bf16x3
+    Np = 84, bf16 Np = 120), with ragged tiles."""
+    for precision, Np in (("fp32", 84), ("bf16", 120), ("bf16x3", 84)):
+        D, u = inputs.contraction_inputs(3, Np, 777, seed=Np, layout=layout)
+        ref_rec = lpx.record(precision, 16, 1, 1)
+        assert supported(3, Np, 777, layout, ref_rec)
+        ref = run(D, u, layout, ref_rec)
+        check_against_oracle(D, u, as_em(ref, layout), layout, precision)
+        for t, p, un in ((16, 0, 1), (64, 0, 4), (32, 2, 2), (64, 10, 1)):
+            rec = lpx.record(precision, t, p, un)
+            if not supported(3, Np, 777, layout, rec):
+                continue
+            print(f"case: arranged D {precision} {layout} Np={Np} {lpx.describe(rec)}", flush=True)
+            assert torch.equal(run(D, u, layout, rec), ref), lpx.describe(rec)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
 def test_many_tiles_per_work_group(layout):
     """E large enough that every work-group walks several tiles (the
     staged pipelines' steady state and drain) with a ragged last tile.  All
