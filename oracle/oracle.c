@@ -11,7 +11,7 @@
  * for GPUs and CPUs", ARRAY'14):
  *
  *   - the reduction  sum(j, D[k,i,j] * u[e,j])  written in the paper's
- *     reduction syntax (sec. 2.1, "Reductions are allowed"), i.e. the
+ *     reduction syntax (sec. 2.1, which admits reductions in instructions), i.e. the
  *     element-local operator application behind Table 1's "dG FEM volume"
  *     row:   out[k,e,i] = sum_j D[k][i][j] * u[e][j];
  *   - its degenerate case C[m,n] = sum_k A[m,k]*B[k,n], the paper's own
