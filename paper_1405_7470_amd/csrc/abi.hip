@@ -89,6 +89,16 @@ lpx_status contract_geometry(int K, int Np, int64_t E, int layout,
                          (long long)K * Np);
     g->nrb = (int)ceil_div((int64_t)K * Np, 16);
     g->nfrag = (int64_t)g->nrb * g->nsteps * 64;
+    // D's MFMA-order arrangement (in LDS or global memory) is indexed by
+    // fragment with 32-bit integers, the bf16x3 lo plane after the hi plane.
+    {
+        const int64_t planes = r.precision == LPX_BF16X3 ? 2 : 1;
+        if (g->nfrag * planes > (int64_t)INT32_MAX)
+            return set_error(LPX_ERR_UNSUPPORTED,
+                             "K=%d Np=%d needs %lld D fragments per plane; the operator "
+                             "arrangement holds at most 2^31 - 1 (over all planes)",
+                             K, Np, (long long)g->nfrag);
+    }
     // A staged u tile is a raw copy of the tile (tile_e * Np floats) plus
     // slack for reads of padding columns up to the next multiple of 32.
     // u ring slot stride in floats: a raw tile copy with slack for reads of

@@ -138,9 +138,30 @@ def test_stacked_rows_limit():
     # the K operators are stacked into K*Np MFMA rows indexed with 32-bit
     # integers: K*Np beyond 2^31 - 16 is refused before any HIP call
     far = dict(u=A + (1 << 44), out=A + (1 << 45))  # D of 2^41 bytes does not overlap them
-    assert status(desc(K=(1 << 24) - 1, Np=128, **far)) == lpx.OK  # 2^31 - 128 rows
     assert status(desc(K=1 << 24, Np=128, **far)) == lpx.ERR_UNSUPPORTED  # 2^31 rows
     assert "stacked operator rows" in lpx.last_error()
+
+
+@pytest.mark.parametrize("prec,Np,kmax", [
+    # fp32: ceil(K*Np/16) row blocks * ceil(Np/4) k-steps * 64 lanes
+    ("fp32", 128, (1 << 17) - 1),     # 2^14 fragments per operator
+    ("fp32", 1, (1 << 29) - 16),      # one k-step, K/16 row blocks
+    # bf16x3: ceil(Np/32) k-steps, two planes (hi, lo) in one index space
+    ("bf16x3", 128, (1 << 19) - 1),   # 2^11 fragments per operator, x2 planes
+    ("bf16", 128, (1 << 20) - 1),
+])
+def test_d_fragment_index_limit(prec, Np, kmax):
+    # D's MFMA-order arrangement is indexed with 32-bit integers: problems
+    # whose fragment count (times the planes) reaches 2^31 are refused before
+    # any HIP call, for every record (validation only; no GPU run)
+    far = dict(u=A + (1 << 44), out=A + (1 << 45))
+    for pf in (0, 1, 2):
+        rec = lpx.record(prec, 16, pf, 1)
+        assert status(desc(K=kmax, Np=Np, E=16, **far), rec) in (lpx.OK, lpx.ERR_UNSUPPORTED)
+        if pf == 0:
+            assert status(desc(K=kmax, Np=Np, E=16, **far), rec) == lpx.OK
+        assert status(desc(K=kmax + 16, Np=Np, E=16, **far), rec) == lpx.ERR_UNSUPPORTED
+        assert "D fragments" in lpx.last_error()
 
 
 def test_register_d_limits():
