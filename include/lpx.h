@@ -96,7 +96,7 @@ typedef int32_t lpx_status;
  *              bit 0: all of D is staged in LDS once per work-group, in
  *              MFMA operand order and converted to the operand precision;
  *              bit 1: each u tile is staged in LDS by dedicated loader waves
- *              that keep two tiles in flight (a two-slot LDS ring, one
+ *              that keep three tiles in flight (a four-slot LDS ring, one
  *              work-group barrier per tile);
  *              bit 2: D is precomputed into private memory -- each wave
  *              keeps the D fragments of its own 16-row blocks of the
@@ -113,7 +113,11 @@ typedef int32_t lpx_status;
  *              with bits 0 and 2 both clear, D is read from an MFMA-order
  *              copy that a pre-pass kernel writes once per call into a
  *              stream-ordered workspace (nrb*nsteps*64 fragments; taken
- *              from and returned to the device's default memory pool).
+ *              from and returned to a memory pool the library creates and
+ *              owns per device -- the device's default pool is not
+ *              touched).  The untuned default record is such a record: it
+ *              launches this pre-pass and allocates this workspace on every
+ *              call.
  *   unroll   : 1, 2 or 4; the reduction loop over MFMA k-steps is split by
  *              `unroll` and the inner part unrolled (tag "unr", sec. 2.4.2).
  *   precision: LPX_FP32 / LPX_BF16 / LPX_BF16X3.
@@ -219,8 +223,10 @@ lpx_status lpx_contract_lds_bytes(const lpx_problem* p, const lpx_record* rec,
  * is the variant's own (the programming model is unordered, sec. 2.3), so
  * results of different records agree to rounding, and bit for bit when all
  * partial sums are exact.  Records that read D from memory (prefetch bits 0
- * and 2 clear) allocate a workspace on `stream` (hipMallocAsync) and free it
- * after the kernel; the others allocate nothing. */
+ * and 2 clear, the untuned default among them) launch a pre-pass kernel
+ * that writes D's MFMA-order arrangement into a workspace allocated on
+ * `stream` from the library's own memory pool, and free it after the
+ * kernel; the others allocate nothing and launch one kernel. */
 lpx_status lpx_contract(const lpx_contract_desc* c, const lpx_record* rec,
                         void* stream);
 
@@ -242,7 +248,8 @@ lpx_status lpx_contract_validate(const lpx_contract_desc* c, const lpx_record* r
  * 128x256x32, 256x256x32; others return LPX_ERR_UNSUPPORTED.  BF16 / BF16X3
  * at 128x128x64 (with K > 0) first split both operands once into
  * K-contiguous bf16 planes (B transposed) in stream-ordered workspace
- * (hipMallocAsync on `stream`, freed the same way), then stream the planes
+ * (allocated on `stream` from the library's own memory pool, freed the
+ * same way), then stream the planes
  * into LDS with direct global-to-LDS loads; the other tilings convert the
  * FP32 operands slab by slab.  C is overwritten (no alpha/beta).  rec = NULL
  * means FP32 with the default tiling.  Errors as for lpx_contract. */

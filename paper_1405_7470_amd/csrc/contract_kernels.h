@@ -296,7 +296,8 @@ __device__ __forceinline__ f4 u_quad_global(const ContractArgs& a, int64_t eb0, 
 //   fp32 quads are lane-major inside their 4*64-float block: step 4Q+m of
 //   pair p, lane l sits at (p*nsteps + 4Q)*64 + 4l + m (one 16-byte read
 //   per lane and quad); the steps after the last quad keep operand order.
-// [u ring: two slots of ldu floats, raw FP32 copies of u tiles]
+// [u ring: four slots of ldu floats, raw FP32 copies of u tiles]
+// [output ring (prefetch bit 3): two slots of ldo floats]
 template <int PREC>
 struct Lds {
     static constexpr int DFRAG_BYTES = PREC == LPX_FP32 ? 4 : 16;  // per plane
@@ -338,7 +339,7 @@ __device__ __forceinline__ void d_frag_store_lds(unsigned char* lds, int64_t nfr
 
 // ---------------------------------------------------- staged u tiles
 // A staged u tile is a raw copy of the tile's bytes in global memory, in a
-// two-slot LDS ring:
+// four-slot LDS ring (three tiles in flight while the fourth is read):
 //   element-major: the contiguous run u[e0 .. e0+nvalid)[0 .. Np), so
 //                  element r, column j sits at r*Np + j;
 //   DOF-major:     the Np row segments u[j][e0 .. e0+TILE_E), so column j,
@@ -1065,6 +1066,10 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
     float* oring = ring + 4 * a.ldu;  // staged output slots follow the u slots
 
     if constexpr (PF_D) stage_d<PREC, S::THREADS>(a, lds, tid);
+    // With a staged u tile every role has written part of D: one full
+    // barrier (LDS writes complete, then s_barrier) before any role goes on,
+    // since the loader waves' own barriers do not wait for LDS writes.
+    if constexpr (PF_D && PF_U) __syncthreads();
 
     if constexpr (!PF_U) {
         if constexpr (PF_D) __syncthreads();

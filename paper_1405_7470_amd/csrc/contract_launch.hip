@@ -99,11 +99,10 @@ lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g, vo
     unsigned char* darr = nullptr;
     const bool arrange = (g.prefetch & 5) == 0;
     if (arrange) {
-        if ((s = keep_pool()) != LPX_OK) return s;
         const int64_t frag_bytes = g.prec == LPX_FP32 ? 4 : (g.prec == LPX_BF16 ? 16 : 32);
-        hipError_t e = hipMallocAsync((void**)&darr, (size_t)(g.nfrag * frag_bytes), st);
-        if (e != hipSuccess)
-            return set_error(LPX_ERR_HIP, "D arrangement workspace: %s", hipGetErrorString(e));
+        s = workspace_alloc((void**)&darr, (size_t)(g.nfrag * frag_bytes), stream,
+                            "D arrangement");
+        if (s != LPX_OK) return s;
         a.Darr = darr;
         const dim3 ag(kern::kArrangeBlocks), ab(kern::kArrangeThreads);
         if (g.prec == LPX_FP32)

@@ -26,7 +26,8 @@
 
 #include <cstdint>
 #include <mutex>
-#include <set>
+#include <cstring>
+#include <map>
 
 #include "lpx_internal.h"
 
@@ -261,24 +262,49 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(Args g) {
 
 }  // namespace gsplit
 
-// The device's default memory pool keeps freed workspace for reuse (its
-// release threshold is raised once per device); otherwise every call would
-// pay for a fresh allocation after each synchronisation.
-lpx_status keep_pool() {
-    static std::mutex mu;
-    static std::set<int> done;
+// Stream-ordered workspace comes from a memory pool the library creates
+// and owns, one per device, whose release threshold is raised so that freed
+// blocks stay in the pool for the next call (otherwise every call would pay
+// for a fresh allocation after each synchronisation).  The device's default
+// pool, which other code in the process may use, is left untouched.
+namespace {
+std::mutex g_pool_mu;
+std::map<int, hipMemPool_t> g_pools;
+}  // namespace
+
+static lpx_status library_pool(hipMemPool_t* out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return set_error(LPX_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
-    std::lock_guard<std::mutex> lock(mu);
-    if (done.count(dev)) return LPX_OK;
-    hipMemPool_t pool;
-    e = hipDeviceGetDefaultMemPool(&pool, dev);
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    auto it = g_pools.find(dev);
+    if (it != g_pools.end()) {
+        *out = it->second;
+        return LPX_OK;
+    }
+    hipMemPoolProps props;
+    std::memset(&props, 0, sizeof props);
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    e = hipMemPoolCreate(&pool, &props);
     uint64_t keep = UINT64_MAX;
     if (e == hipSuccess) e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
     if (e != hipSuccess)
-        return set_error(LPX_ERR_HIP, "memory pool setup: %s", hipGetErrorString(e));
-    done.insert(dev);
+        return set_error(LPX_ERR_HIP, "library memory pool: %s", hipGetErrorString(e));
+    g_pools[dev] = pool;
+    *out = pool;
+    return LPX_OK;
+}
+
+lpx_status workspace_alloc(void** p, size_t bytes, void* stream, const char* what) {
+    hipMemPool_t pool = nullptr;
+    lpx_status s = library_pool(&pool);
+    if (s != LPX_OK) return s;
+    hipError_t e = hipMallocFromPoolAsync(p, bytes, pool, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return set_error(LPX_ERR_HIP, "%s workspace: %s", what, hipGetErrorString(e));
     return LPX_OK;
 }
 
@@ -286,13 +312,12 @@ namespace gsplit {
 
 template <int PLANES>
 lpx_status run(const lpx_gemm_desc& d, hipStream_t st) {
-    lpx_status ks = keep_pool();
-    if (ks != LPX_OK) return ks;
     const int64_t Kp = round_up(d.K, TK);
     const int64_t abytes = (int64_t)PLANES * d.M * Kp * 2, bbytes = (int64_t)PLANES * d.N * Kp * 2;
     void* ws = nullptr;
-    hipError_t e = hipMallocAsync(&ws, (size_t)(abytes + bbytes), st);
-    if (e != hipSuccess) return set_error(LPX_ERR_HIP, "GEMM workspace: %s", hipGetErrorString(e));
+    lpx_status ks = workspace_alloc(&ws, (size_t)(abytes + bbytes), st, "GEMM");
+    if (ks != LPX_OK) return ks;
+    hipError_t e;
     __bf16* As = static_cast<__bf16*>(ws);
     __bf16* Bs = reinterpret_cast<__bf16*>(static_cast<unsigned char*>(ws) + abytes);
     const int64_t na = d.M * (Kp / 8);

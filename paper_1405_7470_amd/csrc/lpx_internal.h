@@ -112,10 +112,12 @@ bool aligned16(const void* p);
 lpx_status tuned_lookup(const lpx_problem& p, lpx_record* out);
 lpx_status tuned_store(const lpx_problem& p, const lpx_record& r);
 
+// Stream-ordered workspace of `bytes` on `stream` from the library's own
+// memory pool of the current device (freed with hipFreeAsync on the same
+// stream; freed blocks stay in the pool for reuse).
+lpx_status workspace_alloc(void** p, size_t bytes, void* stream, const char* what);
+
 // Launches the contraction kernel for a validated problem.
-// Makes the device's default memory pool keep freed blocks (stream-ordered
-// workspaces are then reused without returning to the driver).
-lpx_status keep_pool();
 
 lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g,
                            void* stream);
