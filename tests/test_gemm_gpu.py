@@ -1,6 +1,7 @@
 """GEMM (the contraction's degenerate case) through lpx_gemm vs the FP64
 oracle: every built tiling and precision on ragged shapes, exact integer
-inputs, identity, and sampled rows at 4096^3 and 8192 x 1024 x 4096."""
+inputs, identity, and at 4096^3 and 8192 x 1024 x 4096 a NaN sentinel over
+all of C plus one row of every m-tile and a column stripe of every n-tile."""
 import numpy as np
 import pytest
 import torch
@@ -72,20 +73,40 @@ def test_gemm_strided_rows():
 
 
 @pytest.mark.parametrize("shape", [(4096, 4096, 4096), (8192, 1024, 4096)])
-def test_gemm_full_size_sampled_rows(shape):
+def test_gemm_full_size_every_tile(shape):
+    """Full-size shapes, where the work-groups' XCD-grouped tile order runs
+    (its remap applies only when the tile count is a multiple of 8): C is
+    filled with NaN and none may remain; one row of every 128-row m-tile and
+    a 4-column stripe (all rows) of every 128-column n-tile are checked
+    against the FP64 oracle and its emulation of the precision."""
     M, N, K = shape
     A, B = inputs.gemm_inputs(M, N, K, seed=0)
     Ad, Bd = to_dev(A), to_dev(B)
-    rows = [0, 1, M // 2 + 17, M - 1]
-    for precision, tiles in (("fp32", (128, 128, 32)), ("bf16", (128, 128, 32)),
-                             ("bf16x3", (128, 128, 32)), ("bf16", (128, 128, 64)),
-                             ("bf16x3", (128, 128, 64))):
+    rows = [t * 128 + (37 * t + 5) % 128 for t in range(M // 128)]
+    cols = [t * 128 + c for t in range(N // 128) for c in ((29 * t + 3) % 125,)]
+    cols = sorted(c + d for c in cols for d in range(4))
+    # row m of C depends only on row m of A, column n only on column n of B
+    Ar = np.ascontiguousarray(A[rows])
+    Bc = np.ascontiguousarray(B[:, cols])
+    refs = {prec: (oracle.gemm(Ar, B, prec), oracle.gemm(A, Bc, prec))
+            for prec in ("fp32", "bf16", "bf16x3")}
+    for precision, tiles in (("fp32", (128, 128, 64)), ("bf16", (128, 128, 64)),
+                             ("bf16x3", (128, 128, 64)), ("fp32", (128, 128, 32)),
+                             ("bf16", (128, 128, 32)), ("bf16x3", (128, 128, 32))):
         rec = lpx.record(precision, gemm=tiles)
         print(f"case: gemm full {shape} {lpx.describe(rec)}", flush=True)
-        C = lpx.gemm(Ad, Bd, record=rec)
+        C = torch.full((M, N), float("nan"), device="cuda")
+        lpx.gemm(Ad, Bd, C=C, record=rec)
         torch.cuda.synchronize()
-        for m in rows:
-            check(C[m:m + 1].double().cpu().numpy(), A, B, precision, m0=m)
+        assert not bool(torch.isnan(C).any()), ("unwritten tiles", lpx.describe(rec))
+        got_r = C[rows].double().cpu().numpy()
+        got_c = C[:, cols].double().cpu().numpy()
+        for got, ref, emu in ((got_r, refs["fp32"][0], refs[precision][0]),
+                              (got_c, refs["fp32"][1], refs[precision][1])):
+            err = oracle.rel_err(got, ref)
+            assert err <= TOL[precision], (precision, tiles, err)
+            if precision != "fp32":
+                assert oracle.rel_err(got, emu) <= emu_tol(K), (precision, tiles)
         del C
 
 
