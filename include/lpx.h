@@ -230,6 +230,29 @@ lpx_status lpx_contract_lds_bytes(const lpx_problem* p, const lpx_record* rec,
 lpx_status lpx_contract(const lpx_contract_desc* c, const lpx_record* rec,
                         void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * contraction as lpx_contract, with the same kernels and bit-identical
+ * results, but no allocation of any kind (no hipMalloc, hipFree or
+ * stream-ordered allocation).  Records that read D from memory (prefetch
+ * bits 0 and 2 clear, the untuned default among them) write D's MFMA-order
+ * arrangement into a static scratch array of LPX_NOALLOC_SCRATCH_BYTES in
+ * device memory instead of a per-call workspace; each GPU the library runs
+ * on holds its own copy of that array until the process ends.  The
+ * arrangement takes nrb*nsteps*64 fragments of 4 (FP32), 16 (BF16) or 32
+ * (BF16X3) bytes, nrb = ceil(K*Np/16), nsteps = ceil(Np/4) for FP32 and
+ * ceil(Np/32) otherwise (K = 3, Np = 128: 192 KiB in every precision); a
+ * problem whose arrangement is larger fails with LPX_ERR_UNSUPPORTED before
+ * any HIP call.  Other records use no scratch.  Every call on a GPU shares
+ * that GPU's array and nothing in it needs clearing (each call rewrites
+ * what it reads): calls that overlap on one GPU -- on different streams,
+ * or from threads without ordering between them -- race on it and may
+ * return wrong results.  The first call on a device looks up the array's
+ * device address (hipGetSymbolAddress).  Errors as for lpx_contract. */
+#define LPX_NOALLOC_SCRATCH_BYTES 1048576
+lpx_status lpx_contract_noalloc(const lpx_contract_desc* c, const lpx_record* rec,
+                                void* stream);
+
 /* Runs every check lpx_contract makes before enqueueing (arguments,
  * record, assumption, aliasing, LDS budget) and returns the status
  * lpx_contract would return for them, without any HIP call and without

@@ -373,6 +373,24 @@ lpx_status lpx_contract(const lpx_contract_desc* c, const lpx_record* rec, void*
     }
 }
 
+lpx_status lpx_contract_noalloc(const lpx_contract_desc* c, const lpx_record* rec,
+                                void* stream) {
+    clear_error();
+    try {
+        ContractGeom g;
+        lpx_status s = validate_contract(c, rec, &g);
+        if (s != LPX_OK || g.ntiles == 0) return s;
+        if (darr_bytes(g) > LPX_NOALLOC_SCRATCH_BYTES)
+            return set_error(LPX_ERR_UNSUPPORTED,
+                             "lpx_contract_noalloc: D's arrangement needs %lld bytes, above the "
+                             "%d-byte scratch (K=%d Np=%d)",
+                             (long long)darr_bytes(g), LPX_NOALLOC_SCRATCH_BYTES, c->K, c->Np);
+        return launch_contract(*c, g, stream, true);
+    } catch (...) {
+        return set_error(LPX_ERR_INTERNAL, "unexpected C++ exception");
+    }
+}
+
 lpx_status lpx_gemm_validate(const lpx_gemm_desc* g, const lpx_record* rec) {
     clear_error();
     try {

@@ -56,9 +56,47 @@ lpx_status blocks_per_cu(const void* fn, int threads, int64_t lds, int device, i
     return LPX_OK;
 }
 
+// Device scratch for lpx_contract_noalloc: D's MFMA-order arrangement of
+// records that read D from memory goes here instead of into a workspace
+// allocated per call.  Every GPU the library runs on holds one copy until
+// the process ends.  In host code `scratch` names a host-side stand-in, not
+// the device address: the address is looked up once per device with
+// hipGetSymbolAddress and only that pointer is passed to kernels.
+__device__ __align__(256) unsigned char scratch[LPX_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char*> g_scratch;  // device -> address of its `scratch`
+
+lpx_status scratch_address(unsigned char** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_error(LPX_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it != g_scratch.end()) {
+        *out = it->second;
+        return LPX_OK;
+    }
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+        return set_error(LPX_ERR_HIP, "hipGetSymbolAddress(scratch): %s",
+                         e != hipSuccess ? hipGetErrorString(e) : "null address");
+    g_scratch[dev] = static_cast<unsigned char*>(p);
+    *out = g_scratch[dev];
+    return LPX_OK;
+}
+
 }  // namespace
 
-lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g, void* stream) {
+int64_t darr_bytes(const ContractGeom& g) {
+    if (g.prefetch & 5) return 0;  // D in LDS or registers: no arrangement in memory
+    const int64_t frag_bytes = g.prec == LPX_FP32 ? 4 : (g.prec == LPX_BF16 ? 16 : 32);
+    return g.nfrag * frag_bytes;
+}
+
+lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g, void* stream,
+                           bool noalloc) {
     DeviceInfo dev;
     lpx_status s = current_device_info(&dev);
     if (s != LPX_OK) return s;
@@ -98,10 +136,16 @@ lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g, vo
     // written by a pre-pass into a stream-ordered workspace.
     unsigned char* darr = nullptr;
     const bool arrange = (g.prefetch & 5) == 0;
+    const bool own_ws = arrange && !noalloc;  // a workspace this call allocates and frees
     if (arrange) {
-        const int64_t frag_bytes = g.prec == LPX_FP32 ? 4 : (g.prec == LPX_BF16 ? 16 : 32);
-        s = workspace_alloc((void**)&darr, (size_t)(g.nfrag * frag_bytes), stream,
-                            "D arrangement");
+        if (noalloc) {
+            if (darr_bytes(g) > LPX_NOALLOC_SCRATCH_BYTES)
+                return set_error(LPX_ERR_UNSUPPORTED, "D arrangement needs %lld bytes, scratch holds %d",
+                                 (long long)darr_bytes(g), LPX_NOALLOC_SCRATCH_BYTES);
+            s = scratch_address(&darr);
+        } else {
+            s = workspace_alloc((void**)&darr, (size_t)darr_bytes(g), stream, "D arrangement");
+        }
         if (s != LPX_OK) return s;
         a.Darr = darr;
         const dim3 ag(kern::kArrangeBlocks), ab(kern::kArrangeThreads);
@@ -118,7 +162,7 @@ lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g, vo
         e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)grid),
                             dim3(g.threads), args, (size_t)g.lds_bytes, st);
     if (e == hipSuccess) e = hipGetLastError();
-    if (arrange) {
+    if (own_ws) {
         const hipError_t ef = hipFreeAsync(darr, st);
         if (e == hipSuccess) e = ef;
     }

@@ -119,8 +119,15 @@ lpx_status workspace_alloc(void** p, size_t bytes, void* stream, const char* wha
 
 // Launches the contraction kernel for a validated problem.
 
+// noalloc: D's arrangement (if the record reads D from memory) goes to the
+// library's static device scratch instead of a per-call workspace; the
+// caller has checked darr_bytes(g) against LPX_NOALLOC_SCRATCH_BYTES.
 lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g,
-                           void* stream);
+                           void* stream, bool noalloc = false);
+
+// Bytes of D's MFMA-order arrangement in memory for a geometry (0 when the
+// record keeps D in LDS or registers).
+int64_t darr_bytes(const ContractGeom& g);
 
 // GEMM tiling of a record (defaults filled in); LPX_ERR_UNSUPPORTED if that
 // tiling is not built for the record's precision.

@@ -30,6 +30,7 @@ ERR_INTERNAL = 8
 PRECISION = {"fp32": 0, "bf16": 1, "bf16x3": 2}
 PRECISION_NAME = {v: k for k, v in PRECISION.items()}
 LAYOUT = {"em": 0, "dm": 1}
+NOALLOC_SCRATCH_BYTES = 1 << 20   # LPX_NOALLOC_SCRATCH_BYTES
 RECORD_VERSION = 1
 
 
@@ -119,6 +120,8 @@ def lib():
                                              ctypes.POINTER(ctypes.c_int64)]
         L.lpx_contract_validate.argtypes = [ctypes.POINTER(ContractDesc), ctypes.POINTER(Record)]
         L.lpx_contract.argtypes = [ctypes.POINTER(ContractDesc), ctypes.POINTER(Record), vp]
+        L.lpx_contract_noalloc.argtypes = [ctypes.POINTER(ContractDesc), ctypes.POINTER(Record),
+                                           vp]
         L.lpx_split_bf16.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
         L.lpx_autotune.argtypes = [ctypes.POINTER(ContractDesc), ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, vp, ctypes.c_int64, vp, ctypes.POINTER(Record),
@@ -162,7 +165,7 @@ def lib():
         for name in ("lpx_autotune", "lpx_tune_cache_insert", "lpx_tune_cache_clear",
                      "lpx_record_default", "lpx_record_validate", "lpx_record_describe",
                      "lpx_record_enumerate", "lpx_contract_lds_bytes", "lpx_contract_validate",
-                     "lpx_contract", "lpx_split_bf16"):
+                     "lpx_contract", "lpx_contract_noalloc", "lpx_split_bf16"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -300,6 +303,23 @@ def contract(D, u, out=None, layout="em", record=None, stream=None):
     recp = ctypes.byref(record) if record is not None else None
     _check(lib().lpx_contract(ctypes.byref(desc), recp, _stream_handle(stream)))
     return out
+
+
+def contract_noalloc(D, u, out, layout="em", record=None, stream=None):
+    """The same contraction through lpx_contract_noalloc, which allocates
+    nothing (D's arrangement, when the record needs one, goes to the
+    library's static device scratch).  `out` must be given."""
+    K, Np, E = contract_shapes(D, u, layout)
+    desc = make_desc(D, u, out, layout)
+    recp = ctypes.byref(record) if record is not None else None
+    _check(lib().lpx_contract_noalloc(ctypes.byref(desc), recp, _stream_handle(stream)))
+    return out
+
+
+def contract_noalloc_status(desc, rec=None, stream=None) -> int:
+    """Raw status of lpx_contract_noalloc (for tests of its refusals)."""
+    recp = ctypes.byref(rec) if rec is not None else None
+    return lib().lpx_contract_noalloc(ctypes.byref(desc), recp, _stream_handle(stream))
 
 
 def contract_validate(desc, rec=None) -> int:

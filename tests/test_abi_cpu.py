@@ -245,3 +245,25 @@ def test_gemm_validate():
     assert lpx.gemm_validate(d) == lpx.OK
     assert lpx.lib().lpx_gemm(ctypes.byref(d), None, None) == lpx.OK   # no-op, no HIP call
     assert lpx.lib().lpx_gemm(None, None, None) == lpx.ERR_INVALID_ARG
+
+
+def test_noalloc_refuses_oversize_arrangement_before_any_hip_call():
+    # lpx_contract_noalloc keeps D's arrangement in a 1 MiB static scratch:
+    # fp32 at Np = 128 takes ceil(K*128/16) * 32 * 64 * 4 bytes, 1 MiB at
+    # K = 16; K = 17 is refused with no HIP call (none would work here)
+    assert lpx.NOALLOC_SCRATCH_BYTES == 1 << 20
+    far = dict(u=A + (1 << 44), out=A + (1 << 45))
+    d = desc(K=17, Np=128, E=64, **far)
+    assert status(d) == lpx.OK  # lpx_contract itself would take it
+    assert lpx.contract_noalloc_status(d, None, stream=0) == lpx.ERR_UNSUPPORTED
+    assert "scratch" in lpx.last_error()
+    # bf16x3: 32-byte fragments, ceil(Np/32) steps: 8 * 4 * 64 * 32 bytes per
+    # operator at Np = 128, 1 MiB at K = 16
+    r = lpx.record("bf16x3", 32, 2, 1)
+    assert lpx.contract_noalloc_status(desc(K=17, Np=128, E=64, **far), r, stream=0) == \
+        lpx.ERR_UNSUPPORTED
+    # invalid arguments are refused as lpx_contract refuses them
+    assert lpx.contract_noalloc_status(desc(K=-1), None, stream=0) == lpx.ERR_INVALID_ARG
+    # zero sizes are no-ops with no HIP call
+    assert lpx.contract_noalloc_status(desc(E=0, D=None, u=None, out=None), None,
+                                       stream=0) == lpx.OK
