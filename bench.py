@@ -13,6 +13,14 @@ The records are chosen three ways and each is timed:
 `value` is the throughput of the learned pick if available, otherwise of the
 autotuned records.  Inputs are resident in HBM before the timed region.
 
+Besides the main line: the autotuner's sweep of every record per problem,
+the small parity workload (K = 3, Np = 20, E = 4096, untuned) timed on the
+GPU, dense GEMM in three precisions, the 512-instance ragged batch (one
+persistent graph replay, 512 separate launches, and 512 launches captured in
+one graph), and the CPU leg: the FP64 oracle timed on the host cores over
+bounded samples (all cores and one thread), which also reports the
+normwise error of the GPU results against the oracle on sampled outputs.
+
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
@@ -36,6 +44,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "contract_traffic_K3_Np56_E1M.txt")
 FLOP = 2 * K * E * NP * NP                      # one contraction
 BYTES = 4 * (E * NP + K * E * NP + K * NP * NP)  # read u, D once; write out once
+SMALL = (3, 20, 4096)                           # the small parity workload, element-major
+SAMPLE_STARTS = (0, E // 2 + 13, E - 256)       # element chunks checked against the oracle
+SAMPLE_LEN = 256
 
 
 def parse():
@@ -45,7 +56,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="wall-clock budget of the oracle's bounded sample")
+                    help="wall-clock budget of the oracle's bounded sample (all cores)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the GEMM and ragged-batch side measurements")
     ap.add_argument("--model", default=None, help="picker model file (default: the packaged one)")
@@ -104,17 +115,53 @@ def hbm_copy(stream):
     return {"bytes_each_way": 4 * COPY_FLOATS, "us": t * 1e6, "GBps": 8 * COPY_FLOATS / t / 1e9}
 
 
+def sweep_table(key, times):
+    """The autotuner's timing of every record of one problem (enumeration
+    order): [tile_e, prefetch, unroll, median us, GB/s, % of roofline]."""
+    recs = lpx.enumerate_records(K, NP, E, key[0], key[1])
+    rows = []
+    for r, t in zip(recs, times):
+        if not math.isfinite(t):
+            continue
+        s = t * 1e-6
+        rows.append([r.tile_e, r.prefetch, r.unroll, round(t, 2), round(BYTES / s / 1e9, 1),
+                     round(100.0 * FLOP / s / 1e12 / roof_tflops(key[1]), 2)])
+    return rows
+
+
+def small_case(stream):
+    """The small parity workload (K = 3, Np = 20, E = 4096, element-major,
+    untuned record) on the GPU: median event time of 50 launches (the
+    launch includes the record's D-arrangement pre-pass).  Returns the
+    timing and the host inputs and output for the CPU leg's check."""
+    Kc, Npc, Ec = SMALL
+    D, u = inputs.contraction_inputs(Kc, Npc, Ec, seed=0)
+    Dd, ud = torch.from_numpy(D).cuda(), torch.from_numpy(u).cuda()
+    out = torch.empty((Kc, Ec, Npc), device="cuda")
+    t = _event_time(lambda: lpx.contract(Dd, ud, out=out, layout="em", record=None,
+                                         stream=stream), 50, stream)
+    flop = 2 * Kc * Ec * Npc * Npc
+    res = {"workload": f"K={Kc} Np={Npc} E={Ec} em fp32, untuned record", "us": t * 1e6,
+           "tflops": flop / t / 1e12}
+    return res, (D, u, out.cpu().numpy())
+
+
 def extras(stream, learned_picker=None):
     """Side measurements of the other hot-path rows: dense GEMM (the
     degenerate case) in three precisions, and the 512-instance ragged batch
-    as one graph replay vs 512 separate launches."""
+    as one graph replay vs 512 separate launches vs 512 launches captured in
+    one graph.  Returns (results, host samples for the CPU leg's check)."""
     res = {"gemm": [], "batch": None}
+    samples = {"gemm": []}
     for (M, N, Kd) in ((4096, 4096, 4096), (8192, 1024, 4096)):
         g = torch.Generator(device="cuda")
         g.manual_seed(0)
         A = torch.randn((M, Kd), device="cuda", generator=g)
         B = torch.randn((Kd, N), device="cuda", generator=g)
         C = torch.empty((M, N), device="cuda")
+        rows = [0, M // 2 + 17, M - 1]
+        entry = {"shape": (M, N, Kd), "A": A[rows].cpu().numpy(), "B": B.cpu().numpy(),
+                 "rows": rows, "C": {}}
         for prec, tiles in (("fp32", (128, 128, 64)), ("bf16", (128, 128, 64)),
                             ("bf16x3", (128, 128, 64))):
             rec = lpx.record(prec, gemm=tiles)
@@ -123,6 +170,8 @@ def extras(stream, learned_picker=None):
             res["gemm"].append({"shape": [M, N, Kd], "precision": prec, "tiles": list(tiles),
                                 "us": t * 1e6, "tflops": tf,
                                 "pct_peak": 100 * tf / PEAK_TFLOPS[prec]})
+            entry["C"][prec] = C[rows].cpu().numpy()
+        samples["gemm"].append(entry)
         del A, B, C
     shapes = inputs.ragged_shapes(n=512, seed=0)
     g = torch.Generator(device="cuda")
@@ -140,45 +189,129 @@ def extras(stream, learned_picker=None):
         recs = [lpx.record("fp32", 64, 1, 2)] * len(shapes)
         how = "fixed fp32 tile_e=64 prefetch=1 unroll=2"
     flop = sum(2 * K * Ei * Np * Np for Np, Ei in shapes)
+    nbytes = sum(4 * (Ei * Np + K * Ei * Np + K * Np * Np) for Np, Ei in shapes)
     roof = sum(max(2 * K * Ei * Np * Np / (PEAK_TFLOPS["fp32"] * 1e12),
                    4 * (Ei * Np + K * Ei * Np + K * Np * Np) / (PEAK_HBM_GBS * 1e9))
                for Np, Ei in shapes)
     bt = lpx.Batch(items, recs, stream=stream)
     t_graph = _event_time(lambda: bt.submit(stream=stream), 5, stream)
+    torch.cuda.synchronize()
+    batch_out = [o.clone() for (_, _, o, _) in items[:8]]
     bt.destroy()
     t_sep = _event_time(lambda: [lpx.contract(D, u, out=o, record=r, stream=stream)
                                  for (D, u, o, l), r in zip(items, recs)], 3, stream)
+    # 512 launches captured in one graph (lpx_contract_noalloc allocates
+    # nothing, so it can be captured): the fair comparison for the persistent
+    # kernel, since both pay one graph launch
+    t_cap, same = None, None
+    try:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for (D, u, o, l), r in zip(items, recs):  # warm the per-kernel caches
+                lpx.contract_noalloc(D, u, o, layout=l, record=r, stream=side)
+        side.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            for (D, u, o, l), r in zip(items, recs):
+                lpx.contract_noalloc(D, u, o, layout=l, record=r, stream=side)
+        torch.cuda.synchronize()
+        t_cap = _event_time(graph.replay, 5, stream)
+        torch.cuda.synchronize()
+        same = all(torch.equal(o, b) for (_, _, o, _), b in zip(items[:8], batch_out))
+        del graph
+    except Exception as exc:  # a side measurement never hides the rest
+        same = repr(exc)
     res["batch"] = {"instances": len(shapes), "records": how, "gflop": flop / 1e9,
+                    "gbytes": nbytes / 1e9,
                     "graph_us": t_graph * 1e6, "separate_us": t_sep * 1e6,
+                    "captured_launches_us": t_cap * 1e6 if t_cap else None,
                     "graph_tflops": flop / t_graph / 1e12,
                     "separate_tflops": flop / t_sep / 1e12,
+                    "captured_launches_tflops": flop / t_cap / 1e12 if t_cap else None,
+                    "captured_equals_batch": same,
                     "roofline_us": roof * 1e6, "graph_pct_roof": 100 * roof / t_graph}
-    return res
+    return res, samples
 
 
-def cpu_baseline(seconds):
-    """The FP64 oracle on the host cores over a bounded sample of the same
-    step: rounds of 2048 more elements of each of the four (layout,
-    precision) problems until the time budget is spent."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_leg(seconds, data, gpu_chunks, small, extra_samples):
+    """The FP64 oracle on the host cores.  Timed: a bounded sample of the
+    step (rounds of 2048 more elements of each of the four problems until
+    the budget is spent) on all cores, a shorter one on one thread, and the
+    small workload (median of 3) on all cores and on one thread.  Untimed:
+    the oracle's results for sampled outputs of the GPU run, compared with
+    them (normwise relative error, the parity metric of the tests)."""
     import oracle
-    data = {}
-    for layout in ("em", "dm"):
-        data[layout] = inputs.contraction_inputs(K, NP, E, seed=0, layout=layout)
-    chunk = 2048
-    done = 0
-    t0 = time.perf_counter()
-    while done < E and time.perf_counter() - t0 < seconds:
-        n = min(chunk, E - done)
-        for layout, prec in PROBLEMS:
-            D, u = data[layout]
-            oracle.contract(D, u, layout, prec, done, n)
-        done += n
-    dt = time.perf_counter() - t0
-    flop = len(PROBLEMS) * 2 * K * done * NP * NP
-    return {"value": flop / dt / 1e12, "unit": "TFLOP/s", "cores": oracle.threads(),
-            "kind": "oracle",
+    nthreads = oracle.threads()
+
+    def sample_rate(budget):
+        chunk, done = 2048, 0
+        t0 = time.perf_counter()
+        while done < E and time.perf_counter() - t0 < budget:
+            n = min(chunk, E - done)
+            for layout, prec in PROBLEMS:
+                D, u = data[layout]
+                oracle.contract(D, u, layout, prec, done, n)
+            done += n
+        dt = time.perf_counter() - t0
+        return len(PROBLEMS) * 2 * K * done * NP * NP / dt / 1e12, done, dt
+
+    value, done, dt = sample_rate(seconds)
+    oracle.set_threads(1)
+    try:
+        v1, done1, dt1 = sample_rate(seconds / 4)
+        D, u, _ = small
+        ts1 = sorted(_timed(lambda: oracle.contract(D, u, "em", "fp32")) for _ in range(3))[1]
+    finally:
+        oracle.set_threads(nthreads)
+    D, u, _ = small
+    tsn = sorted(_timed(lambda: oracle.contract(D, u, "em", "fp32")) for _ in range(3))[1]
+    base = {"value": value, "unit": "TFLOP/s", "cores": nthreads, "kind": "oracle",
             "sample": f"elements [0, {done}) of E={E} for each of em/fp32, dm/fp32, "
-                      f"em/bf16x3, dm/bf16x3 (K={K}, Np={NP}), fp64 accumulation, {dt:.1f} s"}
+                      f"em/bf16x3, dm/bf16x3 (K={K}, Np={NP}), fp64 accumulation, "
+                      f"{dt:.1f} s on {nthreads} threads",
+            "single_thread": {"value": v1, "unit": "TFLOP/s",
+                              "sample": f"elements [0, {done1}), {dt1:.1f} s"},
+            "small_workload_ms": {"threads_1": ts1 * 1e3, f"threads_{nthreads}": tsn * 1e3},
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
+
+    parity = {}
+    for key, chunks in gpu_chunks.items():
+        layout, prec = key.split("/")
+        D, u = data[layout]
+        errs = []
+        for s0, got in chunks:
+            ref = oracle.contract(D, u, layout, "fp32", s0, got.shape[1])
+            errs.append(oracle.rel_err(got, ref))
+        parity[key] = max(errs)
+    D, u, out = small
+    parity["small_workload/fp32"] = oracle.rel_err(out, oracle.contract(D, u, "em", "fp32"))
+    for entry in (extra_samples or {}).get("gemm", []):
+        for prec, C in entry["C"].items():
+            ref = oracle.gemm(entry["A"], entry["B"], "fp32")
+            M, N, Kd = entry["shape"]
+            parity[f"gemm {M}x{N}x{Kd}/{prec}"] = oracle.rel_err(C, ref)
+    return base, {"metric": "max|gpu - oracle| / max|oracle| on sampled outputs",
+                  "sampled": f"elements {list(SAMPLE_STARTS)} + {SAMPLE_LEN} of each problem; "
+                             "the whole small workload; GEMM rows 0, M/2+17, M-1",
+                  "rel_err": parity,
+                  "tolerance": {"fp32": 1e-5, "bf16x3": 1e-5, "bf16": 2e-2}}
+
+
+def _timed(fn):
+    t0 = time.perf_counter()
+    fn()
+    return time.perf_counter() - t0
 
 
 def main():
@@ -190,10 +323,11 @@ def main():
         sys.exit(2)
     torch.cuda.init()
     stream = torch.cuda.current_stream()
-    work = {}
+    work, host = {}, {}
     for layout, prec in PROBLEMS:
-        if layout not in {k[0] for k in work}:
-            D, u = inputs.contraction_inputs(K, NP, E, seed=0, layout=layout)
+        if layout not in host:
+            host[layout] = inputs.contraction_inputs(K, NP, E, seed=0, layout=layout)
+            D, u = host[layout]
             Dd, ud = torch.from_numpy(D).cuda(), torch.from_numpy(u).cuda()
         else:
             Dd, ud = next((w[0], w[1]) for k, w in work.items() if k[0] == layout)
@@ -202,10 +336,11 @@ def main():
     torch.cuda.synchronize()
 
     untuned = {key: lpx.default_record(key[1]) for key in work}
-    tuned, tune_times = {}, {}
+    tuned, sweeps = {}, {}
     for key, (D, u, out) in work.items():
-        tuned[key], tune_times[key] = lpx.autotune(D, u, out, key[0], key[1], warmup=2, reps=5,
-                                                   stream=stream)
+        tuned[key], times = lpx.autotune(D, u, out, key[0], key[1], warmup=2, reps=5,
+                                         stream=stream)
+        sweeps[f"{key[0]}/{key[1]}"] = sweep_table(key, times)
     learned, pick_info = None, None
     from paper_1405_7470_amd import picker as picker_mod
     model = args.model or picker_mod.MODEL_PATH
@@ -234,6 +369,15 @@ def main():
                 "gbs": BYTES / (per[k] * 1e-6) / 1e9,
                 "pct_roof": 100.0 * FLOP / (per[k] * 1e-6) / 1e12 / roof_tflops(k[1])}
                 for k in work}}
+    # the outputs now hold the primary records' results (timed last)
+    gpu_chunks = {}
+    for (layout, prec), (_, _, out) in work.items():
+        chunks = []
+        for s0 in SAMPLE_STARTS:
+            c = out[:, s0:s0 + SAMPLE_LEN, :] if layout == "em" else \
+                out[:, :, s0:s0 + SAMPLE_LEN].transpose(1, 2)
+            chunks.append((s0, c.double().cpu().numpy()))
+        gpu_chunks[f"{layout}/{prec}"] = chunks
     primary = results["learned"] or results["autotuned"]
     # dominant kernel of the primary records: the problem with the most time
     dom_key = max(primary["per_problem"], key=lambda k: primary["per_problem"][k]["us"])
@@ -267,24 +411,32 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "fp32+bf16x3",
         "data": "synthetic",
         "config": {"workload": "batched dense contraction out[k,e,i]=sum_j D[k,i,j] u[e,j], "
                                "K=3, Np=56, E=2^20, layouts em+dm, precisions fp32+bf16x3",
                    "selection": "learned" if results["learned"] else "autotuned"},
         "roofline": roofline,
         "variants": results,
+        "sweep": {"columns": ["tile_e", "prefetch", "unroll", "us", "GBps", "pct_roof"],
+                  "note": "autotuner medians (5 reps) of every supported record",
+                  "problems": sweeps},
     }
     if pick_info:
         line["picker"] = pick_info
     line["hbm_copy"] = hbm_copy(stream)
+    small_res, small_host = small_case(stream)
+    line["small_workload"] = small_res
+    ex_samples = None
     if not args.no_extras:
         try:
-            line["extras"] = extras(stream, learned_picker=(pk if learned is not None else None))
+            line["extras"], ex_samples = extras(
+                stream, learned_picker=(pk if learned is not None else None))
         except Exception as exc:  # side measurements never hide the main line
             line["extras"] = {"error": repr(exc)}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        line["cpu_baseline"], line["parity"] = cpu_leg(args.cpu_seconds, host, gpu_chunks,
+                                                       small_host, ex_samples)
     print(json.dumps(line), flush=True)
 
 

@@ -218,11 +218,23 @@ def main():
     ap.add_argument("--model", default=MODEL_PATH)
     ap.add_argument("--seeds", type=int, default=3,
                     help="initialisations trained; the lowest validation regret is kept")
+    ap.add_argument("--eval-only", action="store_true",
+                    help="evaluate the existing model on the held-out shapes only")
+    ap.add_argument("--summary", default=None,
+                    help="also write a text summary of the evaluation to this file")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
+    eval_shapes = inputs.picker_shapes(args.eval_shapes, seed=2)
+    if args.eval_only:
+        summary, res = evaluate(eval_shapes, args.model)
+        json.dump({"summary": summary, "per_shape": res},
+                  open(os.path.join(args.out, "eval.json"), "w"), indent=1)
+        if args.summary:
+            write_summary(args.summary, summary, res, args)
+        print(json.dumps(summary), flush=True)
+        return
     os.makedirs(os.path.dirname(args.model), exist_ok=True)
     train_shapes = inputs.picker_shapes(args.train_shapes, seed=1)
-    eval_shapes = inputs.picker_shapes(args.eval_shapes, seed=2)
     db = os.path.join(args.out, "timings.jsonl")
     if os.path.exists(db):
         os.remove(db)
@@ -242,7 +254,57 @@ def main():
     summary, res = evaluate(eval_shapes, args.model)
     json.dump({"summary": summary, "per_shape": res},
               open(os.path.join(args.out, "eval.json"), "w"), indent=1)
+    if args.summary:
+        write_summary(args.summary, summary, res, args)
     print(json.dumps(summary), flush=True)
+
+
+def write_summary(path, summary, res, args):
+    """A short text record of a held-out evaluation: the summary figures,
+    the regret distribution and the worst shapes."""
+    r = sorted((x["t_learned"] / x["t_best"], x) for x in res)
+    q = np.quantile([v for v, _ in r], [0.5, 0.9, 0.99, 1.0])
+    by = {}
+    for v, x in r:
+        k = (x["shape"]["layout"], x["shape"]["precision"])
+        by.setdefault(k, []).append(v)
+    lines = [
+        "# Learned picker: regret on held-out shapes",
+        "",
+        f"Command: `python -m paper_1405_7470_amd.picker --eval-only --eval-shapes "
+        f"{args.eval_shapes} --summary {path}` (model `{os.path.relpath(args.model)}`).",
+        "",
+        f"Held-out shapes: {summary['shapes']} (seed 2: Np uniform in [8, 128], "
+        "E = floor(2^U(10, 21)), layout and precision uniform, K = 3), each tuned "
+        "exhaustively over every supported record with a cache flush before each timed launch; "
+        "learned pick, untuned default and best read off the same timing pass.",
+        "",
+        "| figure | value |",
+        "|---|---|",
+        f"| geomean t_learned / t_best | {summary['geomean_learned_over_best']:.4f} |",
+        f"| fraction of shapes within 10% of best | {summary['fraction_within_10pct']:.3f} |",
+        f"| sum t_learned / sum t_best | {summary['sum_ratio']:.4f} |",
+        f"| geomean t_untuned / t_learned (gain over no model) | "
+        f"{summary['geomean_untuned_over_learned']:.3f} |",
+        f"| median pick latency (us) | {summary['median_pick_us']:.1f} |",
+        f"| median exhaustive tuning time (s) | {summary['median_exhaustive_tune_s']:.3f} |",
+        f"| regret quantiles 50/90/99/100% | {q[0]:.3f} / {q[1]:.3f} / {q[2]:.3f} / {q[3]:.3f} |",
+        "",
+        "| layout/precision | shapes | geomean regret | within 10% |",
+        "|---|---|---|---|",
+    ]
+    for k in sorted(by):
+        v = np.array(by[k])
+        lines.append(f"| {k[0]}/{k[1]} | {len(v)} | {float(np.exp(np.mean(np.log(v)))):.4f} | "
+                     f"{float(np.mean(v <= 1.10)):.3f} |")
+    lines += ["", "Worst five shapes:", "", "| K | Np | E | layout | precision | regret | learned "
+              "| best |", "|---|---|---|---|---|---|---|---|"]
+    for v, x in r[-5:][::-1]:
+        sh = x["shape"]
+        lines.append(f"| {sh['K']} | {sh['Np']} | {sh['E']} | {sh['layout']} | "
+                     f"{sh['precision']} | {v:.3f} | {x['learned']} | {x['best']} |")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
 
 
 if __name__ == "__main__":
