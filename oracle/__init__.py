@@ -9,6 +9,9 @@ Functions follow the plain definitions:
     reduction syntax; Table 1 "dG FEM volume"), FP64 accumulation;
   * ``gemm``      C = A B                                   (sec. 2.1 example
     reduction sum(k, a[i,k]*b[k,j]); Table 1 "sgemm");
+  * ``dg_volume`` out[d,e,i] = sum_k G(e,d,k) sum_j D[k][i][j] u[e][j]
+    (Table 1 "dG FEM volume": reference derivatives combined with
+    per-element geometric factors);
   * ``bf16_rne`` / ``split_bf16``  reduced-precision operand emulation;
   * ``mlp``       the cost model's forward, backward and Adam step (numpy).
 """
@@ -39,6 +42,9 @@ class Oracle:
         L.oracle_gemm.argtypes = [ctypes.c_long, ctypes.c_long, ctypes.c_long,
                                   ctypes.c_int, f32p, f32p, ctypes.c_long,
                                   ctypes.c_long, f64p]
+        L.oracle_dg_volume.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long,
+                                       ctypes.c_int, ctypes.c_int, f32p, f32p, f32p,
+                                       ctypes.c_long, ctypes.c_long, f64p]
         L.oracle_threads.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         self.L = L
@@ -81,6 +87,25 @@ class Oracle:
         self.L.oracle_contract(K, Np, E, LAYOUT[layout], PREC[precision], pD, pu,
                                e0, ne,
                                ref.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return ref
+
+    def dg_volume(self, D, u, G, layout="em", precision="fp32", e0=0, ne=None):
+        """FP64 dG volume chunk ref[d, e - e0, i] = sum_k G(e,d,k) (D_k u_e)_i.
+
+        G: (E, K, K) float32 for layout "em", (K, K, E) for "dm"."""
+        D, pD = _f32(D)
+        K, Np, Np2 = D.shape
+        assert Np == Np2 and 0 < K <= 8 and Np <= 128
+        u, pu = _f32(u)
+        G, pG = _f32(G)
+        E = u.shape[0] if layout == "em" else u.shape[1]
+        assert G.shape == ((E, K, K) if layout == "em" else (K, K, E))
+        if ne is None:
+            ne = E - e0
+        assert 0 <= e0 and e0 + ne <= E
+        ref = np.zeros((K, ne, Np), dtype=np.float64)
+        self.L.oracle_dg_volume(K, Np, E, LAYOUT[layout], PREC[precision], pD, pu, pG, e0, ne,
+                                ref.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         return ref
 
     def gemm(self, A, B, precision="fp32", m0=0, nm=None):
@@ -138,6 +163,10 @@ def contract(D, u, layout="em", precision="fp32", e0=0, ne=None):
 
 def gemm(A, B, precision="fp32", m0=0, nm=None):
     return default().gemm(A, B, precision, m0, nm)
+
+
+def dg_volume(D, u, G, layout="em", precision="fp32", e0=0, ne=None):
+    return default().dg_volume(D, u, G, layout, precision, e0, ne)
 
 
 def rel_err(y, ref) -> float:

@@ -138,6 +138,53 @@ void oracle_contract(int K, int Np, long E, int layout, int precision,
     }
 }
 
+/* Volume term of a nodal discontinuous Galerkin operator (the "dG FEM
+ * volume" workload of Table 1; the paper names it and prints nothing else
+ * about it).  Reading: the K reference derivatives D_k u of an element are
+ * combined with that element's geometric factors (the derivatives of the
+ * reference coordinates with respect to the physical ones),
+ *
+ *   ref[d][e - e0][i] = sum_{k<K} G(e, d, k) * sum_{j<Np} D[k][i][j] * u(e, j),
+ *
+ * d < K, with G(e, d, k) = G[(e*K + d)*K + k] for element-major storage
+ * and G[(d*K + k)*E + e] for DOF-major storage (one contiguous run of E
+ * factors per (d, k), like u's rows).  The inner sums are oracle_contract's,
+ * under the same precision mode; the factors are applied in FP64 to the
+ * FP64 sums.  K <= 8. */
+void oracle_dg_volume(int K, int Np, long E, int layout, int precision,
+                      const float* D, const float* u, const float* G, long e0,
+                      long ne, double* ref) {
+    if (K <= 0 || K > 8 || Np <= 0 || ne <= 0) return;
+#pragma omp parallel for schedule(static)
+    for (long de = 0; de < ne; ++de) {
+        long e = e0 + de;
+        double t[8 * 128];  /* reference derivatives of element e, [k][i] */
+        for (int k = 0; k < K; ++k) {
+            const float* Dk = D + (long)k * Np * Np;
+            for (int i = 0; i < Np; ++i) {
+                double acc = 0.0;
+                for (int j = 0; j < Np; ++j) {
+                    float uej = (layout == LAYOUT_EM) ? u[e * Np + j]
+                                                      : u[(long)j * E + e];
+                    acc += prod(Dk[(long)i * Np + j], uej, precision);
+                }
+                t[k * Np + i] = acc;
+            }
+        }
+        for (int d = 0; d < K; ++d) {
+            for (int i = 0; i < Np; ++i) {
+                double acc = 0.0;
+                for (int k = 0; k < K; ++k) {
+                    float g = (layout == LAYOUT_EM) ? G[(e * K + d) * K + k]
+                                                    : G[((long)d * K + k) * E + e];
+                    acc += (double)g * t[k * Np + i];
+                }
+                ref[((long)d * ne + de) * Np + i] = acc;
+            }
+        }
+    }
+}
+
 /* C[m - m0][n] = sum_{k=0}^{Kd-1} A[m][k] * B[k][n], A (M x Kd) and
  * B (Kd x N) row-major, FP64, for m in [m0, m0 + nm). */
 void oracle_gemm(long M, long N, long Kd, int precision, const float* A,

@@ -31,6 +31,25 @@ def contraction_inputs(K, Np, E, seed=0, layout="em"):
     return D, u
 
 
+def dg_volume_inputs(K, Np, E, seed=0, layout="em"):
+    """(D, u, G) for the dG volume workload: D and u exactly as
+    contraction_inputs draws them for the same seed, then per-element
+    geometric factors G[e] = s_e (I + 0.25 N(0, 1)^{K x K}) with the element
+    scale s_e ~ U(0.5, 2) (an affine element's inverse Jacobian: near a
+    scaled identity, well conditioned, sizes varying across the mesh).
+    G has shape (E, K, K) for element-major, the same values stored
+    (K, K, E) for DOF-major."""
+    rng = np.random.default_rng(seed)
+    D = rng.normal(0.0, 1.0 / math.sqrt(Np), size=(K, Np, Np)).astype(np.float32)
+    u = _uniform(rng, (E, Np))
+    s = rng.uniform(0.5, 2.0, size=(E, 1, 1))
+    G = (s * (np.eye(K)[None] + 0.25 * rng.standard_normal((E, K, K)))).astype(np.float32)
+    if layout == "dm":
+        u = np.ascontiguousarray(u.T)
+        G = np.ascontiguousarray(G.transpose(1, 2, 0))
+    return D, u, G
+
+
 def integer_contraction_inputs(K, Np, E, seed=0, layout="em", bound=8):
     """Small-integer operands in [-bound, bound]: every product and partial
     sum is exact in FP32 (and in bf16 for |x| <= 256)."""

@@ -240,6 +240,100 @@ def pin_gemm(o):
     assert 1e-8 < e3 < 1e-5, e3
 
 
+def _g_as_em(G, layout):
+    return G if layout == "em" else np.ascontiguousarray(G.transpose(2, 0, 1))
+
+
+def _g_store(G_em, layout):
+    return G_em if layout == "em" else np.ascontiguousarray(G_em.transpose(1, 2, 0))
+
+
+def pin_dg_bruteforce(o):
+    """dG volume on tiny shapes against exact rational sums: the exact
+    contraction (per precision) combined with the exact geometric factors."""
+    rng = np.random.default_rng(21)
+    for (K, Np, E) in [(1, 1, 1), (2, 3, 4), (3, 4, 5), (3, 2, 3)]:
+        D = rng.normal(0, 1, (K, Np, Np)).astype(np.float32)
+        u = rng.uniform(-1, 1, (E, Np)).astype(np.float32)
+        G = rng.normal(0, 1, (E, K, K)).astype(np.float32)
+        for precision in ("fp32", "bf16x3"):
+            c = _exact_contract(D, u, "em", precision)
+            exact = np.empty((K, E, Np), dtype=object)
+            for d in range(K):
+                for e in range(E):
+                    for i in range(Np):
+                        exact[d, e, i] = sum(Fraction(float(G[e, d, k])) * c[k, e, i]
+                                             for k in range(K))
+            for layout in ("em", "dm"):
+                uu = u if layout == "em" else np.ascontiguousarray(u.T)
+                ref = o.dg_volume(D, uu, _g_store(G, layout), layout, precision)
+                _assert_close_exact(ref, exact, Np * K)
+
+
+def pin_dg_identity_and_diagonal(o):
+    """G = I gives the contraction itself, bit for bit; a diagonal G of
+    signed powers of two scales each reference derivative exactly."""
+    K, Np, E = 3, 20, 37
+    D, u, _ = inputs.dg_volume_inputs(K, Np, E, seed=3)
+    rng = np.random.default_rng(4)
+    for layout in ("em", "dm"):
+        uu = u if layout == "em" else np.ascontiguousarray(u.T)
+        c = o.contract(D, uu, layout, "fp32")
+        I = np.broadcast_to(np.eye(K, dtype=np.float32), (E, K, K)).copy()
+        assert np.array_equal(o.dg_volume(D, uu, _g_store(I, layout), layout), c)
+        sc = (rng.choice([-1.0, 1.0], (E, K)) * 2.0 ** rng.integers(-3, 4, (E, K)))
+        Gd = np.zeros((E, K, K), np.float32)
+        for d in range(K):
+            Gd[:, d, d] = sc[:, d]
+        ref = o.dg_volume(D, uu, _g_store(Gd, layout), layout)
+        assert np.array_equal(ref, c * sc.T[:, :, None])
+
+
+def pin_dg_permutation_and_linearity(o):
+    """A permutation metric picks reference derivatives (exactly); the result
+    is linear in G (to FP64 rounding)."""
+    K, Np, E = 3, 12, 29
+    D, u, G1 = inputs.dg_volume_inputs(K, Np, E, seed=5)
+    _, _, G2 = inputs.dg_volume_inputs(K, Np, E, seed=6)
+    c = o.contract(D, u, "em", "fp32")
+    perm = [2, 0, 1]
+    P = np.zeros((E, K, K), np.float32)
+    for d in range(K):
+        P[:, d, perm[d]] = 1.0
+    assert np.array_equal(o.dg_volume(D, u, P), c[perm])
+    # element-varying permutations
+    Pe = np.zeros((E, K, K), np.float32)
+    for e in range(E):
+        pe = np.roll(np.arange(K), e)
+        for d in range(K):
+            Pe[e, d, pe[d]] = 1.0
+    ref = o.dg_volume(D, u, Pe)
+    for e in range(E):
+        pe = np.roll(np.arange(K), e)
+        assert np.array_equal(ref[:, e], c[pe, e])
+    a = o.dg_volume(D, u, G1) + o.dg_volume(D, u, G2)
+    b = o.dg_volume(D, u, (G1 + G2).astype(np.float32))
+    # G1 + G2 rounded to float32: compare against the exactly summed factors
+    assert np.max(np.abs(a - b)) <= 1e-6 * np.max(np.abs(a))
+
+
+def pin_dg_layouts_chunks_integers(o):
+    """Element-major and DOF-major storage give the same values; chunks equal
+    the whole; small-integer inputs are exact in every precision."""
+    K, Np, E = 3, 16, 53
+    D, u, G = inputs.dg_volume_inputs(K, Np, E, seed=7)
+    em = o.dg_volume(D, u, G, "em")
+    dm = o.dg_volume(D, np.ascontiguousarray(u.T), _g_store(G, "dm"), "dm")
+    assert np.array_equal(em, dm)
+    assert np.array_equal(o.dg_volume(D, u, G, "em", "fp32", 10, 20), em[:, 10:30])
+    Di, ui = inputs.integer_contraction_inputs(K, Np, E, seed=8, bound=4)
+    Gi = np.random.default_rng(9).integers(-3, 4, (E, K, K)).astype(np.float32)
+    exact = np.einsum("edk,kij,ej->dei", Gi.astype(np.int64), Di.astype(np.int64),
+                      ui.astype(np.int64)).astype(np.float64)
+    for precision in ("fp32", "bf16", "bf16x3"):
+        assert np.array_equal(o.dg_volume(Di, ui, Gi, "em", precision), exact)
+
+
 ALL_PINS = [
     pin_contract_bruteforce,
     pin_contract_identity,
@@ -252,4 +346,6 @@ ALL_PINS = [
     pin_split_bf16,
     pin_precision_error_bands,
     pin_gemm,
+    pin_dg_bruteforce, pin_dg_identity_and_diagonal, pin_dg_permutation_and_linearity,
+    pin_dg_layouts_chunks_integers,
 ]

@@ -23,6 +23,12 @@ MUTANTS = [
     ("bf16_keeps_fp32", "return (double)oracle_bf16_rne(a) * (double)oracle_bf16_rne(b);",
      "return (double)a * (double)b;"),
     ("chunk_offset_ignored", "long e = e0 + de;", "long e = de;"),
+    ("dg_G_transposed", "G[(e * K + d) * K + k]", "G[(e * K + k) * K + d]"),
+    ("dg_dm_G_index_as_em", "G[((long)d * K + k) * E + e]", "G[(e * K + d) * K + k]"),
+    ("dg_wrong_derivative", "acc += (double)g * t[k * Np + i];", "acc += (double)g * t[d * Np + i];"),
+    ("dg_drops_last_k", "for (int k = 0; k < K; ++k) {\n                    float g",
+     "for (int k = 0; k < K - 1; ++k) {\n                    float g"),
+    ("dg_G_in_float", "acc += (double)g * t[k * Np + i];", "acc += (double)(g * (float)t[k * Np + i]);"),
 ]
 
 
