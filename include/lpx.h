@@ -164,6 +164,33 @@ typedef struct lpx_contract_desc {
                       /* not overlap D or u                             */
 } lpx_contract_desc;
 
+/* ------------------------------------------------- dG volume term */
+/* Volume term of a nodal discontinuous Galerkin operator (Table 1's "dG
+ * FEM volume" workload; the paper names the workload only).  Reading used
+ * here: the K reference derivatives of each element are combined with that
+ * element's geometric factors (derivatives of the reference coordinates
+ * with respect to the physical ones),
+ *
+ *     out[d,e,i] = sum_{k<K} G(e,d,k) * sum_j D[k][i][j] * u[e][j],  d < K.
+ *
+ * Layouts as for the contraction (out like its output, K physical
+ * derivatives in place of K reference ones), and G follows the layout:
+ *   ELEMENT_MAJOR: G(e,d,k) = G[(e*K + d)*K + k]   (a K x K matrix per element)
+ *   DOF_MAJOR    : G(e,d,k) = G[(d*K + k)*E + e]   (K*K runs of E factors)  */
+#define LPX_DG_MAX_K 3
+typedef struct lpx_dg_volume_desc {
+    int32_t K;        /* reference = physical dimensions, 0..3            */
+    int32_t Np;       /* nodes per element, 0..128                        */
+    int64_t E;        /* number of elements, >= 0                         */
+    int32_t layout;   /* LPX_ELEMENT_MAJOR / LPX_DOF_MAJOR                */
+    int32_t reserved; /* must be 0                                        */
+    const float* D;   /* device, K*Np*Np floats, 16-byte aligned          */
+    const float* u;   /* device, E*Np floats, 16-byte aligned             */
+    const float* G;   /* device, E*K*K floats, 16-byte aligned            */
+    float* out;       /* device, K*E*Np floats, 16-byte aligned; must not */
+                      /* overlap D, u or G                                */
+} lpx_dg_volume_desc;
+
 /* -------------------------------------------------------------- GEMM */
 /* C = A B, row-major FP32 (the degenerate case of the contraction). */
 typedef struct lpx_gemm_desc {
@@ -259,6 +286,28 @@ lpx_status lpx_contract_noalloc(const lpx_contract_desc* c, const lpx_record* re
  * reading through the pointers.  Device-dependent failures (LPX_ERR_HIP)
  * can still occur in lpx_contract after this returns LPX_OK. */
 lpx_status lpx_contract_validate(const lpx_contract_desc* c, const lpx_record* rec);
+
+/* The dG volume term (see lpx_dg_volume_desc), enqueued on `stream`, with
+ * the metric applied in the write-back: the contraction's compute waves
+ * stage the K reference derivatives of an element tile in LDS exactly as
+ * lpx_contract's staged-output records do (same kernels, same summation
+ * order), together with the tile's geometric factors, and the store waves
+ * form out[d] = sum_k G(e,d,k) * (D_k u)[i] (FP32, k in increasing order)
+ * while they copy the tile to `out`.  So the record must stage the output
+ * tile: prefetch 10, 11 or 14 (bit 3), any tile_e, unroll and precision;
+ * other records fail with LPX_ERR_UNSUPPORTED, as do K > 3 and shapes
+ * whose LDS rings do not fit.  rec = NULL picks the first of (tile_e,
+ * prefetch) = (64, 14), (64, 10), (32, 10), (16, 10) that fits, in FP32.
+ * Records that read D from memory (prefetch 10) launch the D-arrangement
+ * pre-pass with its workspace, as lpx_contract does.  Errors as for
+ * lpx_contract; G must not overlap out. */
+lpx_status lpx_dg_volume(const lpx_dg_volume_desc* c, const lpx_record* rec, void* stream);
+
+/* Every pre-launch check of lpx_dg_volume, without any HIP call; with
+ * rec = NULL, *chosen (host, may be NULL) receives the record NULL stands
+ * for. */
+lpx_status lpx_dg_volume_validate(const lpx_dg_volume_desc* c, const lpx_record* rec,
+                                  lpx_record* chosen);
 
 /* Dense GEMM  C[m][n] = sum_k A[m][k] B[k][n]  (the paper's sec. 2.1
  * reduction example sum(k, a[i,k]*b[k,j]); Table 1 "sgemm"), enqueued on

@@ -72,7 +72,8 @@ lpx_status check_record(const lpx_record* rec) {
 }
 
 lpx_status contract_geometry(int K, int Np, int64_t E, int layout,
-                             const lpx_record& r, ContractGeom* g) {
+                             const lpx_record& r, ContractGeom* g, bool dg) {
+    g->dg = dg ? 1 : 0;
     g->prec = r.precision;
     g->layout = layout;
     g->tile_e = r.tile_e;
@@ -114,9 +115,14 @@ lpx_status contract_geometry(int K, int Np, int64_t E, int layout,
     }
     // A staged output tile: element-major K*tile_e*Np floats, DOF-major
     // K*Np rows of tile_e + 4 floats (both multiples of 4 floats).
-    const int64_t ldo = layout == LPX_ELEMENT_MAJOR ? round_up((int64_t)K * r.tile_e * Np, 4)
-                                                    : (int64_t)K * Np * (r.tile_e + 4);
+    // The dG volume kernels append the tile's geometric factors (tile_e*K*K
+    // floats) to each output slot.
+    const int64_t ldo_out = layout == LPX_ELEMENT_MAJOR
+                                ? round_up((int64_t)K * r.tile_e * Np, 4)
+                                : (int64_t)K * Np * (r.tile_e + 4);
+    const int64_t ldo = ldo_out + (dg ? round_up((int64_t)r.tile_e * K * K, 4) : 0);
     g->ldo = (r.prefetch & 8) && ldo <= kMaxLdsPerWorkgroup ? (int)ldo : 0;
+    g->ldo_g = dg && g->ldo ? (int)ldo_out : 0;
     if (r.prefetch & 4) {
         // D in registers: each wave holds the fragments of its row blocks,
         // which needs Np <= 64, four waves per 16-element block and all of
@@ -193,7 +199,7 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 // Every check of lpx_contract that needs no HIP call.  On LPX_OK, g holds
 // the launch geometry; g->ntiles == 0 marks a zero-size no-op.
 lpx_status validate_contract(const lpx_contract_desc* c, const lpx_record* rec,
-                             ContractGeom* g) {
+                             ContractGeom* g, bool dg) {
     g->ntiles = 0;
     if (!c) return set_error(LPX_ERR_INVALID_ARG, "descriptor is NULL");
     lpx_record r = rec ? *rec : default_record(LPX_FP32);
@@ -221,7 +227,55 @@ lpx_status validate_contract(const lpx_contract_desc* c, const lpx_record* rec,
     if (overlaps(c->out, oelems * 4, c->u, uelems * 4) ||
         overlaps(c->out, oelems * 4, c->D, delems * 4))
         return set_error(LPX_ERR_ALIAS, "out overlaps D or u");
-    return contract_geometry(c->K, c->Np, c->E, c->layout, r, g);
+    return contract_geometry(c->K, c->Np, c->E, c->layout, r, g, dg);
+}
+
+lpx_status validate_dg(const lpx_dg_volume_desc* c, const lpx_record* rec, ContractGeom* g,
+                       lpx_record* chosen) {
+    g->ntiles = 0;
+    if (!c) return set_error(LPX_ERR_INVALID_ARG, "descriptor is NULL");
+    if (c->K > LPX_DG_MAX_K)
+        return set_error(LPX_ERR_UNSUPPORTED, "dG volume term with K=%d above %d", c->K,
+                         LPX_DG_MAX_K);
+    lpx_contract_desc cd;
+    cd.K = c->K;
+    cd.Np = c->Np;
+    cd.E = c->E;
+    cd.layout = c->layout;
+    cd.reserved = c->reserved;
+    cd.D = c->D;
+    cd.u = c->u;
+    cd.out = c->out;
+    lpx_record r;
+    lpx_status s;
+    if (rec) {
+        r = *rec;
+        if ((s = check_record(&r)) != LPX_OK) return s;
+        if (!(r.prefetch & 8))
+            return set_error(LPX_ERR_UNSUPPORTED,
+                             "the dG volume term needs a staged output tile (prefetch 10, 11 or "
+                             "14), got prefetch %u", r.prefetch);
+        s = validate_contract(&cd, &r, g, true);
+    } else {
+        // the first of these that fits the shape
+        static const uint8_t kDefaults[4][2] = {{64, 14}, {64, 10}, {32, 10}, {16, 10}};
+        s = LPX_ERR_UNSUPPORTED;
+        for (const auto& d : kDefaults) {
+            r = default_record(LPX_FP32);
+            r.tile_e = d[0];
+            r.prefetch = d[1];
+            s = validate_contract(&cd, &r, g, true);
+            if (s != LPX_ERR_UNSUPPORTED) break;
+        }
+    }
+    if (chosen) *chosen = r;
+    if (s != LPX_OK || g->ntiles == 0) return s;
+    if (!c->G) return set_error(LPX_ERR_INVALID_ARG, "NULL G");
+    if (!aligned16(c->G)) return set_error(LPX_ERR_INVALID_ARG, "G must be 16-byte aligned");
+    const int64_t gbytes = c->E * c->K * c->K * 4, obytes = c->E * c->K * c->Np * 4;
+    if (overlaps(c->out, obytes, c->G, gbytes))
+        return set_error(LPX_ERR_ALIAS, "out overlaps G");
+    return LPX_OK;
 }
 
 
@@ -386,6 +440,42 @@ lpx_status lpx_contract_noalloc(const lpx_contract_desc* c, const lpx_record* re
                              "%d-byte scratch (K=%d Np=%d)",
                              (long long)darr_bytes(g), LPX_NOALLOC_SCRATCH_BYTES, c->K, c->Np);
         return launch_contract(*c, g, stream, true);
+    } catch (...) {
+        return set_error(LPX_ERR_INTERNAL, "unexpected C++ exception");
+    }
+}
+
+lpx_status lpx_dg_volume_validate(const lpx_dg_volume_desc* c, const lpx_record* rec,
+                                  lpx_record* chosen) {
+    clear_error();
+    try {
+        ContractGeom g;
+        lpx_record r;
+        lpx_status s = validate_dg(c, rec, &g, &r);
+        if (chosen) *chosen = r;
+        return s;
+    } catch (...) {
+        return set_error(LPX_ERR_INTERNAL, "unexpected C++ exception");
+    }
+}
+
+lpx_status lpx_dg_volume(const lpx_dg_volume_desc* c, const lpx_record* rec, void* stream) {
+    clear_error();
+    try {
+        ContractGeom g;
+        lpx_record r;
+        lpx_status s = validate_dg(c, rec, &g, &r);
+        if (s != LPX_OK || g.ntiles == 0) return s;
+        lpx_contract_desc cd;
+        cd.K = c->K;
+        cd.Np = c->Np;
+        cd.E = c->E;
+        cd.layout = c->layout;
+        cd.reserved = 0;
+        cd.D = c->D;
+        cd.u = c->u;
+        cd.out = c->out;
+        return launch_contract(cd, g, stream, false, c->G);
     } catch (...) {
         return set_error(LPX_ERR_INTERNAL, "unexpected C++ exception");
     }

@@ -54,6 +54,36 @@ ContractFn by_tile(int tile, int pf, int un) {
     }
 }
 
+// dG volume term (EPI = 1): only the staged-output records, prefetch 10, 11
+// and 14, carry the epilogue.
+template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PF>
+ContractFn dg_by_unroll(int un) {
+    switch (un) {
+        case 1: return &kern::contract_kernel<PREC, LAYOUT, NTMAX, TILE_E, PF, 1, 1>;
+        case 2: return &kern::contract_kernel<PREC, LAYOUT, NTMAX, TILE_E, PF, 2, 1>;
+        default: return &kern::contract_kernel<PREC, LAYOUT, NTMAX, TILE_E, PF, 4, 1>;
+    }
+}
+
+template <int PREC, int LAYOUT, int NTMAX, int TILE_E>
+ContractFn dg_by_prefetch(int pf, int un) {
+    if (pf == 10) return dg_by_unroll<PREC, LAYOUT, NTMAX, TILE_E, 10>(un);
+    if (pf == 11) return dg_by_unroll<PREC, LAYOUT, NTMAX, TILE_E, 11>(un);
+    if constexpr (NTMAX <= 4) {
+        if (pf == 14) return &kern::contract_kernel<PREC, LAYOUT, NTMAX, TILE_E, 14, 1, 1>;
+    }
+    return nullptr;
+}
+
+template <int PREC, int LAYOUT, int NTMAX>
+ContractFn dg_by_tile(int tile, int pf, int un) {
+    switch (tile) {
+        case 16: return dg_by_prefetch<PREC, LAYOUT, NTMAX, 16>(pf, un);
+        case 32: return dg_by_prefetch<PREC, LAYOUT, NTMAX, 32>(pf, un);
+        default: return dg_by_prefetch<PREC, LAYOUT, NTMAX, 64>(pf, un);
+    }
+}
+
 }  // namespace dispatch
 
 // The instances of one (precision, layout, i-block bound NTMAX): each
@@ -65,10 +95,20 @@ ContractFn contract_instances(int tile, int pf, int un) {
     return dispatch::by_tile<PREC, LAYOUT, NTMAX>(tile, pf, un);
 }
 
+// The dG volume instances, compiled the same way by the units
+// contract_dg_<precision>_<layout>.hip.
+template <int PREC, int LAYOUT, int NTMAX>
+ContractFn dg_instances(int tile, int pf, int un) {
+    return dispatch::dg_by_tile<PREC, LAYOUT, NTMAX>(tile, pf, un);
+}
+
 #define LPX_EXTERN_INSTANCES(P, L)                                               \
     extern template ContractFn contract_instances<P, L, 2>(int, int, int);    \
     extern template ContractFn contract_instances<P, L, 4>(int, int, int);    \
-    extern template ContractFn contract_instances<P, L, 8>(int, int, int);
+    extern template ContractFn contract_instances<P, L, 8>(int, int, int);    \
+    extern template ContractFn dg_instances<P, L, 2>(int, int, int);          \
+    extern template ContractFn dg_instances<P, L, 4>(int, int, int);          \
+    extern template ContractFn dg_instances<P, L, 8>(int, int, int);
 LPX_EXTERN_INSTANCES(LPX_FP32, LPX_ELEMENT_MAJOR)
 LPX_EXTERN_INSTANCES(LPX_FP32, LPX_DOF_MAJOR)
 LPX_EXTERN_INSTANCES(LPX_BF16, LPX_ELEMENT_MAJOR)
@@ -77,9 +117,16 @@ LPX_EXTERN_INSTANCES(LPX_BF16X3, LPX_ELEMENT_MAJOR)
 LPX_EXTERN_INSTANCES(LPX_BF16X3, LPX_DOF_MAJOR)
 #undef LPX_EXTERN_INSTANCES
 
-// Record -> instance for a run-time bound.
+// Record -> instance for a run-time bound (dg: the dG volume epilogue).
 template <int PREC, int LAYOUT>
-ContractFn contract_instance(int ntmax, int tile, int pf, int un) {
+ContractFn contract_instance(int ntmax, int tile, int pf, int un, bool dg = false) {
+    if (dg) {
+        switch (ntmax) {
+            case 2: return dg_instances<PREC, LAYOUT, 2>(tile, pf, un);
+            case 4: return dg_instances<PREC, LAYOUT, 4>(tile, pf, un);
+            default: return dg_instances<PREC, LAYOUT, 8>(tile, pf, un);
+        }
+    }
     switch (ntmax) {
         case 2: return contract_instances<PREC, LAYOUT, 2>(tile, pf, un);
         case 4: return contract_instances<PREC, LAYOUT, 4>(tile, pf, un);

@@ -75,6 +75,10 @@ struct ContractArgs {
     int nrb;     // stacked row blocks: ceil(K * Np / 16)
     Divider np_div;  // stacked row R -> operator R / Np
     int ldo;     // staged output slot stride (floats), prefetch bit 3
+    // dG volume term (EPI = 1): geometric factors, and the float offset of
+    // the tile's copy of them inside each staged output slot
+    const float* __restrict__ G;
+    int ldo_g;
     int np_vec;  // Np % 4 == 0: 16-byte row accesses are aligned
     int e_vec;   // E % 4 == 0
 };
@@ -351,6 +355,18 @@ __device__ __forceinline__ void d_frag_store_lds(unsigned char* lds, int64_t nfr
 // MASK: zero the columns j >= Np.  Without it the caller guarantees that
 // every column it uses is below Np (the values read for other columns may
 // belong to the next element or to the slot's slack).
+// DOF-major tiles of 64 elements (one 256-byte row per column j, all of
+// the LDS banks) are stored with the 16-byte chunks of each row permuted:
+// element r of column j sits at r ^ (16 * ((j >> 2) & 3)).  The four lane
+// groups of an MFMA operand read columns four apart (j = 16Q + 4g + t), which
+// unpermuted start at the same bank; permuted, group g reads the quarter of
+// the banks that r ^ 16g selects.  The loader writes each chunk to its
+// permuted place by choosing which global chunk each lane fetches.
+template <int LAYOUT, int TILE_E>
+__device__ __forceinline__ int dm_swz(int j) {
+    return (LAYOUT == LPX_DOF_MAJOR && TILE_E == 64) ? ((j >> 2) & 3) << 4 : 0;
+}
+
 template <int PREC, int LAYOUT, int TILE_E, bool MASK = true>
 __device__ __forceinline__ Frag<PREC> u_frag_lds(const float* ut, int Np, bool np_vec, int row0,
                                                  int s, int nquad_steps, int lane) {
@@ -358,7 +374,9 @@ __device__ __forceinline__ Frag<PREC> u_frag_lds(const float* ut, int Np, bool n
     if constexpr (PREC == LPX_FP32) {
         const int j0 = fp32_col(s, lane >> 4, nquad_steps);
         const int jc = j0 < Np ? j0 : Np - 1;  // callers may read steps past the last
-        const float x = LAYOUT == LPX_ELEMENT_MAJOR ? ut[r * Np + jc] : ut[jc * TILE_E + r];
+        const float x = LAYOUT == LPX_ELEMENT_MAJOR
+                            ? ut[r * Np + jc]
+                            : ut[jc * TILE_E + (r ^ dm_swz<LAYOUT, TILE_E>(jc))];
         if constexpr (MASK) return {j0 < Np ? x : 0.0f};
         return {x};
     } else {
@@ -375,7 +393,9 @@ __device__ __forceinline__ Frag<PREC> u_frag_lds(const float* ut, int Np, bool n
         } else {
 #pragma unroll
             for (int t = 0; t < 8; ++t)
-                v[t] = LAYOUT == LPX_ELEMENT_MAJOR ? ut[r * Np + j0 + t] : ut[(j0 + t) * TILE_E + r];
+                v[t] = LAYOUT == LPX_ELEMENT_MAJOR
+                           ? ut[r * Np + j0 + t]
+                           : ut[(j0 + t) * TILE_E + (r ^ dm_swz<LAYOUT, TILE_E>(j0 + t))];
         }
         if constexpr (MASK) {
 #pragma unroll
@@ -394,10 +414,14 @@ __device__ __forceinline__ f4 u_quad_lds(const float* ut, int Np, bool np_vec, i
     f4 v;
     if (LAYOUT == LPX_ELEMENT_MAJOR && np_vec) {  // 16-byte aligned rows
         v = *reinterpret_cast<const f4*>(ut + r * Np + j0);
+    } else if constexpr (LAYOUT == LPX_DOF_MAJOR) {
+        // columns j0 .. j0+3 share (j >> 2) & 3 = lane group: one permuted slot
+        const float* p = ut + j0 * TILE_E + (r ^ dm_swz<LAYOUT, TILE_E>(j0));
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v[t] = p[t * TILE_E];
     } else {
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-            v[t] = LAYOUT == LPX_ELEMENT_MAJOR ? ut[r * Np + j0 + t] : ut[(j0 + t) * TILE_E + r];
+        for (int t = 0; t < 4; ++t) v[t] = ut[r * Np + j0 + t];
     }
     if constexpr (MASK) {
 #pragma unroll
@@ -411,14 +435,15 @@ __device__ __forceinline__ f4 u_quad_lds(const float* ut, int Np, bool np_vec, i
 // registers, each lane's 4 or 16 bytes at base + lane * size).  A tile is
 // a raw copy of its bytes in global memory, cut into 16-byte chunks; chunk
 // c sits at slot byte 16c.  Loader wave lw (of NLW) loads chunks
-// c = lane + 64 * (lw + NLW * q), q < PER_LANE.  Chunks past the tile are
+// c = lane + 64 * (lw * PER_LANE + q), q < PER_LANE.  Chunks past the tile are
 // clamped to its last chunk (the duplicates land in the slot's slack and
 // are never read), so every regular tile costs exactly PER_LANE load
 // instructions per loader wave and the loader can wait for one tile with a
 // compile-time vmcnt while later tiles are still in flight.
 //   element-major: chunk c = floats 4c..4c+3 of the run of nvalid*Np floats;
 //   DOF-major:     chunk c = row j = c / (TILE_E/4), columns
-//                  4*(c % (TILE_E/4)) .. +3.
+//                  4*(c % (TILE_E/4)) .. +3 (64-element tiles: the columns
+//                  of the chunk that belongs at slot chunk c under dm_swz).
 // A tile whose chunks are not all whole 16-byte aligned runs (the last
 // element-major tile when nvalid*Np % 4 != 0; every DOF-major tile when
 // E % 4 != 0) is loaded with 4-byte loads instead (4*PER_LANE
@@ -456,7 +481,7 @@ __device__ __forceinline__ bool loader_issue(const ContractArgs& a, float* slot,
             const int nch = nflat / 4;
 #pragma unroll
             for (int q = 0; q < PL; ++q) {
-                const int w = lw + NLW * q;
+                const int w = lw * PL + q;
                 const int c = lane + 64 * w;
                 dma16(src + 4 * (c < nch ? c : nch - 1), slot + 256 * w);
             }
@@ -464,7 +489,7 @@ __device__ __forceinline__ bool loader_issue(const ContractArgs& a, float* slot,
         }
 #pragma unroll
         for (int q = 0; q < 4 * PL; ++q) {
-            const int w = lw + NLW * q;
+            const int w = lw * 4 * PL + q;
             const int f = lane + 64 * w;
             dma4(src + (f < nflat ? f : nflat - 1), slot + 64 * w);
         }
@@ -474,28 +499,33 @@ __device__ __forceinline__ bool loader_issue(const ContractArgs& a, float* slot,
         // instruction w reads row  l / CPR + w * (64 / CPR)  at a column that
         // does not depend on w: one base address per lane plus a uniform
         // row stride per instruction.
+        // With 64-element tiles the slot position of a lane's chunk is fixed
+        // and the permutation (dm_swz) picks the element chunk it fetches:
+        // row j = lane / 16 + 4w has (j >> 2) & 3 = w & 3 (16-byte loads),
+        // row j = w (4-byte loads).
         constexpr int CPR = TILE_E / 4;
         if (a.e_vec) {  // uniform: E % 4 == 0, so nvalid % 4 == 0 and rows are aligned
-            int col = 4 * (lane % CPR);
-            col = col < nvalid ? col : nvalid - 4;  // columns >= nvalid are never used
-            const float* base = a.u + e0 + col;
 #pragma unroll
             for (int q = 0; q < PL; ++q) {
-                const int w = lw + NLW * q;
+                const int w = lw * PL + q;
+                int col = 4 * (lane % CPR);
+                if constexpr (TILE_E == 64) col ^= (w & 3) << 4;
+                col = col < nvalid ? col : nvalid - 4;  // columns >= nvalid are never used
                 int j = lane / CPR + w * (64 / CPR);
                 j = j < a.Np ? j : a.Np - 1;  // rows past Np land in the slot's slack
-                dma16(base + (int64_t)j * a.E, slot + 256 * w);
+                dma16(a.u + e0 + col + (int64_t)j * a.E, slot + 256 * w);
             }
             return true;
         }
-        const int r = lane % TILE_E;
-        const float* base = a.u + e0 + (r < nvalid ? r : nvalid - 1);
 #pragma unroll
         for (int q = 0; q < 4 * PL; ++q) {
-            const int w = lw + NLW * q;
+            const int w = lw * 4 * PL + q;
+            int r = lane % TILE_E;
+            if constexpr (TILE_E == 64) r ^= ((w >> 2) & 3) << 4;
+            r = r < nvalid ? r : nvalid - 1;
             int j = lane / TILE_E + w * (64 / TILE_E);
             j = j < a.Np ? j : a.Np - 1;
-            dma4(base + (int64_t)j * a.E, slot + 64 * w);
+            dma4(a.u + e0 + r + (int64_t)j * a.E, slot + 64 * w);
         }
         return false;
     }
@@ -583,6 +613,18 @@ __global__ __launch_bounds__(kArrangeThreads) void arrange_d_kernel(ContractArgs
                                                     blockIdx.x * kArrangeThreads + threadIdx.x);
 }
 
+// Streaming store of 16 bytes (the non-temporal hint: the line is written
+// through without being kept in the caches).  Used where every store
+// instruction writes whole contiguous runs (the store waves' copy-out, 1 KiB
+// per instruction) and for the DOF-major direct stores; measured on MI355X at
+// K=3, Np=56, E=2^20: bf16x3 staged-output kernels 187 -> 148 us
+// (element-major) and 191 -> 152 us (DOF-major).  Element-major direct
+// stores (64-byte pieces of each element's run, completed in L2 by other
+// row blocks) stay ordinary stores: streaming them doubled the time.
+__device__ __forceinline__ void store_stream(float* p, const f4& v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<f4*>(p));
+}
+
 // Write-back of one chunk of a wave's row blocks (p = pc + q*WPE, q < PMAX).
 // Element-major: lane l holds stacked rows R0 .. R0+3 (R0 = 16p + 4(l/16))
 // of element e; with Np % 4 == 0 they belong to one operator k = R0 / Np.
@@ -618,7 +660,7 @@ __device__ __forceinline__ void store_pairs(const ContractArgs& a, const f4 (&ac
             if (R < rows && e < a.E) {
                 float* dst = a.out + (int64_t)R * a.E + e;
                 if (a.e_vec) {
-                    *reinterpret_cast<f4*>(dst) = acc[q];
+                    store_stream(dst, acc[q]);
                 } else {
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
@@ -691,7 +733,7 @@ __device__ __forceinline__ void store_tile(const ContractArgs& a, const float* o
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
                         const int c = c0 + STRIDE * u;
-                        if (c < nch) reinterpret_cast<f4*>(g)[c] = v[u];
+                        if (c < nch) store_stream(g + 4 * c, v[u]);
                     }
                 }
             } else {
@@ -703,22 +745,28 @@ __device__ __forceinline__ void store_tile(const ContractArgs& a, const float* o
         constexpr int LDR = TILE_E + 4;  // padded slot row
         const int rows = a.K * a.Np;
         if (a.e_vec) {  // E % 4 == 0: nvalid % 4 == 0 and every row segment is aligned
-            const int nch = rows * CPR;
-            for (int c0 = 64 * sw + lane; c0 < nch; c0 += STRIDE * U) {
+            // Chunk c = 64*sw + lane + STRIDE*m is row c / CPR, column 4*(c % CPR):
+            // CPR divides 64, so a lane keeps its column and moves RSTEP rows
+            // per step (pointers advanced, no per-chunk division).
+            constexpr int RSTEP = STRIDE / CPR;
+            const int col = 4 * (lane % CPR);
+            const bool colok = col < nvalid;
+            int row = (64 * sw + lane) / CPR;
+            float* dst = a.out + (int64_t)row * a.E + e0 + col;
+            const int64_t dstep = (int64_t)RSTEP * a.E;
+            for (; row < rows; row += RSTEP * U) {
                 f4 v[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    int c = c0 + STRIDE * u;
-                    c = c < nch ? c : nch - 1;
-                    v[u] = *reinterpret_cast<const f4*>(os + (c / CPR) * LDR + 4 * (c % CPR));
+                    const int rr = row + RSTEP * u < rows ? row + RSTEP * u : rows - 1;
+                    v[u] = *reinterpret_cast<const f4*>(os + rr * LDR + col);
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int c = c0 + STRIDE * u;
-                    if (c < nch && 4 * (c % CPR) < nvalid)
-                        *reinterpret_cast<f4*>(a.out + (int64_t)(c / CPR) * a.E + e0 +
-                                               4 * (c % CPR)) = v[u];
+                    if (row + RSTEP * u < rows && colok)
+                        store_stream(dst + u * dstep, v[u]);
                 }
+                dst += U * dstep;
             }
         } else {
             const int n = rows * TILE_E;
@@ -727,6 +775,132 @@ __device__ __forceinline__ void store_tile(const ContractArgs& a, const float* o
                 if (r < nvalid) a.out[(int64_t)row * a.E + e0 + r] = os[row * LDR + r];
             }
         }
+    }
+}
+
+// dG volume term, write-back of a staged tile: the slot holds the K
+// reference derivatives (layout of stage_pairs) and the tile's geometric
+// factors at gs (element-major: gs[r*K*K + d*K + k] for element e0 + r;
+// DOF-major: gs[(d*K + k)*TILE_E + r]); store wave sw writes
+// out[d] = sum_k G(e,d,k) * slot[k] (FP32, k increasing) for d < K.
+template <int LAYOUT, int TILE_E, int NSW>
+__device__ __forceinline__ void store_tile_dg(const ContractArgs& a, const float* os,
+                                              const float* gs, int64_t e0, int nvalid, int sw,
+                                              int lane) {
+    constexpr int STRIDE = 64 * NSW;
+    const int K = a.K;
+    if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
+        const int run = nvalid * a.Np;  // floats of one d
+        const int KK = K * K;
+        for (int d = 0; d < K; ++d) {
+            float* g = a.out + ((int64_t)d * a.E + e0) * a.Np;
+            if (a.np_vec) {  // 4 floats of a chunk belong to one element
+                const int nch = run >> 2;
+                for (int c = 64 * sw + lane; c < nch; c += STRIDE) {
+                    const int f = 4 * c;
+                    const int r = row_op(a, f);  // element of the tile: f / Np
+                    const int i = f - r * a.Np;
+                    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int k = 0; k < LPX_DG_MAX_K; ++k) {
+                        if (k < K) {
+                            const f4 v = *reinterpret_cast<const f4*>(
+                                os + (k * TILE_E + r) * a.Np + i);
+                            const float gk = gs[r * KK + d * K + k];
+#pragma unroll
+                            for (int t = 0; t < 4; ++t) acc[t] = fmaf(gk, v[t], acc[t]);
+                        }
+                    }
+                    store_stream(g + 4 * c, acc);
+                }
+            } else {
+                for (int f = 64 * sw + lane; f < run; f += STRIDE) {
+                    const int r = row_op(a, f);
+                    const int i = f - r * a.Np;
+                    float acc = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < LPX_DG_MAX_K; ++k)
+                        if (k < K) acc = fmaf(gs[r * KK + d * K + k], os[(k * TILE_E + r) * a.Np + i], acc);
+                    g[f] = acc;
+                }
+            }
+        }
+    } else {
+        constexpr int CPR = TILE_E / 4;  // 16-byte chunks per row
+        constexpr int LDR = TILE_E + 4;  // padded slot row
+        const int rows = K * a.Np;       // output rows d*Np + i
+        if (a.e_vec) {
+            constexpr int RSTEP = STRIDE / CPR;
+            const int col = 4 * (lane % CPR);
+            const bool colok = col < nvalid;
+            for (int row = (64 * sw + lane) / CPR; row < rows; row += RSTEP) {
+                const int d = row_op(a, row), i = row - d * a.Np;
+                f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int k = 0; k < LPX_DG_MAX_K; ++k) {
+                    if (k < K) {
+                        const f4 v = *reinterpret_cast<const f4*>(os + (k * a.Np + i) * LDR + col);
+                        const f4 gk = *reinterpret_cast<const f4*>(gs + (d * K + k) * TILE_E + col);
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) acc[t] = fmaf(gk[t], v[t], acc[t]);
+                    }
+                }
+                if (colok) store_stream(a.out + (int64_t)row * a.E + e0 + col, acc);
+            }
+        } else {
+            const int n = rows * TILE_E;
+            for (int f = 64 * sw + lane; f < n; f += STRIDE) {
+                const int row = f / TILE_E, r = f % TILE_E;
+                if (r >= nvalid) continue;
+                const int d = row_op(a, row), i = row - d * a.Np;
+                float acc = 0.0f;
+#pragma unroll
+                for (int k = 0; k < LPX_DG_MAX_K; ++k)
+                    if (k < K)
+                        acc = fmaf(gs[(d * K + k) * TILE_E + r], os[(k * a.Np + i) * LDR + r], acc);
+                a.out[(int64_t)row * a.E + e0 + r] = acc;
+            }
+        }
+    }
+}
+
+// dG volume term: the compute waves copy a tile's geometric factors into its
+// staged output slot (they issue no other global access in the staged-output
+// pipeline when D sits in LDS or registers, so waiting for these loads costs
+// nothing else).  Compute wave cw (of NCW) loads floats f = cw*64 + lane +
+// 64*NCW*q of the tile's factors: element-major the run G[e0*K*K ..), DOF-
+// major row f / TILE_E (= d*K + k) at element f % TILE_E.  Reads past the
+// tile are clamped in bounds and never stored past the slot's G area.
+template <int TILE_E, int NCW>
+struct GTile {
+    static constexpr int Q = (TILE_E * LPX_DG_MAX_K * LPX_DG_MAX_K + 64 * NCW - 1) / (64 * NCW);
+};
+
+template <int LAYOUT, int TILE_E, int NCW>
+__device__ __forceinline__ void g_tile_load(const ContractArgs& a, int64_t e0, int nvalid, int cw,
+                                            int lane, float (&gv)[GTile<TILE_E, NCW>::Q]) {
+    const int KK = a.K * a.K;
+#pragma unroll
+    for (int q = 0; q < GTile<TILE_E, NCW>::Q; ++q) {
+        const int f = cw * 64 + lane + 64 * NCW * q;
+        if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
+            const int nflat = nvalid * KK;
+            gv[q] = a.G[e0 * KK + (f < nflat ? f : nflat - 1)];
+        } else {
+            const int row = f / TILE_E, r = f % TILE_E;
+            gv[q] = a.G[(int64_t)(row < KK ? row : KK - 1) * a.E + e0 + (r < nvalid ? r : nvalid - 1)];
+        }
+    }
+}
+
+template <int TILE_E, int NCW>
+__device__ __forceinline__ void g_tile_store(const ContractArgs& a, float* gs, int cw, int lane,
+                                             const float (&gv)[GTile<TILE_E, NCW>::Q]) {
+    const int n = TILE_E * a.K * a.K;
+#pragma unroll
+    for (int q = 0; q < GTile<TILE_E, NCW>::Q; ++q) {
+        const int f = cw * 64 + lane + 64 * NCW * q;
+        if (f < n) gs[f] = gv[q];
     }
 }
 
@@ -1045,9 +1219,12 @@ struct Shape {
                          NSW = CS.nsw, THREADS = CS.threads;
 };
 
-template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PREFETCH, int UNROLL>
+// EPI = 1: the dG volume term (needs PREFETCH bit 3): the tile's geometric
+// factors travel with its staged output and the store waves apply them.
+template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PREFETCH, int UNROLL, int EPI = 0>
 __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void contract_kernel(
     ContractArgs a) {
+    static_assert(EPI == 0 || (PREFETCH & 8), "the dG epilogue runs in the store waves");
     extern __shared__ __align__(16) unsigned char lds[];
     using S = Shape<TILE_E, NTMAX, PREFETCH>;
     constexpr bool PF_D = (PREFETCH & 1) != 0;
@@ -1119,9 +1296,14 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
                 for (int64_t n = 0; n < niter; ++n) {
                     if (n >= 1) {
                         const int64_t tile = t0 + (n - 1) * g;
-                        store_tile<LAYOUT, TILE_E, S::NSW>(a, oring + ((n - 1) & 1) * a.ldo,
-                                                           tile * TILE_E, nvalid_of(tile), sw,
-                                                           lane);
+                        const float* os = oring + ((n - 1) & 1) * a.ldo;
+                        if constexpr (EPI)
+                            store_tile_dg<LAYOUT, TILE_E, S::NSW>(a, os, os + a.ldo_g,
+                                                                  tile * TILE_E, nvalid_of(tile),
+                                                                  sw, lane);
+                        else
+                            store_tile<LAYOUT, TILE_E, S::NSW>(a, os, tile * TILE_E,
+                                                               nvalid_of(tile), sw, lane);
                     }
                     __syncthreads();
                 }
@@ -1149,6 +1331,21 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
                     for (int b = 0; b < S::BPW; ++b)
                         if (16 * (eblk0 + b * BSTRIDE) < nv)
                             block(tile, n, 16 * (eblk0 + b * BSTRIDE));
+                }
+            };
+            // dG volume term: the tile's geometric factors are loaded before
+            // its MFMA work and written to its output slot after it
+            auto with_g = [&](int64_t n, auto&& work) {
+                if constexpr (EPI) {
+                    const int64_t tile = t0 + n * g;
+                    float gv[GTile<TILE_E, S::NCW>::Q];
+                    g_tile_load<LAYOUT, TILE_E, S::NCW>(a, tile * TILE_E, nvalid_of(tile), wave,
+                                                        lane, gv);
+                    work();
+                    g_tile_store<TILE_E, S::NCW>(a, oring + (n & 1) * a.ldo + a.ldo_g, wave,
+                                                 lane, gv);
+                } else {
+                    work();
                 }
             };
             if constexpr (D_REG) {
@@ -1198,10 +1395,12 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
                 __syncthreads();
                 for (int64_t n = 0; n < niter; ++n) {
                     if (n < nmine) {
-                        if constexpr (S::BPW == 4)
-                            pipelined(n);
-                        else
-                            tile_work(block, n);
+                        with_g(n, [&] {
+                            if constexpr (S::BPW == 4)
+                                pipelined(n);
+                            else
+                                tile_work(block, n);
+                        });
                     }
                     __syncthreads();
                 }
@@ -1224,7 +1423,7 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
                     };
                     __syncthreads();
                     for (int64_t n = 0; n < niter; ++n) {
-                        if (n < nmine) tile_work(block, n);
+                        if (n < nmine) with_g(n, [&] { tile_work(block, n); });
                         __syncthreads();
                     }
                 });

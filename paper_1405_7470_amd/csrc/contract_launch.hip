@@ -12,18 +12,18 @@ namespace lpx {
 namespace {
 
 ContractFn select(const ContractGeom& g) {
-    const bool em = g.layout == LPX_ELEMENT_MAJOR;
+    const bool em = g.layout == LPX_ELEMENT_MAJOR, dg = g.dg != 0;
     const int nt = g.ntmax, t = g.tile_e, pf = g.prefetch, un = g.unroll;
     switch (g.prec) {
         case LPX_FP32:
-            return em ? contract_instance<LPX_FP32, LPX_ELEMENT_MAJOR>(nt, t, pf, un)
-                      : contract_instance<LPX_FP32, LPX_DOF_MAJOR>(nt, t, pf, un);
+            return em ? contract_instance<LPX_FP32, LPX_ELEMENT_MAJOR>(nt, t, pf, un, dg)
+                      : contract_instance<LPX_FP32, LPX_DOF_MAJOR>(nt, t, pf, un, dg);
         case LPX_BF16:
-            return em ? contract_instance<LPX_BF16, LPX_ELEMENT_MAJOR>(nt, t, pf, un)
-                      : contract_instance<LPX_BF16, LPX_DOF_MAJOR>(nt, t, pf, un);
+            return em ? contract_instance<LPX_BF16, LPX_ELEMENT_MAJOR>(nt, t, pf, un, dg)
+                      : contract_instance<LPX_BF16, LPX_DOF_MAJOR>(nt, t, pf, un, dg);
         default:
-            return em ? contract_instance<LPX_BF16X3, LPX_ELEMENT_MAJOR>(nt, t, pf, un)
-                      : contract_instance<LPX_BF16X3, LPX_DOF_MAJOR>(nt, t, pf, un);
+            return em ? contract_instance<LPX_BF16X3, LPX_ELEMENT_MAJOR>(nt, t, pf, un, dg)
+                      : contract_instance<LPX_BF16X3, LPX_DOF_MAJOR>(nt, t, pf, un, dg);
     }
 }
 
@@ -96,7 +96,7 @@ int64_t darr_bytes(const ContractGeom& g) {
 }
 
 lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g, void* stream,
-                           bool noalloc) {
+                           bool noalloc, const float* G) {
     DeviceInfo dev;
     lpx_status s = current_device_info(&dev);
     if (s != LPX_OK) return s;
@@ -129,6 +129,8 @@ lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g, vo
     a.nsteps = g.nsteps;
     a.ldu = g.ldu;
     a.ldo = g.ldo;
+    a.G = G;
+    a.ldo_g = g.ldo_g;
     a.np_vec = (c.Np % 4) == 0;
     a.e_vec = (c.E % 4) == 0;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);

@@ -91,6 +91,8 @@ struct ContractGeom {
     int nrb = 0;       // stacked row blocks of 16 rows of D as [K*Np][Np]: ceil(K*Np / 16)
     int ldu = 0;       // LDS ring slot stride of a staged u tile (floats)
     int ldo = 0;       // LDS ring slot stride of a staged output tile (floats)
+    int dg = 0;        // dG volume term: the metric epilogue in the store waves
+    int ldo_g = 0;     // dg: float offset of the geometric factors in an output slot
     int64_t ntiles = 0;
     int64_t nfrag = 0;     // staged D fragments: nrb*nsteps*64 lanes
     int64_t lds_bytes = 0; // dynamic LDS per work-group (0 if no prefetch)
@@ -98,11 +100,18 @@ struct ContractGeom {
 
 // Fills g; returns LPX_OK or LPX_ERR_UNSUPPORTED (with error text) when the
 // shape is outside what the record's kernels are built for.
+// dg: geometry of the dG volume kernels (the output slots also carry the
+// tile's geometric factors).
 lpx_status contract_geometry(int K, int Np, int64_t E, int layout,
-                             const lpx_record& r, ContractGeom* g);
+                             const lpx_record& r, ContractGeom* g, bool dg = false);
 
 // Every check of lpx_contract / lpx_gemm that needs no HIP call.
-lpx_status validate_contract(const lpx_contract_desc* c, const lpx_record* rec, ContractGeom* g);
+lpx_status validate_contract(const lpx_contract_desc* c, const lpx_record* rec, ContractGeom* g,
+                             bool dg = false);
+// The dG volume term: every check without a HIP call; *chosen receives the
+// record used (rec, or the default NULL stands for).
+lpx_status validate_dg(const lpx_dg_volume_desc* c, const lpx_record* rec, ContractGeom* g,
+                       lpx_record* chosen);
 lpx_status validate_gemm(const lpx_gemm_desc* g, const lpx_record* rec, bool* noop);
 bool overlaps(const void* a, int64_t abytes, const void* b, int64_t bbytes);
 bool mul_overflows(int64_t a, int64_t b, int64_t* r);
@@ -123,7 +132,7 @@ lpx_status workspace_alloc(void** p, size_t bytes, void* stream, const char* wha
 // library's static device scratch instead of a per-call workspace; the
 // caller has checked darr_bytes(g) against LPX_NOALLOC_SCRATCH_BYTES.
 lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g,
-                           void* stream, bool noalloc = false);
+                           void* stream, bool noalloc = false, const float* G = nullptr);
 
 // Bytes of D's MFMA-order arrangement in memory for a geometry (0 when the
 // record keeps D in LDS or registers).

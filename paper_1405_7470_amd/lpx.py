@@ -87,6 +87,13 @@ class ContractDesc(ctypes.Structure):
                 ("D", ctypes.c_void_p), ("u", ctypes.c_void_p), ("out", ctypes.c_void_p)]
 
 
+class DgDesc(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("Np", ctypes.c_int32), ("E", ctypes.c_int64),
+                ("layout", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("D", ctypes.c_void_p), ("u", ctypes.c_void_p), ("G", ctypes.c_void_p),
+                ("out", ctypes.c_void_p)]
+
+
 class GemmDesc(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_int64),
                 ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
@@ -122,6 +129,9 @@ def lib():
         L.lpx_contract.argtypes = [ctypes.POINTER(ContractDesc), ctypes.POINTER(Record), vp]
         L.lpx_contract_noalloc.argtypes = [ctypes.POINTER(ContractDesc), ctypes.POINTER(Record),
                                            vp]
+        L.lpx_dg_volume.argtypes = [ctypes.POINTER(DgDesc), ctypes.POINTER(Record), vp]
+        L.lpx_dg_volume_validate.argtypes = [ctypes.POINTER(DgDesc), ctypes.POINTER(Record),
+                                             ctypes.POINTER(Record)]
         L.lpx_split_bf16.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
         L.lpx_autotune.argtypes = [ctypes.POINTER(ContractDesc), ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, vp, ctypes.c_int64, vp, ctypes.POINTER(Record),
@@ -165,7 +175,8 @@ def lib():
         for name in ("lpx_autotune", "lpx_tune_cache_insert", "lpx_tune_cache_clear",
                      "lpx_record_default", "lpx_record_validate", "lpx_record_describe",
                      "lpx_record_enumerate", "lpx_contract_lds_bytes", "lpx_contract_validate",
-                     "lpx_contract", "lpx_contract_noalloc", "lpx_split_bf16"):
+                     "lpx_contract", "lpx_contract_noalloc", "lpx_split_bf16",
+                     "lpx_dg_volume", "lpx_dg_volume_validate"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -303,6 +314,48 @@ def contract(D, u, out=None, layout="em", record=None, stream=None):
     recp = ctypes.byref(record) if record is not None else None
     _check(lib().lpx_contract(ctypes.byref(desc), recp, _stream_handle(stream)))
     return out
+
+
+def g_shape(K, E, layout):
+    """Shape of the geometric factors of the dG volume term."""
+    return (E, K, K) if layout == "em" else (K, K, E)
+
+
+def make_dg_desc(D, u, G, out, layout):
+    K, Np, E = contract_shapes(D, u, layout)
+    for name, t in (("D", D), ("u", u), ("G", G), ("out", out)):
+        if t.dtype != torch.float32:
+            raise TypeError(f"{name} must be float32")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+    if tuple(G.shape) != g_shape(K, E, layout):
+        raise ValueError(f"G must have shape {g_shape(K, E, layout)}")
+    if out.numel() != K * E * Np:
+        raise ValueError(f"out must hold K*E*Np = {K * E * Np} floats")
+    ptr = lambda t: t.data_ptr() if t.numel() else None  # noqa: E731
+    return DgDesc(K, Np, E, LAYOUT[layout], 0, ptr(D), ptr(u), ptr(G), ptr(out))
+
+
+def dg_volume(D, u, G, out=None, layout="em", record=None, stream=None):
+    """dG volume term out[d,e,i] = sum_k G(e,d,k) sum_j D[k][i][j] u[e][j]
+    through lpx_dg_volume.  G: (E, K, K) for "em", (K, K, E) for "dm"; out
+    as for contract().  record: a staged-output Record (prefetch 10, 11 or
+    14) or None (the library's default for the shape)."""
+    K, Np, E = contract_shapes(D, u, layout)
+    if out is None:
+        out = torch.empty(out_shape(K, Np, E, layout), dtype=torch.float32, device=u.device)
+    desc = make_dg_desc(D, u, G, out, layout)
+    recp = ctypes.byref(record) if record is not None else None
+    _check(lib().lpx_dg_volume(ctypes.byref(desc), recp, _stream_handle(stream)))
+    return out
+
+
+def dg_volume_validate(desc, rec=None):
+    """(status, record used) of lpx_dg_volume_validate."""
+    chosen = Record()
+    recp = ctypes.byref(rec) if rec is not None else None
+    st = lib().lpx_dg_volume_validate(ctypes.byref(desc), recp, ctypes.byref(chosen))
+    return st, chosen
 
 
 def contract_noalloc(D, u, out, layout="em", record=None, stream=None):

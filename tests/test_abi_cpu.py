@@ -267,3 +267,38 @@ def test_noalloc_refuses_oversize_arrangement_before_any_hip_call():
     # zero sizes are no-ops with no HIP call
     assert lpx.contract_noalloc_status(desc(E=0, D=None, u=None, out=None), None,
                                        stream=0) == lpx.OK
+
+
+def dgdesc(K=3, Np=56, E=1000, layout=0, D=A, u=A + (1 << 24), G=A + (1 << 27),
+           out=A + (1 << 28), reserved=0):
+    return lpx.DgDesc(K, Np, E, layout, reserved, D, u, G, out)
+
+
+def test_dg_volume_validation():
+    st, rec = lpx.dg_volume_validate(dgdesc())
+    assert st == lpx.OK and (rec.tile_e, rec.prefetch) == (64, 14)  # the NULL default
+    for pf in (10, 11, 14):
+        assert lpx.dg_volume_validate(dgdesc(), lpx.record("bf16x3", 32, pf, 1))[0] == lpx.OK
+    for pf in (0, 1, 2, 3, 4, 6):  # no staged output tile: no epilogue
+        assert lpx.dg_volume_validate(dgdesc(), lpx.record("fp32", 32, pf, 1))[0] == \
+            lpx.ERR_UNSUPPORTED
+        assert "staged output" in lpx.last_error()
+    assert lpx.dg_volume_validate(dgdesc(K=4))[0] == lpx.ERR_UNSUPPORTED
+    assert lpx.dg_volume_validate(dgdesc(G=None))[0] == lpx.ERR_INVALID_ARG
+    assert lpx.dg_volume_validate(dgdesc(G=A + (1 << 27) + 4))[0] == lpx.ERR_INVALID_ARG
+    assert lpx.dg_volume_validate(dgdesc(G=A + (1 << 28) + 64))[0] == lpx.ERR_ALIAS
+    assert lpx.dg_volume_validate(dgdesc(out=A + 16))[0] == lpx.ERR_ALIAS  # out over D
+    for kw in (dict(E=0), dict(K=0), dict(Np=0)):
+        d = dgdesc(D=None, u=None, G=None, out=None, **kw)
+        assert lpx.dg_volume_validate(d)[0] == lpx.OK
+        assert lpx.lib().lpx_dg_volume(ctypes.byref(d), None, None) == lpx.OK
+    # the default falls back to smaller tiles and D from memory where the
+    # rings do not fit: Np = 120, DOF-major
+    st, rec = lpx.dg_volume_validate(dgdesc(Np=120, layout=1, G=A + (1 << 30),
+                                            out=A + (1 << 31)))
+    assert st == lpx.OK and rec.prefetch == 10 and rec.tile_e < 64
+    # the G area of the output slots counts against LDS: a record that fits
+    # the plain contraction at the edge of the budget may not fit the dG one
+    r = lpx.record("fp32", 64, 14, 1)
+    s_plain, b_plain = lpx.lds_bytes(3, 56, 1000, "em", r)
+    assert s_plain == lpx.OK
