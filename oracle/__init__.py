@@ -12,6 +12,8 @@ Functions follow the plain definitions:
   * ``dg_volume`` out[d,e,i] = sum_k G(e,d,k) sum_j D[k][i][j] u[e][j]
     (Table 1 "dG FEM volume": reference derivatives combined with
     per-element geometric factors);
+  * ``coulomb``   phi[t] = sum_s q_s / |x_t - y_s|          (Table 1 "3D
+    Coulomb pot."), FP64;
   * ``bf16_rne`` / ``split_bf16``  reduced-precision operand emulation;
   * ``mlp``       the cost model's forward, backward and Adam step (numpy).
 """
@@ -45,6 +47,8 @@ class Oracle:
         L.oracle_dg_volume.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long,
                                        ctypes.c_int, ctypes.c_int, f32p, f32p, f32p,
                                        ctypes.c_long, ctypes.c_long, f64p]
+        L.oracle_coulomb.argtypes = [ctypes.c_long, ctypes.c_long, ctypes.c_int, f32p, f32p,
+                                     ctypes.c_long, ctypes.c_long, f64p]
         L.oracle_threads.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         self.L = L
@@ -108,6 +112,27 @@ class Oracle:
                                 ref.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         return ref
 
+    def coulomb(self, targets, sources, layout="em", t0=0, n=None):
+        """FP64 potential ref[t - t0] = sum_s q_s / |x_t - y_s| (pairs at zero
+        distance skipped).  layout "em" (AoS): targets (nt, 4) with columns
+        x, y, z, unused; sources (ns, 4) = x, y, z, q.  "dm" (SoA): targets
+        (3, nt), sources (4, ns)."""
+        tg, pt = _f32(targets)
+        sr, ps = _f32(sources)
+        if layout == "em":
+            assert tg.ndim == 2 and tg.shape[1] == 4 and sr.ndim == 2 and sr.shape[1] == 4
+            nt, ns = tg.shape[0], sr.shape[0]
+        else:
+            assert tg.ndim == 2 and tg.shape[0] == 3 and sr.ndim == 2 and sr.shape[0] == 4
+            nt, ns = tg.shape[1], sr.shape[1]
+        if n is None:
+            n = nt - t0
+        assert 0 <= t0 and t0 + n <= nt
+        ref = np.zeros(n, dtype=np.float64)
+        self.L.oracle_coulomb(nt, ns, LAYOUT[layout], pt, ps, t0, n,
+                              ref.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return ref
+
     def gemm(self, A, B, precision="fp32", m0=0, nm=None):
         """FP64 reference rows C[m0:m0+nm, :] of C = A @ B (row-major)."""
         A, pA = _f32(A)
@@ -163,6 +188,10 @@ def contract(D, u, layout="em", precision="fp32", e0=0, ne=None):
 
 def gemm(A, B, precision="fp32", m0=0, nm=None):
     return default().gemm(A, B, precision, m0, nm)
+
+
+def coulomb(targets, sources, layout="em", t0=0, n=None):
+    return default().coulomb(targets, sources, layout, t0, n)
 
 
 def dg_volume(D, u, G, layout="em", precision="fp32", e0=0, ne=None):

@@ -185,6 +185,43 @@ void oracle_dg_volume(int K, int Np, long E, int layout, int precision,
     }
 }
 
+/* 3D Coulomb potential (Table 1's "3D Coulomb pot." workload, counted in
+ * pairs per second; the paper names it only).  Reading: the potential at
+ * each target point due to point charges at the source points,
+ *
+ *   ref[t - t0] = sum_{s < ns, r_ts > 0} q_s / r_ts,
+ *   r_ts = |x_t - y_s| (Euclidean, 3D),
+ *
+ * sources in increasing index order, FP64; a source at the target's own
+ * position (r = 0) contributes nothing.  Storage (the paper's array-of-
+ * structures / structure-of-arrays layout switch): LAYOUT_EM = AoS, target
+ * t at tg[4t .. 4t+2] (4t+3 unused), source s at sr[4s .. 4s+3] = (x, y, z,
+ * q); LAYOUT_DM = SoA, target coordinate c at tg[c*nt + t], source field f
+ * at sr[f*ns + s]. */
+void oracle_coulomb(long nt, long ns, int layout, const float* tg, const float* sr, long t0,
+                    long n, double* ref) {
+    if (n <= 0) return;
+#pragma omp parallel for schedule(static)
+    for (long dt = 0; dt < n; ++dt) {
+        long t = t0 + dt;
+        double xt[3];
+        for (int c = 0; c < 3; ++c)
+            xt[c] = (layout == LAYOUT_EM) ? (double)tg[4 * t + c] : (double)tg[c * nt + t];
+        double acc = 0.0;
+        for (long s = 0; s < ns; ++s) {
+            double r2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                double ys = (layout == LAYOUT_EM) ? (double)sr[4 * s + c] : (double)sr[c * ns + s];
+                double d = xt[c] - ys;
+                r2 += d * d;
+            }
+            double q = (layout == LAYOUT_EM) ? (double)sr[4 * s + 3] : (double)sr[3 * ns + s];
+            if (r2 > 0.0) acc += q / sqrt(r2);
+        }
+        ref[dt] = acc;
+    }
+}
+
 /* C[m - m0][n] = sum_{k=0}^{Kd-1} A[m][k] * B[k][n], A (M x Kd) and
  * B (Kd x N) row-major, FP64, for m in [m0, m0 + nm). */
 void oracle_gemm(long M, long N, long Kd, int precision, const float* A,

@@ -50,6 +50,24 @@ def dg_volume_inputs(K, Np, E, seed=0, layout="em"):
     return D, u, G
 
 
+def coulomb_inputs(nt, ns, seed=0, layout="em"):
+    """Targets and point charges for the Coulomb potential: target and
+    source positions uniform in the unit cube, charges q ~ U(-1, 1), drawn
+    in that order.  Element-major ("em", array of structures): targets
+    (nt, 4) = x, y, z, 0 and sources (ns, 4) = x, y, z, q; DOF-major ("dm",
+    structure of arrays): targets (3, nt), sources (4, ns)."""
+    rng = np.random.default_rng(seed)
+    xt = rng.uniform(0.0, 1.0, size=(nt, 3)).astype(np.float32)
+    xs = rng.uniform(0.0, 1.0, size=(ns, 3)).astype(np.float32)
+    q = _uniform(rng, (ns,))
+    if layout == "em":
+        tg = np.zeros((nt, 4), np.float32)
+        tg[:, :3] = xt
+        sr = np.concatenate([xs, q[:, None]], axis=1).astype(np.float32)
+        return tg, np.ascontiguousarray(sr)
+    return np.ascontiguousarray(xt.T), np.ascontiguousarray(np.concatenate([xs.T, q[None]]))
+
+
 def integer_contraction_inputs(K, Np, E, seed=0, layout="em", bound=8):
     """Small-integer operands in [-bound, bound]: every product and partial
     sum is exact in FP32 (and in bf16 for |x| <= 256)."""

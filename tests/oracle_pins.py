@@ -334,6 +334,82 @@ def pin_dg_layouts_chunks_integers(o):
         assert np.array_equal(o.dg_volume(Di, ui, Gi, "em", precision), exact)
 
 
+def _coulomb_aos(xt, xs, q):
+    tg = np.zeros((len(xt), 4), np.float32)
+    tg[:, :3] = xt
+    sr = np.zeros((len(xs), 4), np.float32)
+    sr[:, :3] = xs
+    sr[:, 3] = q
+    return tg, sr
+
+
+def pin_coulomb_closed_forms(o):
+    """A single charge at Pythagorean offsets (3-4-12-13 and 2-3-6-7 triples,
+    square roots exact) and a target at the centre of a cube of eight equal
+    charges: the potential q / r of the mathematics."""
+    xs = np.array([[0.5, 0.25, 0.125]], np.float32)
+    q = np.array([0.75], np.float32)
+    xt = xs + np.array([[3, 4, 12], [2, 3, 6], [-6, 2, -3], [0, 0, 2]], np.float32)
+    tg, sr = _coulomb_aos(xt, xs, q)
+    ref = o.coulomb(tg, sr)
+    assert list(ref) == [0.75 / 13.0, 0.75 / 7.0, 0.75 / 7.0, 0.375]
+    a = 0.5
+    corners = np.array([[sx * a, sy * a, sz * a] for sx in (-1, 1) for sy in (-1, 1)
+                        for sz in (-1, 1)], np.float32)
+    tg, sr = _coulomb_aos(np.zeros((1, 3), np.float32), corners, np.full(8, 2.0, np.float32))
+    want = 8 * 2.0 / (a * np.sqrt(3.0))
+    assert abs(o.coulomb(tg, sr)[0] - want) <= 1e-15 * want
+
+
+def pin_coulomb_bruteforce_and_self_pairs(o):
+    """Small random sets against a numpy FP64 pairwise sum; targets equal to
+    the sources: the zero-distance pair of each target contributes nothing."""
+    rng = np.random.default_rng(31)
+    xt = rng.uniform(0, 1, (50, 3)).astype(np.float32)
+    xs = rng.uniform(0, 1, (70, 3)).astype(np.float32)
+    q = rng.uniform(-1, 1, 70).astype(np.float32)
+    for a, b in ((xt, xs), (xs, xs)):
+        tg, sr = _coulomb_aos(a, b, q)
+        d = a.astype(np.float64)[:, None, :] - b.astype(np.float64)[None, :, :]
+        r = np.sqrt((d * d).sum(-1))
+        with np.errstate(divide="ignore"):
+            w = np.where(r > 0, q.astype(np.float64)[None, :] / r, 0.0)
+        want = w.sum(1)
+        got = o.coulomb(tg, sr)
+        assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
+
+
+def pin_coulomb_scaling_and_superposition(o):
+    """Doubling every coordinate halves the potential exactly (power-of-two
+    scaling commutes with rounding); charges add (dyadic charges, so their
+    FP32 sum is exact)."""
+    tg, sr = inputs.coulomb_inputs(40, 90, seed=3)
+    ref = o.coulomb(tg, sr)
+    tg2, sr2 = tg.copy(), sr.copy()
+    tg2[:, :3] *= 2
+    sr2[:, :3] *= 2
+    assert np.array_equal(o.coulomb(tg2, sr2), ref / 2)
+    rng = np.random.default_rng(4)
+    q1 = rng.integers(-8, 9, 90).astype(np.float32) / 8
+    q2 = rng.integers(-8, 9, 90).astype(np.float32) / 8
+    sa, sb, sc = sr.copy(), sr.copy(), sr.copy()
+    sa[:, 3], sb[:, 3], sc[:, 3] = q1, q2, q1 + q2
+    s = o.coulomb(tg, sa) + o.coulomb(tg, sb)
+    assert np.max(np.abs(o.coulomb(tg, sc) - s)) <= 1e-13 * np.max(np.abs(s))
+
+
+def pin_coulomb_layouts_chunks(o):
+    """Array-of-structures and structure-of-arrays storage give the same
+    values; a chunk of targets equals the same rows of the whole."""
+    tg, sr = inputs.coulomb_inputs(33, 57, seed=5, layout="em")
+    tgd, srd = inputs.coulomb_inputs(33, 57, seed=5, layout="dm")
+    assert np.array_equal(tgd, tg[:, :3].T) and np.array_equal(srd, sr.T)
+    em = o.coulomb(tg, sr, "em")
+    assert np.array_equal(o.coulomb(tgd, srd, "dm"), em)
+    assert np.array_equal(o.coulomb(tg, sr, "em", 7, 11), em[7:18])
+    assert np.array_equal(o.coulomb(tgd, srd, "dm", 20, 13), em[20:33])
+
+
 ALL_PINS = [
     pin_contract_bruteforce,
     pin_contract_identity,
@@ -348,4 +424,6 @@ ALL_PINS = [
     pin_gemm,
     pin_dg_bruteforce, pin_dg_identity_and_diagonal, pin_dg_permutation_and_linearity,
     pin_dg_layouts_chunks_integers,
+    pin_coulomb_closed_forms, pin_coulomb_bruteforce_and_self_pairs,
+    pin_coulomb_scaling_and_superposition, pin_coulomb_layouts_chunks,
 ]

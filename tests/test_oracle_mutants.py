@@ -28,6 +28,13 @@ MUTANTS = [
     ("dg_wrong_derivative", "acc += (double)g * t[k * Np + i];", "acc += (double)g * t[d * Np + i];"),
     ("dg_drops_last_k", "for (int k = 0; k < K; ++k) {\n                    float g",
      "for (int k = 0; k < K - 1; ++k) {\n                    float g"),
+    ("coulomb_no_sqrt", "if (r2 > 0.0) acc += q / sqrt(r2);", "if (r2 > 0.0) acc += q / r2;"),
+    ("coulomb_sum_not_difference", "double d = xt[c] - ys;", "double d = xt[c] + ys;"),
+    ("coulomb_self_pair_kept", "if (r2 > 0.0) acc += q / sqrt(r2);",
+     "acc += q / sqrt(r2 + 1e-300);"),
+    ("coulomb_soa_stride", "(double)sr[c * ns + s]", "(double)sr[c * nt + s]"),
+    ("coulomb_charge_field", "(double)sr[4 * s + 3]", "(double)sr[4 * s + 2]"),
+    ("coulomb_chunk_offset", "long t = t0 + dt;", "long t = dt;"),
     ("dg_G_in_float", "acc += (double)g * t[k * Np + i];", "acc += (double)(g * (float)t[k * Np + i]);"),
 ]
 
