@@ -234,6 +234,68 @@ def extras(stream, learned_picker=None):
     return res, samples
 
 
+COULOMB_NT, COULOMB_NS = 1 << 20, 1 << 15
+# v_sub x3, v_mul, v_fmac x3, v_cmp, v_cndmask at the full FP32 rate and
+# v_rsq_f32 at a quarter of it: 13 VALU lane-slots per pair.  FP32 vector
+# peak 157.3 TFLOP/s = 256 CUs x 2.4 GHz x 128 FMA lanes per clock, so
+# 256 x 128 x 2.4e9 lane-slots per second
+COULOMB_SLOTS_PER_PAIR = 13
+COULOMB_PEAK_PAIRS = 256 * 128 * 2.4e9 / COULOMB_SLOTS_PER_PAIR
+
+
+def coulomb_extras(stream):
+    """The 3D Coulomb potential at 2^20 targets x 2^15 sources, every
+    variant in both storage layouts (median of 3 launches each)."""
+    res = {"nt": COULOMB_NT, "ns": COULOMB_NS, "unit": "Mpairs/s",
+           "alu_peak_mpairs": COULOMB_PEAK_PAIRS / 1e6, "layouts": {}}
+    pairs = COULOMB_NT * COULOMB_NS
+    for layout in ("em", "dm"):
+        tg, sr = inputs.coulomb_inputs(COULOMB_NT, COULOMB_NS, seed=0, layout=layout)
+        tgd, srd = torch.from_numpy(tg).cuda(), torch.from_numpy(sr).cuda()
+        phi = torch.empty(COULOMB_NT, device="cuda")
+        sweep = []
+        for rec in lpx.coulomb_records():
+            t = _event_time(lambda: lpx.coulomb(tgd, srd, phi, layout=layout, record=rec,
+                                                stream=stream), 3, stream)
+            sweep.append([rec.tile_e * 16, rec.prefetch, rec.unroll, round(t * 1e6, 1),
+                          round(pairs / t / 1e6, 0)])
+        best = max(sweep, key=lambda r: r[4])
+        res["layouts"]["aos" if layout == "em" else "soa"] = {
+            "best": {"source_tile": best[0], "prefetch": best[1], "targets_per_thread": best[2],
+                     "us": best[3], "mpairs_per_s": best[4],
+                     "frac_alu_peak": best[4] * 1e6 / COULOMB_PEAK_PAIRS},
+            "sweep_columns": ["source_tile", "prefetch", "targets_per_thread", "us", "Mpairs/s"],
+            "sweep": sweep}
+        del tgd, srd, phi
+    return res
+
+
+def dg_extras(stream):
+    """The dG volume term at K = 3, Np = 56, E = 2^20 (the contraction plus
+    per-element 3 x 3 geometric factors applied by the store waves)."""
+    Kd, Npd, Ed = K, NP, E
+    flop = 2 * Kd * Ed * Npd * Npd + 2 * Kd * Kd * Ed * Npd
+    nbytes = 4 * (Ed * Npd + Kd * Ed * Npd + Kd * Npd * Npd + Kd * Kd * Ed)
+    out = {"workload": f"K={Kd} Np={Npd} E={Ed}", "gflop": flop / 1e9, "gbytes": nbytes / 1e9,
+           "runs": []}
+    for layout in ("em", "dm"):
+        D, u, G = inputs.dg_volume_inputs(Kd, Npd, Ed, seed=0, layout=layout)
+        Dd, ud, Gd = (torch.from_numpy(x).cuda() for x in (D, u, G))
+        o = torch.empty(lpx.out_shape(Kd, Npd, Ed, layout), device="cuda")
+        for prec, tile, pf in (("fp32", 64, 14), ("fp32", 64, 10), ("bf16x3", 64, 14),
+                               ("bf16x3", 32, 14)):
+            rec = lpx.record(prec, tile, pf, 1)
+            t = _event_time(lambda: lpx.dg_volume(Dd, ud, Gd, out=o, layout=layout, record=rec,
+                                                  stream=stream), 5, stream)
+            tf = flop / t / 1e12
+            roof = min(PEAK_TFLOPS[prec], flop / nbytes * PEAK_HBM_GBS / 1000.0)
+            out["runs"].append({"layout": layout, "record": lpx.describe(rec), "us": t * 1e6,
+                                "tflops": tf, "gbs": nbytes / t / 1e9,
+                                "pct_roof": 100 * tf / roof})
+        del Dd, ud, Gd, o
+    return out
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -434,6 +496,12 @@ def main():
                 stream, learned_picker=(pk if learned is not None else None))
         except Exception as exc:  # side measurements never hide the main line
             line["extras"] = {"error": repr(exc)}
+    if not args.no_extras:
+        for name, fn in (("coulomb", coulomb_extras), ("dg_volume", dg_extras)):
+            try:
+                line["extras"][name] = fn(stream)
+            except Exception as exc:  # side measurements never hide the main line
+                line["extras"][name] = {"error": repr(exc)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"], line["parity"] = cpu_leg(args.cpu_seconds, host, gpu_chunks,
                                                        small_host, ex_samples)

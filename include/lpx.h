@@ -191,6 +191,23 @@ typedef struct lpx_dg_volume_desc {
                       /* overlap D, u or G                                */
 } lpx_dg_volume_desc;
 
+/* --------------------------------------------- 3D Coulomb potential */
+/* phi[t] = sum over sources s with r_ts > 0 of q_s / r_ts, r_ts = |x_t - y_s|
+ * (Table 1's "3D Coulomb pot." workload; the paper names it only).  Storage
+ * (sec. 2.4.3, array of structures vs structure of arrays):
+ *   ELEMENT_MAJOR (AoS): target t at targets[4t .. 4t+2] (4t+3 unused),
+ *                        source s at sources[4s .. 4s+3] = (x, y, z, q);
+ *   DOF_MAJOR     (SoA): targets[c*nt + t], c < 3; sources[f*ns + s], f < 4. */
+typedef struct lpx_coulomb_desc {
+    int64_t nt;             /* targets, 0 .. 2^40                          */
+    int64_t ns;             /* sources, 0 .. 2^40                          */
+    int32_t layout;         /* LPX_ELEMENT_MAJOR / LPX_DOF_MAJOR            */
+    int32_t reserved;       /* must be 0                                    */
+    const float* targets;   /* device; AoS 16-byte aligned, SoA 4-byte      */
+    const float* sources;   /* device; as targets                           */
+    float* phi;             /* device, nt floats; must not overlap inputs   */
+} lpx_coulomb_desc;
+
 /* -------------------------------------------------------------- GEMM */
 /* C = A B, row-major FP32 (the degenerate case of the contraction). */
 typedef struct lpx_gemm_desc {
@@ -308,6 +325,22 @@ lpx_status lpx_dg_volume(const lpx_dg_volume_desc* c, const lpx_record* rec, voi
  * for. */
 lpx_status lpx_dg_volume_validate(const lpx_dg_volume_desc* c, const lpx_record* rec,
                                   lpx_record* chosen);
+
+/* The Coulomb potential, enqueued on `stream`.  The record is the
+ * variant: tile_e sets the source tile (16 * tile_e = 256, 512 or 1024
+ * sources, split_iname of the source loop, sec. 2.4.1), prefetch 2 stages
+ * each tile in LDS (add_prefetch, sec. 2.4.4) and 0 reads sources from
+ * global memory at one address per wave, unroll is the number of targets
+ * per thread (the `ilp` tag, sec. 2.4.2); precision must be FP32 and other
+ * prefetch values fail with LPX_ERR_UNSUPPORTED.  rec = NULL: tile_e 16,
+ * prefetch 0, unroll 1.  Each target sums its pairs in increasing source
+ * order in FP32 (reciprocal square root v_rsq_f32, fused multiply-adds), so
+ * every record gives bit-identical results.  A pair at zero distance
+ * contributes nothing.  nt = 0 is a no-op; ns = 0 writes zeros. */
+lpx_status lpx_coulomb(const lpx_coulomb_desc* c, const lpx_record* rec, void* stream);
+
+/* Every pre-launch check of lpx_coulomb, without any HIP call. */
+lpx_status lpx_coulomb_validate(const lpx_coulomb_desc* c, const lpx_record* rec);
 
 /* Dense GEMM  C[m][n] = sum_k A[m][k] B[k][n]  (the paper's sec. 2.1
  * reduction example sum(k, a[i,k]*b[k,j]); Table 1 "sgemm"), enqueued on

@@ -94,6 +94,12 @@ class DgDesc(ctypes.Structure):
                 ("out", ctypes.c_void_p)]
 
 
+class CoulombDesc(ctypes.Structure):
+    _fields_ = [("nt", ctypes.c_int64), ("ns", ctypes.c_int64), ("layout", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("targets", ctypes.c_void_p),
+                ("sources", ctypes.c_void_p), ("phi", ctypes.c_void_p)]
+
+
 class GemmDesc(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_int64),
                 ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
@@ -130,6 +136,8 @@ def lib():
         L.lpx_contract_noalloc.argtypes = [ctypes.POINTER(ContractDesc), ctypes.POINTER(Record),
                                            vp]
         L.lpx_dg_volume.argtypes = [ctypes.POINTER(DgDesc), ctypes.POINTER(Record), vp]
+        L.lpx_coulomb.argtypes = [ctypes.POINTER(CoulombDesc), ctypes.POINTER(Record), vp]
+        L.lpx_coulomb_validate.argtypes = [ctypes.POINTER(CoulombDesc), ctypes.POINTER(Record)]
         L.lpx_dg_volume_validate.argtypes = [ctypes.POINTER(DgDesc), ctypes.POINTER(Record),
                                              ctypes.POINTER(Record)]
         L.lpx_split_bf16.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
@@ -176,7 +184,8 @@ def lib():
                      "lpx_record_default", "lpx_record_validate", "lpx_record_describe",
                      "lpx_record_enumerate", "lpx_contract_lds_bytes", "lpx_contract_validate",
                      "lpx_contract", "lpx_contract_noalloc", "lpx_split_bf16",
-                     "lpx_dg_volume", "lpx_dg_volume_validate"):
+                     "lpx_dg_volume", "lpx_dg_volume_validate", "lpx_coulomb",
+                     "lpx_coulomb_validate"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -314,6 +323,44 @@ def contract(D, u, out=None, layout="em", record=None, stream=None):
     recp = ctypes.byref(record) if record is not None else None
     _check(lib().lpx_contract(ctypes.byref(desc), recp, _stream_handle(stream)))
     return out
+
+
+def coulomb_desc(targets, sources, phi, layout="em"):
+    """Descriptor of the Coulomb potential from CUDA tensors: AoS ("em")
+    targets (nt, 4), sources (ns, 4); SoA ("dm") targets (3, nt), sources
+    (4, ns); phi (nt,)."""
+    if layout == "em":
+        nt, ns = targets.shape[0], sources.shape[0]
+        ok = targets.dim() == 2 and targets.shape[1] == 4 and sources.shape[1:] == (4,)
+    else:
+        nt, ns = targets.shape[1], sources.shape[1]
+        ok = targets.dim() == 2 and targets.shape[0] == 3 and sources.shape[0] == 4
+    if not ok:
+        raise ValueError("targets/sources shapes do not match the layout")
+    for name, t in (("targets", targets), ("sources", sources), ("phi", phi)):
+        if t.dtype != torch.float32 or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous float32 tensor")
+    if phi.numel() != nt:
+        raise ValueError("phi must hold nt floats")
+    ptr = lambda t: t.data_ptr() if t.numel() else None  # noqa: E731
+    return CoulombDesc(nt, ns, LAYOUT[layout], 0, ptr(targets), ptr(sources), ptr(phi))
+
+
+def coulomb(targets, sources, phi=None, layout="em", record=None, stream=None):
+    """phi[t] = sum_s q_s / |x_t - y_s| through lpx_coulomb."""
+    nt = targets.shape[0] if layout == "em" else targets.shape[1]
+    if phi is None:
+        phi = torch.empty(nt, dtype=torch.float32, device=targets.device)
+    d = coulomb_desc(targets, sources, phi, layout)
+    recp = ctypes.byref(record) if record is not None else None
+    _check(lib().lpx_coulomb(ctypes.byref(d), recp, _stream_handle(stream)))
+    return phi
+
+
+def coulomb_records():
+    """The Coulomb variants: source tile 256/512/1024 (tile_e 16/32/64),
+    sources staged in LDS or not (prefetch 2/0), 1/2/4 targets per thread."""
+    return [record("fp32", t, p, u) for t in (16, 32, 64) for p in (0, 2) for u in (1, 2, 4)]
 
 
 def g_shape(K, E, layout):

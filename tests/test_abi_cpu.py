@@ -302,3 +302,28 @@ def test_dg_volume_validation():
     r = lpx.record("fp32", 64, 14, 1)
     s_plain, b_plain = lpx.lds_bytes(3, 56, 1000, "em", r)
     assert s_plain == lpx.OK
+
+
+def cdesc(nt=100, ns=50, layout=0, tg=A, sr=A + (1 << 20), phi=A + (1 << 24), reserved=0):
+    return lpx.CoulombDesc(nt, ns, layout, reserved, tg, sr, phi)
+
+
+def test_coulomb_validation():
+    v = lambda d, r=None: lpx.lib().lpx_coulomb_validate(  # noqa: E731
+        ctypes.byref(d), ctypes.byref(r) if r is not None else None)
+    assert v(cdesc()) == lpx.OK
+    for rec in lpx.coulomb_records():
+        assert v(cdesc(), rec) == lpx.OK
+    assert len(lpx.coulomb_records()) == 18
+    assert v(cdesc(), lpx.record("bf16x3", 16, 0, 1)) == lpx.ERR_UNSUPPORTED
+    assert v(cdesc(), lpx.record("fp32", 16, 1, 1)) == lpx.ERR_UNSUPPORTED
+    assert v(cdesc(), lpx.record("fp32", 16, 6, 1)) == lpx.ERR_UNSUPPORTED
+    assert v(cdesc(tg=A + 4)) == lpx.ERR_INVALID_ARG          # AoS needs 16-byte records
+    assert v(cdesc(layout=1, tg=A + 4)) == lpx.OK               # SoA: 4-byte floats
+    assert v(cdesc(phi=A + 64)) == lpx.ERR_ALIAS
+    assert v(cdesc(nt=-1)) == lpx.ERR_INVALID_ARG
+    assert v(cdesc(layout=3)) == lpx.ERR_INVALID_ARG
+    assert v(cdesc(sr=None)) == lpx.ERR_INVALID_ARG
+    assert v(cdesc(ns=0, sr=None)) == lpx.OK
+    d = cdesc(nt=0, tg=None, sr=None, phi=None)
+    assert v(d) == lpx.OK and lpx.lib().lpx_coulomb(ctypes.byref(d), None, None) == lpx.OK
