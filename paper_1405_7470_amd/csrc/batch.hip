@@ -317,6 +317,7 @@ lpx_status fill_table(lpx_batch* b, const lpx_contract_desc* items, const lpx_re
         it.a.ldo = g.ldo;
         it.a.np_vec = (c.Np % 4) == 0;
         it.a.e_vec = (c.E % 4) == 0;
+        it.a.stream_out = (int64_t)c.K * c.E * c.Np * 4 >= ((int64_t)32 << 20);
         it.tile_begin = tile;
         const int64_t frag_bytes = b->precision == LPX_FP32 ? 4 : (b->precision == LPX_BF16 ? 16 : 32);
         const int64_t dbytes = g.nfrag * frag_bytes;

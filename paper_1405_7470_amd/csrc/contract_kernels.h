@@ -81,6 +81,7 @@ struct ContractArgs {
     int ldo_g;
     int np_vec;  // Np % 4 == 0: 16-byte row accesses are aligned
     int e_vec;   // E % 4 == 0
+    int stream_out;  // large outputs: streaming (non-temporal) stores, see store_stream
 };
 
 // Operator index of stacked row R (0 <= R < 2^31).
@@ -621,8 +622,15 @@ __global__ __launch_bounds__(kArrangeThreads) void arrange_d_kernel(ContractArgs
 // (element-major) and 191 -> 152 us (DOF-major).  Element-major direct
 // stores (64-byte pieces of each element's run, completed in L2 by other
 // row blocks) stay ordinary stores: streaming them doubled the time.
-__device__ __forceinline__ void store_stream(float* p, const f4& v) {
-    __builtin_nontemporal_store(v, reinterpret_cast<f4*>(p));
+// The hint is applied only to outputs of at least 32 MiB (stream_out, set
+// by the host): a launch ends when its writes are acknowledged, and for small
+// outputs the streamed writes' longer acknowledgement shows as launch latency
+// (512 separate small contractions: 9.1 -> 12.3 ms with the hint everywhere).
+__device__ __forceinline__ void store_stream(const ContractArgs& a, float* p, const f4& v) {
+    if (a.stream_out)  // uniform
+        __builtin_nontemporal_store(v, reinterpret_cast<f4*>(p));
+    else
+        *reinterpret_cast<f4*>(p) = v;
 }
 
 // Write-back of one chunk of a wave's row blocks (p = pc + q*WPE, q < PMAX).
@@ -660,7 +668,7 @@ __device__ __forceinline__ void store_pairs(const ContractArgs& a, const f4 (&ac
             if (R < rows && e < a.E) {
                 float* dst = a.out + (int64_t)R * a.E + e;
                 if (a.e_vec) {
-                    store_stream(dst, acc[q]);
+                    store_stream(a, dst, acc[q]);
                 } else {
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
@@ -733,7 +741,7 @@ __device__ __forceinline__ void store_tile(const ContractArgs& a, const float* o
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
                         const int c = c0 + STRIDE * u;
-                        if (c < nch) store_stream(g + 4 * c, v[u]);
+                        if (c < nch) store_stream(a, g + 4 * c, v[u]);
                     }
                 }
             } else {
@@ -764,7 +772,7 @@ __device__ __forceinline__ void store_tile(const ContractArgs& a, const float* o
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     if (row + RSTEP * u < rows && colok)
-                        store_stream(dst + u * dstep, v[u]);
+                        store_stream(a, dst + u * dstep, v[u]);
                 }
                 dst += U * dstep;
             }
@@ -788,38 +796,62 @@ __device__ __forceinline__ void store_tile_dg(const ContractArgs& a, const float
                                               const float* gs, int64_t e0, int nvalid, int sw,
                                               int lane) {
     constexpr int STRIDE = 64 * NSW;
-    const int K = a.K;
+    constexpr int KM = LPX_DG_MAX_K;
+    const int K = a.K, KK = a.K * a.K;
     if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
         const int run = nvalid * a.Np;  // floats of one d
-        const int KK = K * K;
-        for (int d = 0; d < K; ++d) {
-            float* g = a.out + ((int64_t)d * a.E + e0) * a.Np;
-            if (a.np_vec) {  // 4 floats of a chunk belong to one element
-                const int nch = run >> 2;
-                for (int c = 64 * sw + lane; c < nch; c += STRIDE) {
-                    const int f = 4 * c;
-                    const int r = row_op(a, f);  // element of the tile: f / Np
-                    const int i = f - r * a.Np;
-                    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (a.np_vec) {
+            // A chunk (4 floats of one element) is read once for all K outputs:
+            // the K reference derivatives and the element's K x K factors.
+            // U chunks are read before any is combined and stored.
+            constexpr int U = 2;
+            const int nch = run >> 2;
+            for (int c0 = 64 * sw + lane; c0 < nch; c0 += STRIDE * U) {
+                f4 v[U][KM];
+                float gk[U][KM][KM];
 #pragma unroll
-                    for (int k = 0; k < LPX_DG_MAX_K; ++k) {
+                for (int u = 0; u < U; ++u) {
+                    int c = c0 + STRIDE * u;
+                    c = c < nch ? c : nch - 1;
+                    const int r = row_op(a, 4 * c), i = 4 * c - r * a.Np;
+#pragma unroll
+                    for (int k = 0; k < KM; ++k) {
                         if (k < K) {
-                            const f4 v = *reinterpret_cast<const f4*>(
-                                os + (k * TILE_E + r) * a.Np + i);
-                            const float gk = gs[r * KK + d * K + k];
+                            v[u][k] = *reinterpret_cast<const f4*>(os + (k * TILE_E + r) * a.Np + i);
 #pragma unroll
-                            for (int t = 0; t < 4; ++t) acc[t] = fmaf(gk, v[t], acc[t]);
+                            for (int d = 0; d < KM; ++d)
+                                if (d < K) gk[u][d][k] = gs[r * KK + d * K + k];
                         }
                     }
-                    store_stream(g + 4 * c, acc);
                 }
-            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int c = c0 + STRIDE * u;
+                    if (c >= nch) continue;
+#pragma unroll
+                    for (int d = 0; d < KM; ++d) {
+                        if (d >= K) continue;
+                        f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                        for (int k = 0; k < KM; ++k)
+                            if (k < K) {
+#pragma unroll
+                                for (int t = 0; t < 4; ++t)
+                                    acc[t] = fmaf(gk[u][d][k], v[u][k][t], acc[t]);
+                            }
+                        store_stream(a, a.out + ((int64_t)d * a.E + e0) * a.Np + 4 * c, acc);
+                    }
+                }
+            }
+        } else {
+            for (int d = 0; d < K; ++d) {
+                float* g = a.out + ((int64_t)d * a.E + e0) * a.Np;
                 for (int f = 64 * sw + lane; f < run; f += STRIDE) {
                     const int r = row_op(a, f);
                     const int i = f - r * a.Np;
                     float acc = 0.0f;
 #pragma unroll
-                    for (int k = 0; k < LPX_DG_MAX_K; ++k)
+                    for (int k = 0; k < KM; ++k)
                         if (k < K) acc = fmaf(gs[r * KK + d * K + k], os[(k * TILE_E + r) * a.Np + i], acc);
                     g[f] = acc;
                 }
@@ -828,34 +860,48 @@ __device__ __forceinline__ void store_tile_dg(const ContractArgs& a, const float
     } else {
         constexpr int CPR = TILE_E / 4;  // 16-byte chunks per row
         constexpr int LDR = TILE_E + 4;  // padded slot row
-        const int rows = K * a.Np;       // output rows d*Np + i
         if (a.e_vec) {
+            // A lane keeps one column chunk and walks rows i of the operator:
+            // its factors (K*K chunks of the G area) are read once per tile,
+            // the K slot rows k*Np + i once per row for all K outputs.
             constexpr int RSTEP = STRIDE / CPR;
             const int col = 4 * (lane % CPR);
             const bool colok = col < nvalid;
-            for (int row = (64 * sw + lane) / CPR; row < rows; row += RSTEP) {
-                const int d = row_op(a, row), i = row - d * a.Np;
-                f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            f4 gk[KM][KM];
 #pragma unroll
-                for (int k = 0; k < LPX_DG_MAX_K; ++k) {
-                    if (k < K) {
-                        const f4 v = *reinterpret_cast<const f4*>(os + (k * a.Np + i) * LDR + col);
-                        const f4 gk = *reinterpret_cast<const f4*>(gs + (d * K + k) * TILE_E + col);
+            for (int d = 0; d < KM; ++d)
 #pragma unroll
-                        for (int t = 0; t < 4; ++t) acc[t] = fmaf(gk[t], v[t], acc[t]);
-                    }
+                for (int k = 0; k < KM; ++k)
+                    if (d < K && k < K)
+                        gk[d][k] = *reinterpret_cast<const f4*>(gs + (d * K + k) * TILE_E + col);
+            for (int i = (64 * sw + lane) / CPR; i < a.Np; i += RSTEP) {
+                f4 v[KM];
+#pragma unroll
+                for (int k = 0; k < KM; ++k)
+                    if (k < K) v[k] = *reinterpret_cast<const f4*>(os + (k * a.Np + i) * LDR + col);
+#pragma unroll
+                for (int d = 0; d < KM; ++d) {
+                    if (d >= K) continue;
+                    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int k = 0; k < KM; ++k)
+                        if (k < K) {
+#pragma unroll
+                            for (int t = 0; t < 4; ++t) acc[t] = fmaf(gk[d][k][t], v[k][t], acc[t]);
+                        }
+                    if (colok)
+                        store_stream(a, a.out + (int64_t)(d * a.Np + i) * a.E + e0 + col, acc);
                 }
-                if (colok) store_stream(a.out + (int64_t)row * a.E + e0 + col, acc);
             }
         } else {
-            const int n = rows * TILE_E;
+            const int n = K * a.Np * TILE_E;
             for (int f = 64 * sw + lane; f < n; f += STRIDE) {
                 const int row = f / TILE_E, r = f % TILE_E;
                 if (r >= nvalid) continue;
                 const int d = row_op(a, row), i = row - d * a.Np;
                 float acc = 0.0f;
 #pragma unroll
-                for (int k = 0; k < LPX_DG_MAX_K; ++k)
+                for (int k = 0; k < KM; ++k)
                     if (k < K)
                         acc = fmaf(gs[(d * K + k) * TILE_E + r], os[(k * a.Np + i) * LDR + r], acc);
                 a.out[(int64_t)row * a.E + e0 + r] = acc;

@@ -133,6 +133,7 @@ lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g, vo
     a.ldo_g = g.ldo_g;
     a.np_vec = (c.Np % 4) == 0;
     a.e_vec = (c.E % 4) == 0;
+    a.stream_out = (int64_t)c.K * c.E * c.Np * 4 >= ((int64_t)32 << 20);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     // Kernels that read D from memory read its MFMA-order arrangement,
     // written by a pre-pass into a stream-ordered workspace.
