@@ -379,12 +379,16 @@ typedef struct lpx_batch lpx_batch;
 /* items[0..n-1]: contraction descriptors (validated as by lpx_contract; no
  * zero sizes); all must share one layout.  recs: one record per item (all
  * of one precision), or NULL to take each item's FP32 winner from the
- * tuning cache, else the FP32 default.
+ * tuning cache, else the FP32 default.  Each record is checked as
+ * lpx_contract would check it, but the batch takes from it only the
+ * precision and -- in the direct kernel below -- whether the instance keeps
+ * D on chip (prefetch bit 0 or 2): its tile_e, unroll and other storage
+ * bits are not used, because the batch runs one tile routine for all of
+ * its instances, chosen for the whole set.
  *   *h == NULL: builds the batch -- instances ordered largest first (cost
  *     K*Np^2*E) and cut into element tiles -- captures the persistent
  *     launch into a graph, launches it on `stream`, and returns the handle
- *     in *h.  The records fix the precision; the batch runs one tile
- *     routine for all instances: when its LDS rings fit (160 KiB), the
+ *     in *h.  The tile routine: when its LDS rings fit (160 KiB), the
  *     staged pipeline of prefetch bits 1 and 3 on 32-element tiles dealt
  *     round-robin to the work-groups (u tiles and outputs staged in LDS,
  *     D read from global memory); otherwise 16-element tiles pulled from
