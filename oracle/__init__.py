@@ -12,6 +12,8 @@ Functions follow the plain definitions:
   * ``dg_volume`` out[d,e,i] = sum_k G(e,d,k) sum_j D[k][i][j] u[e][j]
     (Table 1 "dG FEM volume": reference derivatives combined with
     per-element geometric factors);
+  * ``dg_surface`` out[e,i] = sum_m L[i][m] s(e,m/nfp) f(e,m) (Table 1 "dG
+    FEM surface": face fluxes lifted by a rectangular operator);
   * ``coulomb``   phi[t] = sum_s q_s / |x_t - y_s|          (Table 1 "3D
     Coulomb pot."), FP64;
   * ``bf16_rne`` / ``split_bf16``  reduced-precision operand emulation;
@@ -47,6 +49,9 @@ class Oracle:
         L.oracle_dg_volume.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long,
                                        ctypes.c_int, ctypes.c_int, f32p, f32p, f32p,
                                        ctypes.c_long, ctypes.c_long, f64p]
+        L.oracle_dg_surface.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_long,
+                                        ctypes.c_int, ctypes.c_int, f32p, f32p, f32p,
+                                        ctypes.c_long, ctypes.c_long, f64p]
         L.oracle_coulomb.argtypes = [ctypes.c_long, ctypes.c_long, ctypes.c_int, f32p, f32p,
                                      ctypes.c_long, ctypes.c_long, f64p]
         L.oracle_threads.restype = ctypes.c_int
@@ -110,6 +115,28 @@ class Oracle:
         ref = np.zeros((K, ne, Np), dtype=np.float64)
         self.L.oracle_dg_volume(K, Np, E, LAYOUT[layout], PREC[precision], pD, pu, pG, e0, ne,
                                 ref.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return ref
+
+    def dg_surface(self, L, f, sc, nf, layout="em", precision="fp32", e0=0, ne=None):
+        """FP64 lift chunk ref[e - e0, i] = sum_m L[i][m] fl32(s(e, m // nfp) f(e, m)).
+
+        L: (Np, M) float32; f: (E, M) for "em", (M, E) for "dm"; sc: (E, nf)
+        for "em", (nf, E) for "dm"; M = nf * nfp."""
+        L_, pL = _f32(L)
+        Np, M = L_.shape
+        assert M % nf == 0
+        nfp = M // nf
+        f_, pf = _f32(f)
+        s_, ps = _f32(sc)
+        E = f_.shape[0] if layout == "em" else f_.shape[1]
+        assert f_.shape == ((E, M) if layout == "em" else (M, E))
+        assert s_.shape == ((E, nf) if layout == "em" else (nf, E))
+        if ne is None:
+            ne = E - e0
+        assert 0 <= e0 and e0 + ne <= E
+        ref = np.zeros((ne, Np), dtype=np.float64)
+        self.L.oracle_dg_surface(Np, nf, nfp, E, LAYOUT[layout], PREC[precision], pL, pf, ps,
+                                 e0, ne, ref.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         return ref
 
     def coulomb(self, targets, sources, layout="em", t0=0, n=None):
@@ -188,6 +215,10 @@ def contract(D, u, layout="em", precision="fp32", e0=0, ne=None):
 
 def gemm(A, B, precision="fp32", m0=0, nm=None):
     return default().gemm(A, B, precision, m0, nm)
+
+
+def dg_surface(L, f, sc, nf, layout="em", precision="fp32", e0=0, ne=None):
+    return default().dg_surface(L, f, sc, nf, layout, precision, e0, ne)
 
 
 def coulomb(targets, sources, layout="em", t0=0, n=None):

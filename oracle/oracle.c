@@ -185,6 +185,42 @@ void oracle_dg_volume(int K, int Np, long E, int layout, int precision,
     }
 }
 
+/* Surface term of a nodal discontinuous Galerkin operator (the "dG FEM
+ * surface" workload of Table 1; named only).  Reading: each element's face
+ * fluxes (nf faces of nfp nodes, M = nf*nfp values) are scaled by a per-
+ * face factor (the surface-to-volume Jacobian ratio of an affine element)
+ * and lifted into the element's Np nodes by one rectangular operator
+ * L [Np][M]:
+ *
+ *   ref[e - e0][i] = sum_{m < M} L[i][m] * (s(e, m / nfp) * f(e, m)),
+ *
+ * m in increasing order, FP64, the scaled value rounded to FP32 first (the
+ * scaling is an FP32 product on the GPU); under a reduced-precision mode the
+ * scaled FP32 value and L are the operands rounded as in prod().
+ * Element-major: f(e, m) = f[e*M + m], s(e, c) = s[e*nf + c],
+ * out[e*Np + i]; DOF-major: f[m*E + e], s[c*E + e], out[i*E + e]. */
+void oracle_dg_surface(int Np, int nf, int nfp, long E, int layout, int precision,
+                       const float* L, const float* f, const float* sc, long e0, long ne,
+                       double* ref) {
+    const long M = (long)nf * nfp;
+    if (Np <= 0 || M <= 0 || ne <= 0) return;
+#pragma omp parallel for schedule(static)
+    for (long de = 0; de < ne; ++de) {
+        long e = e0 + de;
+        for (int i = 0; i < Np; ++i) {
+            double acc = 0.0;
+            for (long m = 0; m < M; ++m) {
+                long c = m / nfp;
+                float fv = (layout == LAYOUT_EM) ? f[e * M + m] : f[m * E + e];
+                float sv = (layout == LAYOUT_EM) ? sc[e * nf + c] : sc[c * E + e];
+                float g = sv * fv; /* FP32 product, as the GPU forms it */
+                acc += prod(L[(long)i * M + m], g, precision);
+            }
+            ref[de * Np + i] = acc;
+        }
+    }
+}
+
 /* 3D Coulomb potential (Table 1's "3D Coulomb pot." workload, counted in
  * pairs per second; the paper names it only).  Reading: the potential at
  * each target point due to point charges at the source points,

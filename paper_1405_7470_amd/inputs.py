@@ -50,6 +50,23 @@ def dg_volume_inputs(K, Np, E, seed=0, layout="em"):
     return D, u, G
 
 
+def dg_surface_inputs(Np, nf, nfp, E, seed=0, layout="em"):
+    """(L, f, s) for the dG surface (lift) workload: L ~ N(0, 1/M) of shape
+    (Np, M), M = nf * nfp; face fluxes f ~ U(-1, 1); per-face factors
+    s ~ U(0.5, 2) (surface-to-volume Jacobian ratios), drawn in that order.
+    Element-major: f (E, M), s (E, nf); DOF-major: the same values stored
+    (M, E) and (nf, E)."""
+    rng = np.random.default_rng(seed)
+    M = nf * nfp
+    L = rng.normal(0.0, 1.0 / math.sqrt(M), size=(Np, M)).astype(np.float32)
+    f = _uniform(rng, (E, M))
+    s = rng.uniform(0.5, 2.0, size=(E, nf)).astype(np.float32)
+    if layout == "dm":
+        f = np.ascontiguousarray(f.T)
+        s = np.ascontiguousarray(s.T)
+    return L, f, s
+
+
 def coulomb_inputs(nt, ns, seed=0, layout="em"):
     """Targets and point charges for the Coulomb potential: target and
     source positions uniform in the unit cube, charges q ~ U(-1, 1), drawn

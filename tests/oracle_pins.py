@@ -334,6 +334,73 @@ def pin_dg_layouts_chunks_integers(o):
         assert np.array_equal(o.dg_volume(Di, ui, Gi, "em", precision), exact)
 
 
+def pin_dg_surface_bruteforce(o):
+    """The lift on tiny shapes against exact rational sums of the FP32-
+    rounded scaled fluxes (numpy's float32 product) times the operator,
+    operands rounded per precision by the library bf16 routine."""
+    rng = np.random.default_rng(41)
+    for (Np, nf, nfp, E) in [(1, 1, 1, 1), (3, 2, 2, 4), (5, 4, 3, 3), (4, 3, 1, 2)]:
+        M = nf * nfp
+        L = rng.normal(0, 1, (Np, M)).astype(np.float32)
+        f = rng.uniform(-1, 1, (E, M)).astype(np.float32)
+        sc = rng.uniform(0.5, 2, (E, nf)).astype(np.float32)
+        g = (np.repeat(sc, nfp, axis=1) * f).astype(np.float32)
+        for precision in ("fp32", "bf16", "bf16x3"):
+            Lh, Ll = _operands(L, precision)
+            gh, gl = _operands(g, precision)
+            exact = np.empty((E, Np), dtype=object)
+            for e in range(E):
+                for i in range(Np):
+                    t = Fraction(0)
+                    for m in range(M):
+                        t += Fraction(float(Lh[i, m])) * Fraction(float(gh[e, m]))
+                        if precision == "bf16x3":
+                            t += Fraction(float(Lh[i, m])) * Fraction(float(gl[e, m]))
+                            t += Fraction(float(Ll[i, m])) * Fraction(float(gh[e, m]))
+                    exact[e, i] = t
+            for layout in ("em", "dm"):
+                ff = f if layout == "em" else np.ascontiguousarray(f.T)
+                ss = sc if layout == "em" else np.ascontiguousarray(sc.T)
+                ref = o.dg_surface(L, ff, ss, nf, layout, precision)
+                _assert_close_exact(ref, exact, M)
+
+
+def pin_dg_surface_against_contraction(o):
+    """One face (nf = 1) with unit factors and a square operator is the
+    contraction with K = 1, bit for bit; a factor of 2^k on a face scales
+    exactly the part of the sum that face contributes."""
+    Np, E = 12, 17
+    D, u = inputs.contraction_inputs(1, Np, E, seed=9)
+    for precision in ("fp32", "bf16x3"):
+        ref = o.dg_surface(D[0], u, np.ones((E, 1), np.float32), 1, "em", precision)
+        assert np.array_equal(ref, o.contract(D, u, "em", precision)[0])
+    # two faces of nfp = 6: face 1's factor 4, face 0's 1 -> contraction of the
+    # face-0 half plus 4x the contraction of the face-1 half
+    L, f, _ = inputs.dg_surface_inputs(Np, 2, 6, E, seed=10)
+    sc = np.ones((E, 2), np.float32)
+    sc[:, 1] = 4.0
+    got = o.dg_surface(L, f, sc, 2)
+    h0 = o.dg_surface(L[:, :6].copy(), f[:, :6].copy(), np.ones((E, 1), np.float32), 1)
+    h1 = o.dg_surface(L[:, 6:].copy(), f[:, 6:].copy(), np.ones((E, 1), np.float32), 1)
+    assert np.max(np.abs(got - (h0 + 4 * h1))) <= 1e-14 * np.max(np.abs(got))
+
+
+def pin_dg_surface_layouts_chunks_integers(o):
+    Np, nf, nfp, E = 10, 4, 5, 23
+    L, f, sc = inputs.dg_surface_inputs(Np, nf, nfp, E, seed=11)
+    em = o.dg_surface(L, f, sc, nf, "em")
+    dm = o.dg_surface(L, np.ascontiguousarray(f.T), np.ascontiguousarray(sc.T), nf, "dm")
+    assert np.array_equal(em, dm)
+    assert np.array_equal(o.dg_surface(L, f, sc, nf, "em", "fp32", 5, 9), em[5:14])
+    rng = np.random.default_rng(12)
+    Li = rng.integers(-4, 5, (Np, nf * nfp)).astype(np.float32)
+    fi = rng.integers(-4, 5, (E, nf * nfp)).astype(np.float32)
+    si = (2.0 ** rng.integers(-2, 3, (E, nf))).astype(np.float32)
+    exact = (np.repeat(si, nfp, axis=1).astype(np.float64) * fi) @ Li.T.astype(np.float64)
+    for precision in ("fp32", "bf16", "bf16x3"):
+        assert np.array_equal(o.dg_surface(Li, fi, si, nf, "em", precision), exact)
+
+
 def _coulomb_aos(xt, xs, q):
     tg = np.zeros((len(xt), 4), np.float32)
     tg[:, :3] = xt
@@ -426,4 +493,6 @@ ALL_PINS = [
     pin_dg_layouts_chunks_integers,
     pin_coulomb_closed_forms, pin_coulomb_bruteforce_and_self_pairs,
     pin_coulomb_scaling_and_superposition, pin_coulomb_layouts_chunks,
+    pin_dg_surface_bruteforce, pin_dg_surface_against_contraction,
+    pin_dg_surface_layouts_chunks_integers,
 ]

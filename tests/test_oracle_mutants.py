@@ -28,6 +28,13 @@ MUTANTS = [
     ("dg_wrong_derivative", "acc += (double)g * t[k * Np + i];", "acc += (double)g * t[d * Np + i];"),
     ("dg_drops_last_k", "for (int k = 0; k < K; ++k) {\n                    float g",
      "for (int k = 0; k < K - 1; ++k) {\n                    float g"),
+    ("surface_face_index", "long c = m / nfp;", "long c = m / nf;"),
+    ("surface_scale_ignored", "float g = sv * fv;", "float g = fv; (void)sv;"),
+    ("surface_scale_in_double", "acc += prod(L[(long)i * M + m], g, precision);",
+     "acc += (double)L[(long)i * M + m] * ((double)sv * (double)fv);"),
+    ("surface_L_transposed", "prod(L[(long)i * M + m], g, precision)",
+     "prod(L[(long)m * Np + i], g, precision)"),
+    ("surface_dm_flux_as_em", ": f[m * E + e];", ": f[e * M + m];"),
     ("coulomb_no_sqrt", "if (r2 > 0.0) acc += q / sqrt(r2);", "if (r2 > 0.0) acc += q / r2;"),
     ("coulomb_sum_not_difference", "double d = xt[c] - ys;", "double d = xt[c] + ys;"),
     ("coulomb_self_pair_kept", "if (r2 > 0.0) acc += q / sqrt(r2);",
