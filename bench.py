@@ -296,6 +296,32 @@ def dg_extras(stream):
     return out
 
 
+def surface_extras(stream):
+    """The dG surface (lift) term at Np = 56, 4 faces of 21 nodes, E = 2^20:
+    every variant in FP32 and bf16x3, both layouts (median of 5)."""
+    Nps, nf, nfp, Es = 56, 4, 21, E
+    M = nf * nfp
+    flop = 2 * Nps * M * Es
+    nbytes = 4 * (Es * M + Es * nf + Es * Nps + Nps * M)
+    out = {"workload": f"Np={Nps} nf={nf} nfp={nfp} E={Es}", "gflop": flop / 1e9,
+           "gbytes": nbytes / 1e9, "runs": []}
+    for layout in ("em", "dm"):
+        L, f, s = inputs.dg_surface_inputs(Nps, nf, nfp, Es, seed=0, layout=layout)
+        Ld, fd, sd = (torch.from_numpy(x).cuda() for x in (L, f, s))
+        o = torch.empty((Es, Nps) if layout == "em" else (Nps, Es), device="cuda")
+        for prec in ("fp32", "bf16x3"):
+            roof = min(PEAK_TFLOPS[prec], flop / nbytes * PEAK_HBM_GBS / 1000.0)
+            for rec in lpx.surface_records(prec):
+                t = _event_time(lambda: lpx.dg_surface(Ld, fd, sd, nf, out=o, layout=layout,
+                                                       record=rec, stream=stream), 5, stream)
+                tf = flop / t / 1e12
+                out["runs"].append({"layout": layout, "record": lpx.describe(rec), "us": t * 1e6,
+                                    "tflops": tf, "gbs": nbytes / t / 1e9,
+                                    "pct_roof": 100 * tf / roof})
+        del Ld, fd, sd, o
+    return out
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -497,7 +523,8 @@ def main():
         except Exception as exc:  # side measurements never hide the main line
             line["extras"] = {"error": repr(exc)}
     if not args.no_extras:
-        for name, fn in (("coulomb", coulomb_extras), ("dg_volume", dg_extras)):
+        for name, fn in (("coulomb", coulomb_extras), ("dg_volume", dg_extras),
+                         ("dg_surface", surface_extras)):
             try:
                 line["extras"][name] = fn(stream)
             except Exception as exc:  # side measurements never hide the main line

@@ -191,6 +191,35 @@ typedef struct lpx_dg_volume_desc {
                       /* overlap D, u or G                                */
 } lpx_dg_volume_desc;
 
+/* ------------------------------------------------ dG surface term */
+/* Surface term of a nodal discontinuous Galerkin operator (Table 1's "dG
+ * FEM surface"; named only).  Reading used here: each element's face
+ * fluxes (nf faces of nfp nodes, M = nf*nfp values) are scaled by a factor
+ * per face (the surface-to-volume Jacobian ratio of an affine element) and
+ * lifted into the element's Np nodes by one rectangular operator L:
+ *
+ *     out[e,i] = sum_{m<M} L[i][m] * fl32(s(e, m / nfp) * f(e, m))
+ *
+ * (the product of factor and flux rounded to FP32, then the operands
+ * treated per precision as for the contraction).  Storage:
+ *   ELEMENT_MAJOR: f[e*M + m], s[e*nf + c], out[e*Np + i];
+ *   DOF_MAJOR    : f[m*E + e], s[c*E + e], out[i*E + e].
+ * L is L[i*M + m] in both.                                               */
+typedef struct lpx_dg_surface_desc {
+    int32_t Np;       /* nodes per element, 0..128                        */
+    int32_t nf;       /* faces per element, >= 0                          */
+    int32_t nfp;      /* nodes per face, >= 0; nf*nfp <= 4096             */
+    int32_t layout;   /* LPX_ELEMENT_MAJOR / LPX_DOF_MAJOR                */
+    int64_t E;        /* number of elements, >= 0                         */
+    int32_t reserved; /* must be 0                                        */
+    int32_t reserved2;/* must be 0                                        */
+    const float* L;   /* device, Np*M floats, 16-byte aligned             */
+    const float* f;   /* device, E*M floats, 16-byte aligned              */
+    const float* s;   /* device, E*nf floats, 16-byte aligned             */
+    float* out;       /* device, E*Np floats, 16-byte aligned; must not   */
+                      /* overlap L, f or s                                */
+} lpx_dg_surface_desc;
+
 /* --------------------------------------------- 3D Coulomb potential */
 /* phi[t] = sum over sources s with r_ts > 0 of q_s / r_ts, r_ts = |x_t - y_s|
  * (Table 1's "3D Coulomb pot." workload; the paper names it only).  Storage
@@ -325,6 +354,21 @@ lpx_status lpx_dg_volume(const lpx_dg_volume_desc* c, const lpx_record* rec, voi
  * for. */
 lpx_status lpx_dg_volume_validate(const lpx_dg_volume_desc* c, const lpx_record* rec,
                                   lpx_record* chosen);
+
+/* The dG surface (lift) term, enqueued on `stream`: the contraction with a
+ * rectangular operator and the per-face scaling fused into the operand
+ * reads.  Record: precision FP32, BF16 or BF16X3; prefetch must be 1 (the
+ * operator is staged in LDS once per work-group, in MFMA operand order, up
+ * to 160 KiB: Np = 128 allows M up to 320), else LPX_ERR_UNSUPPORTED;
+ * tile_e / 16 element blocks go to each wave at a time, so each operator
+ * fragment read from LDS feeds that many MFMAs; unroll does not apply.
+ * rec = NULL: FP32, tile_e 16, prefetch 1.  Every record of a precision
+ * sums each output in column order with the same operations (bit-identical
+ * results).  Zero sizes are no-ops. */
+lpx_status lpx_dg_surface(const lpx_dg_surface_desc* c, const lpx_record* rec, void* stream);
+
+/* Every pre-launch check of lpx_dg_surface, without any HIP call. */
+lpx_status lpx_dg_surface_validate(const lpx_dg_surface_desc* c, const lpx_record* rec);
 
 /* The Coulomb potential, enqueued on `stream`.  The record is the
  * variant: tile_e sets the source tile (16 * tile_e = 256, 512 or 1024

@@ -94,6 +94,13 @@ class DgDesc(ctypes.Structure):
                 ("out", ctypes.c_void_p)]
 
 
+class SurfaceDesc(ctypes.Structure):
+    _fields_ = [("Np", ctypes.c_int32), ("nf", ctypes.c_int32), ("nfp", ctypes.c_int32),
+                ("layout", ctypes.c_int32), ("E", ctypes.c_int64), ("reserved", ctypes.c_int32),
+                ("reserved2", ctypes.c_int32), ("L", ctypes.c_void_p), ("f", ctypes.c_void_p),
+                ("s", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
 class CoulombDesc(ctypes.Structure):
     _fields_ = [("nt", ctypes.c_int64), ("ns", ctypes.c_int64), ("layout", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("targets", ctypes.c_void_p),
@@ -137,6 +144,8 @@ def lib():
                                            vp]
         L.lpx_dg_volume.argtypes = [ctypes.POINTER(DgDesc), ctypes.POINTER(Record), vp]
         L.lpx_coulomb.argtypes = [ctypes.POINTER(CoulombDesc), ctypes.POINTER(Record), vp]
+        L.lpx_dg_surface.argtypes = [ctypes.POINTER(SurfaceDesc), ctypes.POINTER(Record), vp]
+        L.lpx_dg_surface_validate.argtypes = [ctypes.POINTER(SurfaceDesc), ctypes.POINTER(Record)]
         L.lpx_coulomb_validate.argtypes = [ctypes.POINTER(CoulombDesc), ctypes.POINTER(Record)]
         L.lpx_dg_volume_validate.argtypes = [ctypes.POINTER(DgDesc), ctypes.POINTER(Record),
                                              ctypes.POINTER(Record)]
@@ -185,7 +194,7 @@ def lib():
                      "lpx_record_enumerate", "lpx_contract_lds_bytes", "lpx_contract_validate",
                      "lpx_contract", "lpx_contract_noalloc", "lpx_split_bf16",
                      "lpx_dg_volume", "lpx_dg_volume_validate", "lpx_coulomb",
-                     "lpx_coulomb_validate"):
+                     "lpx_coulomb_validate", "lpx_dg_surface", "lpx_dg_surface_validate"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -323,6 +332,43 @@ def contract(D, u, out=None, layout="em", record=None, stream=None):
     recp = ctypes.byref(record) if record is not None else None
     _check(lib().lpx_contract(ctypes.byref(desc), recp, _stream_handle(stream)))
     return out
+
+
+def surface_desc(L, f, s, out, nf, layout="em"):
+    """Descriptor of the dG surface (lift) term from CUDA tensors: L (Np, M);
+    f (E, M) and s (E, nf) for "em", (M, E) and (nf, E) for "dm"; out like
+    f with Np in place of M."""
+    Np, M = L.shape
+    if nf <= 0 or M % nf:
+        raise ValueError("nf must divide the operator's column count")
+    E = f.shape[0] if layout == "em" else f.shape[1]
+    want = {"f": (E, M) if layout == "em" else (M, E), "s": (E, nf) if layout == "em" else (nf, E),
+            "out": (E, Np) if layout == "em" else (Np, E)}
+    for name, t in (("L", L), ("f", f), ("s", s), ("out", out)):
+        if t.dtype != torch.float32 or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous float32 tensor")
+        if name in want and tuple(t.shape) != want[name]:
+            raise ValueError(f"{name} must have shape {want[name]}")
+    ptr = lambda t: t.data_ptr() if t.numel() else None  # noqa: E731
+    return SurfaceDesc(Np, nf, M // nf, LAYOUT[layout], E, 0, 0, ptr(L), ptr(f), ptr(s), ptr(out))
+
+
+def dg_surface(L, f, s, nf, out=None, layout="em", record=None, stream=None):
+    """out[e,i] = sum_m L[i][m] s(e, m // nfp) f(e, m) through lpx_dg_surface."""
+    Np = L.shape[0]
+    E = f.shape[0] if layout == "em" else f.shape[1]
+    if out is None:
+        out = torch.empty((E, Np) if layout == "em" else (Np, E), dtype=torch.float32,
+                          device=f.device)
+    d = surface_desc(L, f, s, out, nf, layout)
+    recp = ctypes.byref(record) if record is not None else None
+    _check(lib().lpx_dg_surface(ctypes.byref(d), recp, _stream_handle(stream)))
+    return out
+
+
+def surface_records(precision="fp32"):
+    """The lift variants of a precision: 1, 2 or 4 element blocks per wave."""
+    return [record(precision, t, 1, 1) for t in (16, 32, 64)]
 
 
 def coulomb_desc(targets, sources, phi, layout="em"):

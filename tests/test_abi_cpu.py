@@ -327,3 +327,30 @@ def test_coulomb_validation():
     assert v(cdesc(ns=0, sr=None)) == lpx.OK
     d = cdesc(nt=0, tg=None, sr=None, phi=None)
     assert v(d) == lpx.OK and lpx.lib().lpx_coulomb(ctypes.byref(d), None, None) == lpx.OK
+
+
+def sdesc(Np=56, nf=4, nfp=21, E=1000, layout=0, L=A, f=A + (1 << 20), s=A + (1 << 24),
+          out=A + (1 << 26), reserved=0):
+    return lpx.SurfaceDesc(Np, nf, nfp, layout, E, reserved, 0, L, f, s, out)
+
+
+def test_dg_surface_validation():
+    v = lambda d, r=None: lpx.lib().lpx_dg_surface_validate(  # noqa: E731
+        ctypes.byref(d), ctypes.byref(r) if r is not None else None)
+    assert v(sdesc()) == lpx.OK
+    for prec in ("fp32", "bf16", "bf16x3"):
+        for r in lpx.surface_records(prec):
+            assert v(sdesc(), r) == lpx.OK
+    assert v(sdesc(), lpx.record("fp32", 16, 0, 1)) == lpx.ERR_UNSUPPORTED  # not staged
+    assert v(sdesc(), lpx.record("fp32", 16, 3, 1)) == lpx.ERR_UNSUPPORTED
+    assert v(sdesc(Np=129)) == lpx.ERR_UNSUPPORTED
+    # LDS: FP32 fragments nrb * ceil(M/4) * 256 bytes; Np = 128, M = 320 fits, 324 not
+    assert v(sdesc(Np=128, nf=4, nfp=80)) == lpx.OK
+    assert v(sdesc(Np=128, nf=4, nfp=81)) == lpx.ERR_UNSUPPORTED
+    assert v(sdesc(f=A + (1 << 20) + 4)) == lpx.ERR_INVALID_ARG
+    assert v(sdesc(out=A + (1 << 20) + 64)) == lpx.ERR_ALIAS
+    assert v(sdesc(E=-1)) == lpx.ERR_INVALID_ARG
+    assert v(sdesc(s=None)) == lpx.ERR_INVALID_ARG
+    for kw in (dict(E=0), dict(Np=0), dict(nf=0)):
+        d = sdesc(L=None, f=None, s=None, out=None, **kw)
+        assert v(d) == lpx.OK and lpx.lib().lpx_dg_surface(ctypes.byref(d), None, None) == lpx.OK
