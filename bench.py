@@ -49,6 +49,11 @@ SAMPLE_STARTS = (0, E // 2 + 13, E - 256)       # element chunks checked against
 SAMPLE_LEN = 256
 
 
+def progress(msg):
+    """A progress line on stderr (long profiled runs show they are alive)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +65,9 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the GEMM and ragged-batch side measurements")
     ap.add_argument("--model", default=None, help="picker model file (default: the packaged one)")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="run only the side measurements (GEMM, ragged batch, dG volume and "
+                         "surface, Coulomb) and print them as one JSON line (for profiling)")
     return ap.parse_args()
 
 
@@ -185,9 +193,9 @@ def extras(stream, learned_picker=None):
         recs = [lpx.pick_variant(K, Np, Ei, "em", "fp32", mode=lpx.PICK_LEARNED,
                                  picker=learned_picker, stream=stream) for Np, Ei in shapes]
         how = "learned"
-    else:
-        recs = [lpx.record("fp32", 64, 1, 2)] * len(shapes)
-        how = "fixed fp32 tile_e=64 prefetch=1 unroll=2"
+    else:  # the default record is valid for every shape
+        recs = [lpx.default_record("fp32")] * len(shapes)
+        how = "default fp32 record"
     flop = sum(2 * K * Ei * Np * Np for Np, Ei in shapes)
     nbytes = sum(4 * (Ei * Np + K * Ei * Np + K * Np * Np) for Np, Ei in shapes)
     roof = sum(max(2 * K * Ei * Np * Np / (PEAK_TFLOPS["fp32"] * 1e12),
@@ -411,6 +419,18 @@ def main():
         sys.exit(2)
     torch.cuda.init()
     stream = torch.cuda.current_stream()
+    if args.extras_only:
+        from paper_1405_7470_amd import picker as picker_mod
+        model = args.model or picker_mod.MODEL_PATH
+        pk = lpx.Picker(model) if os.path.exists(model) else None
+        line = {"extras": extras(stream, learned_picker=pk)[0]}
+        progress("GEMM and batch done")
+        for name, fn in (("coulomb", coulomb_extras), ("dg_volume", dg_extras),
+                         ("dg_surface", surface_extras)):
+            line["extras"][name] = fn(stream)
+            progress(f"{name} done")
+        print(json.dumps(line), flush=True)
+        return
     work, host = {}, {}
     for layout, prec in PROBLEMS:
         if layout not in host:
@@ -429,6 +449,7 @@ def main():
         tuned[key], times = lpx.autotune(D, u, out, key[0], key[1], warmup=2, reps=5,
                                          stream=stream)
         sweeps[f"{key[0]}/{key[1]}"] = sweep_table(key, times)
+        progress(f"tuned {key[0]}/{key[1]}")
     learned, pick_info = None, None
     from paper_1405_7470_amd import picker as picker_mod
     model = args.model or picker_mod.MODEL_PATH
@@ -448,6 +469,7 @@ def main():
             results[name] = None
             continue
         ms, per = time_steps(work, recs, args.steps, args.warmup, stream)
+        progress(f"timed {name} records")
         results[name] = {
             "ms_per_step": ms,
             "tflops": len(work) * FLOP / (ms * 1e-3) / 1e12,
@@ -520,6 +542,7 @@ def main():
         try:
             line["extras"], ex_samples = extras(
                 stream, learned_picker=(pk if learned is not None else None))
+            progress("GEMM and batch done")
         except Exception as exc:  # side measurements never hide the main line
             line["extras"] = {"error": repr(exc)}
     if not args.no_extras:
@@ -527,6 +550,7 @@ def main():
                          ("dg_surface", surface_extras)):
             try:
                 line["extras"][name] = fn(stream)
+                progress(f"{name} done")
             except Exception as exc:  # side measurements never hide the main line
                 line["extras"][name] = {"error": repr(exc)}
     if not args.no_cpu_baseline:

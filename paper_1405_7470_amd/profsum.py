@@ -9,6 +9,8 @@ they support:
   ``--pmc`` run for the contraction kernels a bench.py line names, with the
   MFMA utilisation they imply (SQ_VALU_MFMA_BUSY_CYCLES over four SIMDs
   times SQ_BUSY_CU_CYCLES).
+* ``kernels``: per-dispatch counter averages of the side-workload kernels
+  (GEMM, ragged batch, dG, lift, Coulomb) whose names match a pattern.
 * ``traffic``: HBM bytes per launch of every contraction kernel from two
   ``--pmc`` runs (``FETCH_SIZE``, then ``WRITE_SIZE``; KiB per dispatch).
   Each counter is scaled by what it reads for the plain copy kernel
@@ -56,7 +58,7 @@ def contraction_kernel_name(precision, layout, Np, rec):
     ntmax = 2 if nt <= 2 else (4 if nt <= 4 else 8)
     unroll = 1 if rec.prefetch & 4 else rec.unroll  # register-D kernels are built once
     return (f"void lpx::kern::contract_kernel<{PRECISION_CODE[precision]}, {LAYOUT_CODE[layout]}, "
-            f"{ntmax}, {rec.tile_e}, {rec.prefetch}, {unroll}>(lpx::kern::ContractArgs)")
+            f"{ntmax}, {rec.tile_e}, {rec.prefetch}, {unroll}, 0>(lpx::kern::ContractArgs)")
 
 
 def _per_kernel(path, counter):
@@ -195,6 +197,33 @@ def write_counters(csv_path, bench_json, out, cmd, title):
                      " | ".join(f"{row.get(c, float('nan')):.4g}" for c in names) + " |\n")
 
 
+def write_kernel_counters(csv_path, out, cmd, title, pattern, top=30):
+    """Per-dispatch counter averages of every kernel whose name matches
+    `pattern` (the side workloads: GEMM, ragged batch, dG, lift, Coulomb),
+    with the MFMA utilisation when both SQ counters are present."""
+    table = counters(csv_path)
+    rx = re.compile(pattern)
+    names = sorted({c for k in table for c in table[k]})
+    keys = [k for k in table if rx.search(k)][:top]
+    with open(out, "w") as fh:
+        fh.write(f"# {title}\n\nCommand: `{cmd}`\n\n")
+        fh.write("Per-dispatch averages (counters summed over the device; a kernel's average "
+                 "mixes every shape it ran on in the command).  MFMA utilisation = "
+                 "SQ_VALU_MFMA_BUSY_CYCLES / (4 SIMDs x SQ_BUSY_CU_CYCLES).\n\n")
+        util_col = "SQ_VALU_MFMA_BUSY_CYCLES" in names and "SQ_BUSY_CU_CYCLES" in names
+        fh.write("| kernel |" + (" MFMA utilisation |" if util_col else "") +
+                 "".join(f" {n} |" for n in names) + "\n")
+        fh.write("|---|" + ("---|" if util_col else "") + "---|" * len(names) + "\n")
+        for k in sorted(keys):
+            row = table[k]
+            cells = []
+            if util_col:
+                cells.append(f"{row['SQ_VALU_MFMA_BUSY_CYCLES'] / (4.0 * row['SQ_BUSY_CU_CYCLES']):.3f}"
+                             if row.get("SQ_BUSY_CU_CYCLES") else "n/a")
+            cells += [f"{row.get(c, float('nan')):.4g}" for c in names]
+            fh.write(f"| `{k}` | " + " | ".join(cells) + " |\n")
+
+
 def write_stats(csv_path, out, cmd, title, top=25, trace_csv=None, bench_json=None):
     with open(csv_path, newline="") as fh:
         rows = list(csv.DictReader(fh))
@@ -247,6 +276,12 @@ def main():
     c.add_argument("--out", required=True)
     c.add_argument("--cmd", required=True)
     c.add_argument("--title", default="SQ counters of the contraction kernels")
+    k = sub.add_parser("kernels")
+    k.add_argument("--csv", required=True)
+    k.add_argument("--out", required=True)
+    k.add_argument("--cmd", required=True)
+    k.add_argument("--pattern", default=".")
+    k.add_argument("--title", default="Counters of the side-workload kernels")
     b = sub.add_parser("traffic")
     b.add_argument("--fetch", required=True)
     b.add_argument("--write", required=True)
@@ -261,6 +296,8 @@ def main():
                     bench_json=args.bench_json)
     elif args.what == "counters":
         write_counters(args.csv, args.bench_json, args.out, args.cmd, args.title)
+    elif args.what == "kernels":
+        write_kernel_counters(args.csv, args.out, args.cmd, args.title, args.pattern)
     else:
         rows, ff, fw = traffic(args.fetch, args.write, args.copy_bytes)
         write_traffic(args.out, rows, ff, fw, args.copy_bytes, args.cmd_fetch, args.cmd_write,
