@@ -392,16 +392,18 @@ lpx_status lpx_coulomb_validate(const lpx_coulomb_desc* c, const lpx_record* rec
  * products follow the same FP32 / BF16 / BF16X3 rules, FP32 accumulation)
  * and the tiling: gemm_tm x gemm_tn tile of C per work-group, gemm_tk-deep
  * k slabs staged in LDS (0 = 128 x 128 x 32 for FP32, 128 x 128 x 64 for
- * BF16 / BF16X3).  Built tilings: 64x64x32, 64x64x64, 128x128x32,
- * 128x128x64, 128x64x32, 64x128x32, and for FP32/BF16 also 256x128x32,
- * 128x256x32, 256x256x32; others return LPX_ERR_UNSUPPORTED.  BF16 / BF16X3
- * at 128x128x64 (with K > 0) first split both operands once into
- * K-contiguous bf16 planes (B transposed) in stream-ordered workspace
- * (allocated on `stream` from the library's own memory pool, freed the
- * same way), then stream the planes
- * into LDS with direct global-to-LDS loads; the other tilings convert the
- * FP32 operands slab by slab.  C is overwritten (no alpha/beta).  rec = NULL
- * means FP32 with the default tiling.  Errors as for lpx_contract. */
+ * BF16, and for BF16X3 256 x 256 x 32 when ceil(M/256) ceil(N/256) >= 256,
+ * else 128 x 128 x 64).  Built tilings: 64x64x32, 64x64x64, 128x128x32,
+ * 128x128x64, 128x64x32, 64x128x32; for FP32/BF16 also 256x128x32,
+ * 128x256x32, 256x256x32; for BF16 also 256x256x64, 256x128x64; for BF16X3
+ * also 256x256x32, 256x128x32; others return LPX_ERR_UNSUPPORTED.  BF16 /
+ * BF16X3 at 128x128x64 and at the 256-row tilings (with K > 0) first split
+ * both operands once into K-contiguous bf16 planes (B transposed) in
+ * stream-ordered workspace (allocated on `stream` from the library's own
+ * memory pool, freed the same way), then stream the planes into LDS with
+ * direct global-to-LDS loads; the other tilings convert the FP32 operands
+ * slab by slab.  C is overwritten (no alpha/beta).  rec = NULL means FP32
+ * with the default tiling.  Errors as for lpx_contract. */
 lpx_status lpx_gemm(const lpx_gemm_desc* g, const lpx_record* rec, void* stream);
 
 /* Every pre-launch check of lpx_gemm, without any HIP call. */

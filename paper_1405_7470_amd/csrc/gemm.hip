@@ -253,12 +253,15 @@ GemmFn pick(int tm, int tn, int tk, int* lds) {
 
 }  // namespace gemm
 
+bool gemm_split_tiling(int precision, int tm, int tn, int tk);
+
 lpx_status gemm_tiles(const lpx_record& r, int* tm, int* tn, int* tk) {
     // default: 128 x 128 x 64 for the reduced precisions (the pre-split
     // path), 128 x 128 x 32 for fp32
     *tm = r.gemm_tm ? r.gemm_tm : 128;
     *tn = r.gemm_tn ? r.gemm_tn : 128;
     *tk = r.gemm_tk ? r.gemm_tk : (r.precision == LPX_FP32 ? 32 : 64);
+    if (gemm_split_tiling(r.precision, *tm, *tn, *tk)) return LPX_OK;
     int lds = 0;
     void* fn = nullptr;
     switch (r.precision) {
@@ -270,21 +273,31 @@ lpx_status gemm_tiles(const lpx_record& r, int* tm, int* tn, int* tk) {
         return set_error(LPX_ERR_UNSUPPORTED,
                          "GEMM tile %dx%dx%d is not built for this precision (built: 64x64x32, "
                          "64x64x64, 128x128x32, 128x128x64, 128x64x32, 64x128x32; fp32/bf16 also "
-                         "256x128x32, 128x256x32, 256x256x32)",
+                         "256x128x32, 128x256x32, 256x256x32; bf16 256x256x64, 256x128x64; "
+                         "bf16x3 256x256x32, 256x128x32 (pre-split))",
                          *tm, *tn, *tk);
     return LPX_OK;
 }
 
-lpx_status launch_gemm_split(const lpx_gemm_desc& d, int precision, void* stream);
+lpx_status launch_gemm_split(const lpx_gemm_desc& d, int precision, int tm, int tn, int tk,
+                             void* stream);
 
 lpx_status launch_gemm(const lpx_gemm_desc& d, const lpx_record& r, void* stream) {
     int tm, tn, tk, lds = 0;
     lpx_status s = gemm_tiles(r, &tm, &tn, &tk);
     if (s != LPX_OK) return s;
-    // bf16 / bf16x3 at 128 x 128 x 64: operands split once into bf16 planes,
-    // then the direct-to-LDS kernel (nothing to split when K == 0)
-    if (r.precision != LPX_FP32 && tm == 128 && tn == 128 && tk == 64 && d.K > 0)
-        return launch_gemm_split(d, r.precision, stream);
+    // bf16x3 default: 256 x 256 x 32 once C has a 256 x 256 tile per compute
+    // unit (three MFMAs per product keep the single wave per SIMD busy; below
+    // that the 128 x 128 tiles fill the chip better)
+    if (r.precision == LPX_BF16X3 && !r.gemm_tm && !r.gemm_tn && !r.gemm_tk &&
+        ceil_div(d.M, 256) * ceil_div(d.N, 256) >= 256)
+        tm = 256, tn = 256, tk = 32;
+    // bf16 / bf16x3 at 128 x 128 x 64 and the 256-row tilings: operands split
+    // once into bf16 planes, then the direct-to-LDS kernel (nothing to split
+    // when K == 0: the general kernel writes the zeros)
+    const bool split = gemm_split_tiling(r.precision, tm, tn, tk);
+    if (split && d.K > 0) return launch_gemm_split(d, r.precision, tm, tn, tk, stream);
+    if (split) tm = 128, tn = 128, tk = 64;
     gemm::GemmFn fn = nullptr;
     switch (r.precision) {
         case LPX_FP32: fn = gemm::pick<LPX_FP32>(tm, tn, tk, &lds); break;

@@ -233,7 +233,12 @@ def test_gemm_validate():
         for tiles in ((64, 64, 32), (128, 128, 64), (128, 64, 32)):
             assert lpx.gemm_validate(gdesc(), lpx.record(prec, gemm=tiles)) == lpx.OK
     assert lpx.gemm_validate(gdesc(), lpx.record("fp32", gemm=(256, 256, 32))) == lpx.OK
-    assert lpx.gemm_validate(gdesc(), lpx.record("bf16x3", gemm=(256, 256, 32))) == lpx.ERR_UNSUPPORTED
+    for prec, tiles in (("bf16", (256, 256, 64)), ("bf16", (256, 128, 64)),
+                        ("bf16x3", (256, 256, 32)), ("bf16x3", (256, 128, 32))):  # pre-split
+        assert lpx.gemm_validate(gdesc(), lpx.record(prec, gemm=tiles)) == lpx.OK
+    for prec, tiles in (("bf16x3", (128, 256, 32)), ("bf16x3", (256, 256, 64)),
+                        ("fp32", (256, 256, 64)), ("bf16", (256, 128, 128))):
+        assert lpx.gemm_validate(gdesc(), lpx.record(prec, gemm=tiles)) == lpx.ERR_UNSUPPORTED
     assert lpx.gemm_validate(gdesc(), lpx.record("fp32", gemm=(96, 64, 32))) == lpx.ERR_UNSUPPORTED
     assert lpx.gemm_validate(gdesc(M=-1)) == lpx.ERR_INVALID_ARG
     assert lpx.gemm_validate(gdesc(lda=100)) == lpx.ERR_INVALID_ARG   # below K

@@ -1,7 +1,8 @@
 """GEMM (the contraction's degenerate case) through lpx_gemm vs the FP64
 oracle: every built tiling and precision on ragged shapes, exact integer
-inputs, identity, and at 4096^3 and 8192 x 1024 x 4096 a NaN sentinel over
-all of C plus one row of every m-tile and a column stripe of every n-tile."""
+inputs, identity, K = 0, and at 4096^3 and 8192 x 1024 x 4096 a NaN sentinel
+over all of C plus one row of every m-tile and a column stripe of every
+n-tile."""
 import numpy as np
 import pytest
 import torch
@@ -14,8 +15,13 @@ pytestmark = pytest.mark.gpu
 
 TILES = {"fp32": [(64, 64, 32), (64, 64, 64), (128, 128, 32), (128, 128, 64), (128, 64, 32),
                   (64, 128, 32), (256, 128, 32), (128, 256, 32), (256, 256, 32)],
-         "bf16": [(64, 64, 32), (128, 128, 32), (128, 128, 64), (256, 256, 32)],
-         "bf16x3": [(64, 64, 32), (64, 64, 64), (128, 128, 32), (128, 128, 64), (64, 128, 32)]}
+         "bf16": [(64, 64, 32), (128, 128, 32), (128, 128, 64), (256, 256, 32), (256, 256, 64),
+                  (256, 128, 64)],
+         "bf16x3": [(64, 64, 32), (64, 64, 64), (128, 128, 32), (128, 128, 64), (64, 128, 32),
+                    (256, 256, 32), (256, 128, 32)]}
+# tilings that run the pre-split kernel (operands split into bf16 planes first)
+PRESPLIT = {"bf16": [(128, 128, 64), (256, 256, 64), (256, 128, 64)],
+            "bf16x3": [(128, 128, 64), (256, 256, 32), (256, 128, 32)]}
 
 
 def check(C, A, B, precision, m0=0):
@@ -90,9 +96,10 @@ def test_gemm_full_size_every_tile(shape):
     Bc = np.ascontiguousarray(B[:, cols])
     refs = {prec: (oracle.gemm(Ar, B, prec), oracle.gemm(A, Bc, prec))
             for prec in ("fp32", "bf16", "bf16x3")}
-    for precision, tiles in (("fp32", (128, 128, 64)), ("bf16", (128, 128, 64)),
-                             ("bf16x3", (128, 128, 64)), ("fp32", (128, 128, 32)),
-                             ("bf16", (128, 128, 32)), ("bf16x3", (128, 128, 32))):
+    cases = [("fp32", (128, 128, 64)), ("fp32", (128, 128, 32)), ("bf16", (128, 128, 32)),
+             ("bf16x3", (128, 128, 32))]
+    cases += [(prec, t) for prec, tl in PRESPLIT.items() for t in tl]
+    for precision, tiles in cases:
         rec = lpx.record(precision, gemm=tiles)
         print(f"case: gemm full {shape} {lpx.describe(rec)}", flush=True)
         C = torch.full((M, N), float("nan"), device="cuda")
@@ -112,16 +119,32 @@ def test_gemm_full_size_every_tile(shape):
 
 @pytest.mark.parametrize("precision", ("bf16", "bf16x3"))
 def test_gemm_presplit_strided_and_default(precision):
-    """The pre-split path (the reduced precisions' default tiling) with row
-    strides that are not multiples of 4 and a ragged K, and the untouched
-    columns of C past N."""
-    A, B = inputs.gemm_inputs(130, 70, 45, seed=4)
-    Ab = torch.zeros((130, 47), device="cuda")
+    """The pre-split path (the reduced precisions' default tiling, and the
+    256-row tilings) with row strides that are not multiples of 4 and a
+    ragged K, and the untouched columns of C past N."""
+    A, B = inputs.gemm_inputs(300, 270, 45, seed=4)
+    Ab = torch.zeros((300, 47), device="cuda")
     Ab[:, :45] = to_dev(A)
-    Bb = torch.zeros((45, 73), device="cuda")
-    Bb[:, :70] = to_dev(B)
-    Cb = torch.full((130, 75), 7.0, device="cuda")
-    lpx.gemm(Ab[:, :45], Bb[:, :70], C=Cb[:, :70], record=lpx.record(precision))
-    torch.cuda.synchronize()
-    check(Cb[:, :70].double().cpu().numpy(), A, B, precision)
-    assert bool((Cb[:, 70:] == 7.0).all())
+    Bb = torch.zeros((45, 273), device="cuda")
+    Bb[:, :270] = to_dev(B)
+    for tiles in [(0, 0, 0)] + PRESPLIT[precision]:
+        rec = lpx.record(precision, gemm=tiles)
+        print(f"case: gemm strided 300x270x45 {lpx.describe(rec)}", flush=True)
+        Cb = torch.full((300, 275), 7.0, device="cuda")
+        lpx.gemm(Ab[:, :45], Bb[:, :270], C=Cb[:, :270], record=rec)
+        torch.cuda.synchronize()
+        check(Cb[:, :270].double().cpu().numpy(), A, B, precision)
+        assert bool((Cb[:, 270:] == 7.0).all())
+
+
+@pytest.mark.parametrize("precision", ("bf16", "bf16x3"))
+def test_gemm_presplit_k_zero(precision):
+    """K = 0 with a pre-split tiling: nothing to split, C is all zeros (the
+    general kernel writes them)."""
+    A = torch.empty((300, 0), device="cuda")
+    B = torch.empty((0, 270), device="cuda")
+    for tiles in PRESPLIT[precision]:
+        C = torch.full((300, 270), 7.0, device="cuda")
+        lpx.gemm(A, B, C=C, record=lpx.record(precision, gemm=tiles))
+        torch.cuda.synchronize()
+        assert bool((C == 0).all()), tiles
