@@ -197,16 +197,23 @@ def write_counters(csv_path, bench_json, out, cmd, title):
                      " | ".join(f"{row.get(c, float('nan')):.4g}" for c in names) + " |\n")
 
 
-def write_kernel_counters(csv_path, out, cmd, title, pattern, top=30):
+def write_kernel_counters(csv_paths, out, cmds, title, pattern, top=40):
     """Per-dispatch counter averages of every kernel whose name matches
     `pattern` (the side workloads: GEMM, ragged batch, dG, lift, Coulomb),
-    with the MFMA utilisation when both SQ counters are present."""
-    table = counters(csv_path)
+    with the MFMA utilisation when both SQ counters are present.  Several
+    --pmc runs of the same command merge into one table (one column per
+    counter)."""
+    table = defaultdict(dict)
+    for path in csv_paths:
+        for k, row in counters(path).items():
+            table[k].update(row)
     rx = re.compile(pattern)
     names = sorted({c for k in table for c in table[k]})
     keys = [k for k in table if rx.search(k)][:top]
     with open(out, "w") as fh:
-        fh.write(f"# {title}\n\nCommand: `{cmd}`\n\n")
+        fh.write(f"# {title}\n\n")
+        for c in cmds:
+            fh.write(f"Command: `{c}`\n\n")
         fh.write("Per-dispatch averages (counters summed over the device; a kernel's average "
                  "mixes every shape it ran on in the command).  MFMA utilisation = "
                  "SQ_VALU_MFMA_BUSY_CYCLES / (4 SIMDs x SQ_BUSY_CU_CYCLES).\n\n")
@@ -277,9 +284,9 @@ def main():
     c.add_argument("--cmd", required=True)
     c.add_argument("--title", default="SQ counters of the contraction kernels")
     k = sub.add_parser("kernels")
-    k.add_argument("--csv", required=True)
+    k.add_argument("--csv", required=True, action="append", help="repeatable")
     k.add_argument("--out", required=True)
-    k.add_argument("--cmd", required=True)
+    k.add_argument("--cmd", required=True, action="append", help="one per --csv")
     k.add_argument("--pattern", default=".")
     k.add_argument("--title", default="Counters of the side-workload kernels")
     b = sub.add_parser("traffic")
