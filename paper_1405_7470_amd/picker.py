@@ -222,7 +222,15 @@ def main():
                     help="evaluate the existing model on the held-out shapes only")
     ap.add_argument("--summary", default=None,
                     help="also write a text summary of the evaluation to this file")
+    ap.add_argument("--summary-from", default=None,
+                    help="write --summary from the eval.json of an earlier evaluation "
+                         "(no GPU work)")
     args = ap.parse_args()
+    if args.summary_from:
+        d = json.load(open(args.summary_from))
+        args.out = os.path.dirname(args.summary_from)
+        write_summary(args.summary, d["summary"], d["per_shape"], args)
+        return
     os.makedirs(args.out, exist_ok=True)
     eval_shapes = inputs.picker_shapes(args.eval_shapes, seed=2)
     if args.eval_only:
@@ -262,7 +270,7 @@ def main():
 def write_summary(path, summary, res, args):
     """A short text record of a held-out evaluation: the summary figures,
     the regret distribution and the worst shapes."""
-    r = sorted((x["t_learned"] / x["t_best"], x) for x in res)
+    r = sorted(((x["t_learned"] / x["t_best"], x) for x in res), key=lambda p: p[0])
     q = np.quantile([v for v, _ in r], [0.5, 0.9, 0.99, 1.0])
     by = {}
     for v, x in r:
@@ -272,7 +280,9 @@ def write_summary(path, summary, res, args):
         "# Learned picker: regret on held-out shapes",
         "",
         f"Command: `python -m paper_1405_7470_amd.picker --eval-only --eval-shapes "
-        f"{args.eval_shapes} --summary {path}` (model `{os.path.relpath(args.model)}`).",
+        f"{args.eval_shapes} --out {args.out}` (model `{os.path.relpath(args.model)}`), "
+        f"then `python -m paper_1405_7470_amd.picker --summary-from "
+        f"{os.path.join(args.out, 'eval.json')} --summary {path}`.",
         "",
         f"Held-out shapes: {summary['shapes']} (seed 2: Np uniform in [8, 128], "
         "E = floor(2^U(10, 21)), layout and precision uniform, K = 3), each tuned "
