@@ -226,6 +226,7 @@ def extras(stream, learned_picker=None):
     t_graph = _event_time(lambda: bt.submit(stream=stream), 5, stream)
     torch.cuda.synchronize()
     batch_out = [o.clone() for (_, _, o, _) in items[:8]]
+    binfo = bt.info()
     bt.destroy()
     t_sep = _event_time(lambda: [lpx.contract(D, u, out=o, record=r, stream=stream)
                                  for (D, u, o, l), r in zip(items, recs)], 3, stream)
@@ -259,7 +260,8 @@ def extras(stream, learned_picker=None):
                     "separate_tflops": flop / t_sep / 1e12,
                     "captured_launches_tflops": flop / t_cap / 1e12 if t_cap else None,
                     "captured_equals_batch": same,
-                    "roofline_us": roof * 1e6, "graph_pct_roof": 100 * roof / t_graph}
+                    "roofline_us": roof * 1e6, "graph_pct_roof": 100 * roof / t_graph,
+                    "graph_kernels": binfo["kernels"], "graph_workgroups": binfo["grid"]}
     return res, samples
 
 

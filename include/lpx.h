@@ -418,42 +418,42 @@ lpx_status lpx_split_bf16(const float* x, uint16_t* hi, uint16_t* lo,
                           int64_t n, void* stream);
 
 /* ------------------------------------------------------- ragged batch */
-/* Many contractions of uneven sizes in one persistent launch, captured
- * once into a HIP graph and replayed.  Opaque, library-owned handle. */
+/* Many contractions of uneven sizes in one HIP graph (one persistent
+ * launch per kernel the records select), captured once and replayed.
+ * Opaque, library-owned handle. */
 typedef struct lpx_batch lpx_batch;
 
 /* items[0..n-1]: contraction descriptors (validated as by lpx_contract; no
- * zero sizes); all must share one layout.  recs: one record per item (all
- * of one precision), or NULL to take each item's FP32 winner from the
- * tuning cache, else the FP32 default.  Each record is checked as
- * lpx_contract would check it, but the batch takes from it only the
- * precision and -- in the direct kernel below -- whether the instance keeps
- * D on chip (prefetch bit 0 or 2): its tile_e, unroll and other storage
- * bits are not used, because the batch runs one tile routine for all of
- * its instances, chosen for the whole set.
- *   *h == NULL: builds the batch -- instances ordered largest first (cost
- *     K*Np^2*E) and cut into element tiles -- captures the persistent
- *     launch into a graph, launches it on `stream`, and returns the handle
- *     in *h.  The tile routine: when its LDS rings fit (160 KiB), the
- *     staged pipeline of prefetch bits 1 and 3 on 32-element tiles dealt
- *     round-robin to the work-groups (u tiles and outputs staged in LDS,
- *     D read from global memory); otherwise 16-element tiles pulled from
- *     an atomic counter with u read from global memory and D staged in
- *     LDS when a record asks for it and it fits 48 KiB (the graph then
- *     holds [counter reset, kernel]).
+ * zero sizes).  recs: one record per item, or NULL to take each item's FP32
+ * winner from the tuning cache, else the FP32 default.  Every record is
+ * honoured: each instance is checked as lpx_contract would check it with
+ * its record (a record whose storage does not fit the instance fails the
+ * call, naming the instance) and runs that record's kernel, so instances
+ * may differ in precision, layout and every record field.
+ *   *h == NULL: builds the batch and launches it on `stream`, returning the
+ *     handle in *h.  Instances are grouped by the kernel their record
+ *     selects; each group is one persistent launch of that kernel's batch
+ *     form, which runs the contraction's own tile code on runs of
+ *     consecutive element tiles of one instance at a time (D staged or
+ *     loaded again at the start of a run).  Each instance's tiles are cut
+ *     into runs of similar length, and the runs are dealt largest first to
+ *     the least-loaded work-group.  Records that read D from memory get its
+ *     MFMA-order arrangement from the graph's first nodes (into device
+ *     memory the batch owns).  The nodes are captured once into a HIP graph.
  *   *h != NULL: items must have the batch's n and per-item K, Np, E and
  *     layout (pointers may change); copies the updated descriptor table and
  *     replays the graph on `stream`.
- * Outputs are bit-identical to lpx_contract with the same precision (every
- * record of a precision sums each output in the same order).  The caller
- * keeps all buffers alive until `stream` passes the work. */
+ * Outputs are bit-identical to lpx_contract with the same records (and to
+ * any record of the same precision: every record of a precision sums each
+ * output in the same order).  The caller keeps all buffers alive until
+ * `stream` passes the work. */
 lpx_status lpx_batch_submit(const lpx_contract_desc* items, const lpx_record* recs,
                             int32_t n, lpx_batch** h, void* stream);
 
-/* Tiles in the batch, elements per tile (32 staged, 16 direct), persistent
- * grid size and dynamic LDS per work-group (any output pointer may be
- * NULL). */
-lpx_status lpx_batch_info(const lpx_batch* b, int64_t* total_tiles, int32_t* tile_e,
+/* Element tiles in the batch (each instance cut by its record's tile_e),
+ * kernels launched (one per group), work-groups over all launches and the
+ * largest dynamic LDS of a launch (any output pointer may be NULL). */
+lpx_status lpx_batch_info(const lpx_batch* b, int64_t* total_tiles, int32_t* kernels,
                           int32_t* grid, int64_t* lds_bytes);
 
 /* Frees the batch; the caller must first make sure no submitted replay is

@@ -1,244 +1,84 @@
-// Ragged batch of contractions in one persistent, graph-captured launch.
+// Ragged batch of contractions in one graph, each instance run by its own
+// record's kernel.
 //
-// Each instance i (its own K, Np, E, pointers) is cut into element tiles;
-// the tiles of all instances form one list, largest instances first
-// (longest-processing-time order, cost K*Np^2*E).
+// Instances are grouped by the kernel their record (and i-block bound)
+// selects; each group is one persistent launch of that kernel's batch-run
+// twin (contract_runs_kernel), which executes the contraction's own tile
+// code on runs of consecutive tiles of one instance at a time.  Every
+// instance's tiles are cut into runs of about the same length, and the runs
+// are dealt to the group's work-groups largest first, each to the
+// work-group with the least work so far (cost of a tile: its row blocks x
+// k-steps), so a work-group changes instance -- and stages or loads D again
+// -- only between runs.  Records that read D from memory get its MFMA-order
+// arrangement from the first graph nodes, into a buffer the batch owns.
 //
-// Staged kernel (the default): 32-element tiles dealt round-robin to the
-// persistent work-groups (work-group w takes tiles w, w + G, w + 2G, ...,
-// which spreads every instance over all of them).  Each work-group runs the
-// contraction's staged pipeline -- loader waves filling a four-slot LDS ring
-// of u tiles with direct global-to-LDS loads, eight compute waves (D
-// fragments from global memory, L2-resident), four store waves writing the
-// previous tile's staged output with contiguous stores -- and every wave
-// follows the instance table with its own cursor (tiles of a work-group
-// come in increasing order, so the cursor only moves forward).
-//
-// Direct kernel (when the staged rings do not fit in LDS): 16-element tiles
-// pulled in chunks from one atomic counter by four-wave work-groups that
-// read u straight from global memory, D staged in LDS when it fits.
-//
-// Both run the same per-block MFMA routine as lpx_contract, so every output
-// is bit-identical to a separate lpx_contract call of the same precision.
-// The kernel (after a one-thread counter reset for the direct kernel; no
-// memset node) is captured once into a HIP graph on a library-owned stream;
-// lpx_batch_submit replays it on the caller's stream after copying the
-// (possibly updated) descriptor table.
+// The nodes (arrangements, then one launch per group) are captured once
+// into a HIP graph on a library-owned stream; lpx_batch_submit replays it
+// on the caller's stream after copying the (possibly updated) descriptor
+// table.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
-#include <numeric>
+#include <functional>
+#include <map>
+#include <queue>
 #include <string>
+#include <utility>
 #include <vector>
 
-#include "contract_kernels.h"
+#include "contract_dispatch.h"
 
 namespace lpx {
 namespace batchk {
 
-constexpr int kThreadsB = 256;
-constexpr int kChunk = 8;                         // tiles per counter fetch (direct kernel)
-constexpr int64_t kLdsBudget = 48 * 1024;         // D staging budget per work-group (direct)
-constexpr int kTileS = 32;                        // staged kernel: elements per tile
-constexpr int kPfS = 10;                          // staged u tile + staged output, D global
-
-struct Item {
-    kern::ContractArgs a;
-    int64_t tile_begin;  // first global tile index of this instance
-    int d_lds;           // stage D in LDS for this instance
-    int pad;
-};
-
-struct BatchArgs {
-    const Item* __restrict__ items;
-    unsigned long long* counter;
-    int64_t total_tiles;
-    int n;
-    int ldu, ldo;  // staged kernel: u and output ring slot strides (floats)
-};
-
-__global__ void reset_counter(unsigned long long* c) { *c = 0ull; }
-
-template <int PREC, int LAYOUT, int NTMAX>
-__global__ __launch_bounds__(kThreadsB) void batch_kernel(BatchArgs b) {
-    extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ long long s_t0;
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // scalar: uniform per wave
-    int cur = -1;
-    for (;;) {
-        if (tid == 0) s_t0 = (long long)atomicAdd(b.counter, (unsigned long long)kChunk);
-        __syncthreads();
-        const long long tv = s_t0;  // the same value in every lane: make it scalar
-        const int64_t t0 = ((int64_t)__builtin_amdgcn_readfirstlane((int)(tv >> 32)) << 32) |
-                           (uint32_t)__builtin_amdgcn_readfirstlane((int)(tv & 0xffffffff));
-        __syncthreads();  // every thread has read s_t0 before it is rewritten
-        if (t0 >= b.total_tiles) break;  // uniform: all waves leave together
-        const int64_t t1 = t0 + kChunk < b.total_tiles ? t0 + kChunk : b.total_tiles;
-        for (int64_t t = t0; t < t1; ++t) {
-            int lo = 0, hi = b.n - 1;  // last instance with tile_begin <= t
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (b.items[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
-            }
-            const kern::ContractArgs a = b.items[lo].a;
-            const bool dl = b.items[lo].d_lds != 0;
-            if (lo != cur) {
-                cur = lo;
-                if (dl) {
-                    __syncthreads();  // the previous instance's D is no longer read
-                    kern::stage_d<PREC, kThreadsB>(a, lds, tid);
-                    __syncthreads();
-                }
-            }
-            const int64_t eb0 = (t - b.items[lo].tile_begin) * 16;
-            constexpr int CAP = kern::pmax_cap<NTMAX, 4>();
-            kern::with_pmax<CAP, 4, PREC == LPX_FP32 ? 2 : 0>(a.nrb, [&](auto pm) {
-                constexpr int P = decltype(pm)::value;
-                if (dl)
-                    kern::block_compute<PREC, LAYOUT, NTMAX, true, false, 16, 4, 2, false, true, P>(
-                        a, lds, nullptr, 0, eb0, wave, lane);
-                else  // D arranged in global memory
-                    kern::block_compute<PREC, LAYOUT, NTMAX, true, false, 16, 4, 2, false, true, P>(
-                        a, a.Darr, nullptr, 0, eb0, wave, lane);
-            });
-        }
-    }
-}
-
-// D of every instance in MFMA operand order, written to its slice of the
-// batch's arrangement buffer (the first node of the graph, so updated D
-// pointers are followed on every replay).
+// D of the listed instances in MFMA operand order, written to their slices
+// of the batch's arrangement buffer (a.Darr).
 template <int PREC>
-__global__ __launch_bounds__(kern::kArrangeThreads) void arrange_all(const Item* __restrict__ items,
-                                                                    int n) {
-    for (int i = blockIdx.y; i < n; i += gridDim.y) {
-        const kern::ContractArgs a = items[i].a;
+__global__ __launch_bounds__(kern::kArrangeThreads) void arrange_list(
+    const kern::ContractArgs* __restrict__ items, const int32_t* __restrict__ idx, int m) {
+    for (int i = blockIdx.y; i < m; i += gridDim.y) {
+        const kern::ContractArgs a = items[idx[i]];
         kern::stage_d<PREC, kern::kArrangeThreads * kern::kArrangeBlocks>(
             a, const_cast<unsigned char*>(a.Darr),
             blockIdx.x * kern::kArrangeThreads + threadIdx.x);
     }
 }
 
-// Instance of tile t, starting the search at instance `cur` (a wave's tiles
-// come in increasing order).
-__device__ __forceinline__ int advance(const Item* items, int n, int64_t t, int cur) {
-    while (cur + 1 < n && items[cur + 1].tile_begin <= t) ++cur;
-    return cur;
-}
-
-template <int NTMAX>
-using ShapeS = kern::Shape<kTileS, NTMAX, kPfS>;
-
-template <int PREC, int LAYOUT, int NTMAX>
-__global__ __launch_bounds__((ShapeS<NTMAX>::THREADS)) void batch_staged(BatchArgs b) {
-    using S = ShapeS<NTMAX>;
-    static_assert(S::BPW == 1, "one block per compute wave and tile");
-    extern __shared__ __align__(16) unsigned char lds[];
-    float* ring = reinterpret_cast<float*>(lds);
-    float* oring = ring + 4 * b.ldu;
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // scalar: uniform per wave
-    const int64_t t0 = blockIdx.x, g = gridDim.x;
-    const int64_t nmine = t0 < b.total_tiles ? (b.total_tiles - 1 - t0) / g + 1 : 0;
-    const int64_t niter = nmine + 1;  // store waves trail by one tile
-    struct Tile {
-        int inst, nvalid;
-        int64_t e0;
-    };
-    auto tile_at = [&](int64_t n, int& cur) {
-        const int64_t t = t0 + n * g;
-        cur = advance(b.items, b.n, t, cur);
-        const int64_t e0 = (t - b.items[cur].tile_begin) * kTileS;
-        const int64_t rest = b.items[cur].a.E - e0;
-        return Tile{cur, (int)(rest < kTileS ? rest : kTileS), e0};
-    };
-    int cur = 0;
-    if (wave >= S::NCW + S::NLW) {
-        const int sw = wave - S::NCW - S::NLW;
-        __syncthreads();
-        for (int64_t n = 0; n < niter; ++n) {
-            if (n >= 1) {
-                const Tile tt = tile_at(n - 1, cur);
-                kern::store_tile<LAYOUT, kTileS, S::NSW>(b.items[tt.inst].a,
-                                                         oring + ((n - 1) & 1) * b.ldo, tt.e0,
-                                                         tt.nvalid, sw, lane);
-            }
-            __syncthreads();
-        }
-    } else if (wave >= S::NCW) {
-        const int lw = wave - S::NCW;
-        kern::loader_loop<kern::Loader<kTileS, NTMAX, S::NLW>::PER_LANE>(
-            nmine, niter, [&](int64_t n) {
-                const Tile tt = tile_at(n, cur);
-                return kern::loader_issue<LAYOUT, kTileS, NTMAX, S::NLW>(
-                    b.items[tt.inst].a, ring + (n & 3) * b.ldu, tt.e0, tt.nvalid, lw, lane);
-            });
-    } else {
-        const int row0 = 16 * (wave / S::WPE), part = wave % S::WPE;
-        __syncthreads();
-        for (int64_t n = 0; n < niter; ++n) {
-            if (n < nmine) {
-                const Tile tt = tile_at(n, cur);
-                const kern::ContractArgs& a = b.items[tt.inst].a;
-                if (row0 < tt.nvalid) {
-                    // the instance's own row-block count: small instances in
-                    // a batch built for Np up to 16 * NTMAX run no duplicate
-                    // MFMA chains (every size for FP32)
-                    constexpr int CAP = kern::pmax_cap<NTMAX, S::WPE>();
-                    kern::with_pmax<CAP, S::WPE, PREC == LPX_FP32 ? 2 : 0>(a.nrb, [&](auto pm) {
-                        auto run = [&](auto mask) {
-                            // D from its arrangement in global memory
-                            kern::block_compute<PREC, LAYOUT, NTMAX, true, true, kTileS, S::WPE,
-                                                2, true, decltype(mask)::value,
-                                                decltype(pm)::value>(
-                                a, a.Darr, ring + (n & 3) * b.ldu, row0, tt.e0 + row0, part,
-                                lane, oring + (n & 1) * b.ldo);
-                        };
-                        if (PREC == LPX_FP32 && a.np_vec)  // uniform
-                            run(std::false_type());
-                        else
-                            run(std::true_type());
-                    });
-                }
-            }
-            __syncthreads();
-        }
+RunsFn select_runs(const ContractGeom& g) {
+    const bool em = g.layout == LPX_ELEMENT_MAJOR;
+    const int nt = g.ntmax, t = g.tile_e, pf = g.prefetch, un = g.unroll;
+    switch (g.prec) {
+        case LPX_FP32:
+            return em ? runs_instance<LPX_FP32, LPX_ELEMENT_MAJOR>(nt, t, pf, un)
+                      : runs_instance<LPX_FP32, LPX_DOF_MAJOR>(nt, t, pf, un);
+        case LPX_BF16:
+            return em ? runs_instance<LPX_BF16, LPX_ELEMENT_MAJOR>(nt, t, pf, un)
+                      : runs_instance<LPX_BF16, LPX_DOF_MAJOR>(nt, t, pf, un);
+        default:
+            return em ? runs_instance<LPX_BF16X3, LPX_ELEMENT_MAJOR>(nt, t, pf, un)
+                      : runs_instance<LPX_BF16X3, LPX_DOF_MAJOR>(nt, t, pf, un);
     }
 }
 
-using BatchFn = void (*)(BatchArgs);
+// One persistent launch: the instances whose records select kernel `fn`.
+struct Group {
+    RunsFn fn = nullptr;
+    int threads = 0;
+    int64_t lds = 0;       // largest dynamic LDS of its instances
+    int grid = 0;
+    int64_t run_off = 0;   // first entry in the batch's run table
+    int64_t wg_off = 0;    // first entry in the batch's work-group table
+    int64_t tiles = 0;
+    std::vector<int32_t> inst;
+};
 
-template <int PREC, bool STAGED, int LAYOUT, int NTMAX>
-BatchFn kernel_of() {
-    if constexpr (STAGED)
-        return &batch_staged<PREC, LAYOUT, NTMAX>;
-    else
-        return &batch_kernel<PREC, LAYOUT, NTMAX>;
-}
-
-template <int PREC, bool STAGED>
-BatchFn pick(int layout, int ntmax) {
-    if (layout == LPX_ELEMENT_MAJOR) {
-        if (ntmax == 2) return kernel_of<PREC, STAGED, LPX_ELEMENT_MAJOR, 2>();
-        if (ntmax == 4) return kernel_of<PREC, STAGED, LPX_ELEMENT_MAJOR, 4>();
-        return kernel_of<PREC, STAGED, LPX_ELEMENT_MAJOR, 8>();
-    }
-    if (ntmax == 2) return kernel_of<PREC, STAGED, LPX_DOF_MAJOR, 2>();
-    if (ntmax == 4) return kernel_of<PREC, STAGED, LPX_DOF_MAJOR, 4>();
-    return kernel_of<PREC, STAGED, LPX_DOF_MAJOR, 8>();
-}
-
-template <bool STAGED>
-BatchFn pick_any(int precision, int layout, int ntmax) {
-    return precision == LPX_FP32 ? pick<LPX_FP32, STAGED>(layout, ntmax)
-         : precision == LPX_BF16 ? pick<LPX_BF16, STAGED>(layout, ntmax)
-                                 : pick<LPX_BF16X3, STAGED>(layout, ntmax);
-}
+// Runs per work-group in a balanced group: enough to even out the tail,
+// few enough that a run is long against its start-up (pipeline fill, D).
+constexpr int kRunsPerWg = 3;
+constexpr int64_t kMinRunTiles = 4;
 
 }  // namespace batchk
-
 }  // namespace lpx
 
 using namespace lpx;
@@ -246,25 +86,23 @@ using namespace lpx::batchk;
 
 struct lpx_batch {
     int32_t n = 0;
-    int precision = 0, layout = 0, ntmax = 2;
-    std::vector<int32_t> K, Np;
+    std::vector<int32_t> K, Np, layout;
     std::vector<int64_t> E;
-    std::vector<int32_t> order;       // instance index of each table slot
-    Item* host_items = nullptr;       // pinned host copy of the table
-    Item* dev_items = nullptr;
-    unsigned long long* counter = nullptr;
-    unsigned char* darr = nullptr;    // every instance's D in MFMA operand order
-    std::vector<int64_t> darr_off;    // byte offset of each slot's arrangement
-    int64_t darr_bytes = 0;
-    int64_t total_tiles = 0, lds = 0;
-    int grid = 0;
-    bool staged = false;  // staged kernel (32-element tiles) or direct kernel (16)
-    int tile_e = 16;
-    int ldu = 0, ldo = 0;
+    std::vector<lpx_record> rec;
+    kern::ContractArgs* host_items = nullptr;  // pinned host copy of the table
+    kern::ContractArgs* dev_items = nullptr;
+    kern::Run* dev_runs = nullptr;
+    int32_t* dev_wg = nullptr;
+    int32_t* dev_idx = nullptr;      // instances to arrange, per precision
+    unsigned char* darr = nullptr;   // D arrangements of the records that read D from memory
+    std::vector<Group> groups;
+    int64_t arr_off[3] = {0, 0, 0}, arr_cnt[3] = {0, 0, 0};  // FP32, BF16, BF16X3 lists
+    int64_t total_tiles = 0, lds_max = 0;
+    int grid_total = 0;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipEvent_t copied = nullptr;      // the table copy of the last submit is done
+    hipEvent_t copied = nullptr;     // the table copy of the last submit is done
     int device = -1;
 };
 
@@ -281,185 +119,214 @@ void free_batch(lpx_batch* b) {
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->copied) (void)hipEventDestroy(b->copied);
     if (b->dev_items) (void)hipFree(b->dev_items);
-    if (b->counter) (void)hipFree(b->counter);
+    if (b->dev_runs) (void)hipFree(b->dev_runs);
+    if (b->dev_wg) (void)hipFree(b->dev_wg);
+    if (b->dev_idx) (void)hipFree(b->dev_idx);
     if (b->darr) (void)hipFree(b->darr);
     if (b->host_items) (void)hipHostFree(b->host_items);
     delete b;
 }
 
-// Fills the pinned table from the descriptors (shapes already validated).
-lpx_status fill_table(lpx_batch* b, const lpx_contract_desc* items, const lpx_record* recs) {
-    int64_t tile = 0;
-    b->lds = b->staged ? 4 * (int64_t)b->ldu * 4 + 2 * (int64_t)b->ldo * 4 : 0;
-    for (int32_t slot = 0; slot < b->n; ++slot) {
-        const int32_t i = b->order[slot];
-        const lpx_contract_desc& c = items[i];
-        lpx_record r = recs ? recs[i] : default_record(b->precision);
-        lpx_record r0 = r;
-        r0.prefetch = 0;  // geometry without LDS staging; the D bit is decided below
-        ContractGeom g;
-        lpx_status s = contract_geometry(c.K, c.Np, c.E, c.layout, r0, &g);
-        if (s != LPX_OK) return s;
-        Item& it = b->host_items[slot];
-        std::memset(&it, 0, sizeof it);
-        it.a.D = c.D;
-        it.a.u = c.u;
-        it.a.out = c.out;
-        it.a.E = c.E;
-        it.a.ntiles = ceil_div(c.E, b->tile_e);
-        it.a.K = c.K;
-        it.a.Np = c.Np;
-        it.a.nt = g.nt;
-        it.a.nrb = g.nrb;
-        it.a.np_div = make_divider(c.Np);
-        it.a.nsteps = g.nsteps;
-        it.a.ldu = g.ldu;
-        it.a.ldo = g.ldo;
-        it.a.np_vec = (c.Np % 4) == 0;
-        it.a.e_vec = (c.E % 4) == 0;
-        it.a.stream_out = (int64_t)c.K * c.E * c.Np * 4 >= ((int64_t)32 << 20);
-        it.tile_begin = tile;
-        const int64_t frag_bytes = b->precision == LPX_FP32 ? 4 : (b->precision == LPX_BF16 ? 16 : 32);
-        const int64_t dbytes = g.nfrag * frag_bytes;
-        b->darr_off.push_back(b->darr_bytes);
-        b->darr_bytes += round_up(dbytes, 256);
-        // direct kernel: D staged in LDS when the record keeps D on chip
-        // (LDS or registers); the staged kernel reads D from global memory
-        it.d_lds = !b->staged && (r.prefetch & 5) != 0 && dbytes <= kLdsBudget;
-        if (it.d_lds) b->lds = std::max(b->lds, dbytes);
-        tile += it.a.ntiles;
-    }
-    b->total_tiles = tile;
-    return LPX_OK;
+int prec_slot(int precision) {
+    return precision == LPX_FP32 ? 0 : (precision == LPX_BF16 ? 1 : 2);
 }
 
+// Every instance checked as lpx_contract checks it, with its own record.
 lpx_status check_items(const lpx_contract_desc* items, const lpx_record* recs, int32_t n,
-                       int* precision, int* layout, int* ntmax) {
+                       std::vector<ContractGeom>* geo) {
     if (!items || n <= 0) return set_error(LPX_ERR_INVALID_ARG, "need n > 0 descriptors");
-    *precision = recs ? recs[0].precision : LPX_FP32;
-    *layout = items[0].layout;
-    *ntmax = 2;
+    geo->resize(n);
     for (int32_t i = 0; i < n; ++i) {
-        // The batch stages D only when it fits its own budget, so the
-        // record is checked with LDS staging off.
-        lpx_record rr = recs ? recs[i] : default_record(LPX_FP32);
-        rr.prefetch = 0;
-        const lpx_record* r = &rr;
-        ContractGeom g;
-        lpx_status s = validate_contract(&items[i], r, &g);
+        if (items[i].K == 0 || items[i].Np == 0 || items[i].E == 0)
+            return set_error(LPX_ERR_INVALID_ARG, "instance %d has a zero size", i);
+        lpx_status s = validate_contract(&items[i], &recs[i], &(*geo)[i]);
         if (s != LPX_OK) {
             std::string why = last_error_text();  // set_error overwrites it
             return set_error(s, "instance %d: %s", i, why.c_str());
         }
-        if ((r ? r->precision : LPX_FP32) != *precision || items[i].layout != *layout)
-            return set_error(LPX_ERR_UNSUPPORTED,
-                             "instance %d: a batch needs one precision and one layout", i);
-        if (items[i].K == 0 || items[i].Np == 0 || items[i].E == 0)
-            return set_error(LPX_ERR_INVALID_ARG, "instance %d has a zero size", i);
-        *ntmax = std::max(*ntmax, g.ntmax);
     }
     return LPX_OK;
 }
 
+// Cuts the group's instances into runs and deals them to at most `gmax`
+// work-groups; appends to runs / wg_first (offsets recorded in the group).
+void plan_group(Group& G, const std::vector<ContractGeom>& geo, int gmax,
+                std::vector<kern::Run>* runs, std::vector<int32_t>* wg_first) {
+    int64_t T = 0;
+    for (int32_t i : G.inst) T += geo[i].ntiles;
+    G.tiles = T;
+    const int64_t len = std::max<int64_t>(kMinRunTiles, T / ((int64_t)gmax * kRunsPerWg));
+    struct Cut {
+        double cost;
+        kern::Run run;
+    };
+    std::vector<Cut> cuts;
+    for (int32_t i : G.inst) {
+        const int64_t nt = geo[i].ntiles;
+        const int64_t nr = (nt + len - 1) / len;
+        const double per_tile = (double)geo[i].nrb * geo[i].nsteps;
+        for (int64_t r = 0; r < nr; ++r) {
+            const int64_t first = nt * r / nr, last = nt * (r + 1) / nr;
+            cuts.push_back({per_tile * (double)(last - first),
+                            kern::Run{first, i, (int32_t)(last - first)}});
+        }
+    }
+    std::stable_sort(cuts.begin(), cuts.end(),
+                     [](const Cut& x, const Cut& y) { return x.cost > y.cost; });
+    const int grid = (int)std::min<int64_t>(gmax, (int64_t)cuts.size());
+    // least-loaded work-group first (ties: lowest index)
+    using Load = std::pair<double, int>;
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+    for (int w = 0; w < grid; ++w) heap.push({0.0, w});
+    std::vector<std::vector<kern::Run>> per(grid);
+    for (const Cut& c : cuts) {
+        const Load l = heap.top();
+        heap.pop();
+        per[l.second].push_back(c.run);
+        heap.push({l.first + c.cost, l.second});
+    }
+    G.grid = grid;
+    G.run_off = (int64_t)runs->size();
+    G.wg_off = (int64_t)wg_first->size();
+    int32_t q = 0;
+    for (int w = 0; w < grid; ++w) {
+        wg_first->push_back(q);
+        for (const kern::Run& r : per[w]) runs->push_back(r);
+        q += (int32_t)per[w].size();
+    }
+    wg_first->push_back(q);
+}
+
 lpx_status create(const lpx_contract_desc* items, const lpx_record* recs, int32_t n,
                   lpx_batch** out) {
-    int precision, layout, ntmax;
-    lpx_status s = check_items(items, recs, n, &precision, &layout, &ntmax);
+    std::vector<ContractGeom> geo;
+    lpx_status s = check_items(items, recs, n, &geo);
     if (s != LPX_OK) return s;
+    DeviceInfo dev;
+    if ((s = current_device_info(&dev)) != LPX_OK) return s;
     lpx_batch* b = new lpx_batch;
     b->n = n;
-    b->precision = precision;
-    b->layout = layout;
-    b->ntmax = ntmax;
+    b->device = dev.device;
     for (int32_t i = 0; i < n; ++i) {
         b->K.push_back(items[i].K);
         b->Np.push_back(items[i].Np);
         b->E.push_back(items[i].E);
+        b->layout.push_back(items[i].layout);
+        b->rec.push_back(recs[i]);
     }
-    // Staged kernel when its rings fit in LDS for every instance.
-    {
-        int64_t ldu = 0, ldo = 0;
-        lpx_record rs = default_record(precision);
-        rs.tile_e = kTileS;
-        rs.prefetch = kPfS;
-        bool fits = true;
-        for (int32_t i = 0; i < n && fits; ++i) {
-            ContractGeom g;
-            lpx_problem p{items[i].K, items[i].Np, items[i].E, layout, precision};
-            (void)p;
-            if (contract_geometry(items[i].K, items[i].Np, items[i].E, layout, rs, &g) != LPX_OK) {
-                fits = false;
-                break;
-            }
-            // the batch kernel is compiled for the batch's largest i-block
-            // count: its loader rounds set the u slot size
-            const ContractShape cs = contract_shape(kTileS, ntmax, kPfS);
-            const int64_t rounds = 256LL * cs.nlw * loader_per_lane(kTileS, ntmax, cs.nlw);
-            ldu = std::max({ldu, (int64_t)g.ldu, rounds});
-            ldo = std::max(ldo, (int64_t)g.ldo);
-        }
-        clear_error();
-        b->staged = fits && 4 * ldu * 4 + 2 * ldo * 4 <= kMaxLdsPerWorkgroup;
-        b->tile_e = b->staged ? kTileS : 16;
-        b->ldu = (int)ldu;
-        b->ldo = (int)ldo;
-    }
-    b->order.resize(n);
-    std::iota(b->order.begin(), b->order.end(), 0);
-    std::stable_sort(b->order.begin(), b->order.end(), [&](int32_t x, int32_t y) {
-        auto cost = [&](int32_t i) { return (double)items[i].K * items[i].Np * items[i].Np * items[i].E; };
-        return cost(x) > cost(y);
-    });
-    hipError_t e = hipGetDevice(&b->device);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&b->host_items, sizeof(Item) * n, hipHostMallocDefault);
+    hipError_t e =
+        hipHostMalloc((void**)&b->host_items, sizeof(kern::ContractArgs) * n, hipHostMallocDefault);
     if (e != hipSuccess) { free_batch(b); return hip_err(e, "batch host table"); }
-    if ((s = fill_table(b, items, recs)) != LPX_OK) { free_batch(b); return s; }
-    if ((e = hipMalloc((void**)&b->dev_items, sizeof(Item) * n)) != hipSuccess ||
-        (e = hipMalloc((void**)&b->darr, (size_t)b->darr_bytes)) != hipSuccess ||
-        (e = hipMalloc((void**)&b->counter, sizeof(unsigned long long))) != hipSuccess ||
+
+    // kernel per instance, groups, arrangement lists
+    std::map<const void*, int> group_of;
+    std::vector<int32_t> arr[3];
+    std::vector<int64_t> darr_off(n, -1);
+    int64_t darr_total = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const ContractGeom& g = geo[i];
+        if (g.lds_bytes > dev.max_lds_per_block) {
+            free_batch(b);
+            return set_error(LPX_ERR_UNSUPPORTED, "instance %d needs %lld bytes of LDS", i,
+                             (long long)g.lds_bytes);
+        }
+        RunsFn fn = select_runs(g);
+        if (!fn) {
+            free_batch(b);
+            return set_error(LPX_ERR_INTERNAL, "instance %d: no kernel for a validated record", i);
+        }
+        auto it = group_of.find(reinterpret_cast<const void*>(fn));
+        if (it == group_of.end()) {
+            it = group_of.emplace(reinterpret_cast<const void*>(fn), (int)b->groups.size()).first;
+            Group G;
+            G.fn = fn;
+            G.threads = g.threads;
+            b->groups.push_back(G);
+        }
+        Group& G = b->groups[it->second];
+        G.inst.push_back(i);
+        G.lds = std::max(G.lds, g.lds_bytes);
+        b->host_items[i] = contract_args(items[i], g);
+        const int64_t db = darr_bytes(g);
+        if (db > 0) {
+            darr_off[i] = darr_total;
+            darr_total += round_up(db, 256);
+            arr[prec_slot(g.prec)].push_back(i);
+        }
+    }
+    std::vector<kern::Run> runs;
+    std::vector<int32_t> wg_first;
+    for (Group& G : b->groups) {
+        int nb = 0;
+        s = blocks_per_cu(reinterpret_cast<const void*>(G.fn), G.threads, G.lds, dev.device, &nb);
+        if (s == LPX_OK && nb <= 0)
+            s = set_error(LPX_ERR_UNSUPPORTED, "batch kernel cannot be resident (LDS %lld bytes)",
+                          (long long)G.lds);
+        if (s != LPX_OK) { free_batch(b); return s; }
+        plan_group(G, geo, nb * dev.num_cu, &runs, &wg_first);
+        b->total_tiles += G.tiles;
+        b->grid_total += G.grid;
+        b->lds_max = std::max(b->lds_max, G.lds);
+    }
+    std::vector<int32_t> idx;
+    for (int p = 0; p < 3; ++p) {
+        b->arr_off[p] = (int64_t)idx.size();
+        b->arr_cnt[p] = (int64_t)arr[p].size();
+        idx.insert(idx.end(), arr[p].begin(), arr[p].end());
+    }
+    if ((e = hipMalloc((void**)&b->dev_items, sizeof(kern::ContractArgs) * n)) != hipSuccess ||
+        (e = hipMalloc((void**)&b->dev_runs, sizeof(kern::Run) * runs.size())) != hipSuccess ||
+        (e = hipMalloc((void**)&b->dev_wg, sizeof(int32_t) * wg_first.size())) != hipSuccess ||
+        (!idx.empty() &&
+         (e = hipMalloc((void**)&b->dev_idx, sizeof(int32_t) * idx.size())) != hipSuccess) ||
+        (darr_total > 0 && (e = hipMalloc((void**)&b->darr, (size_t)darr_total)) != hipSuccess) ||
         (e = hipEventCreateWithFlags(&b->copied, hipEventDisableTiming)) != hipSuccess ||
         (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
         free_batch(b);
         return hip_err(e, "batch allocation");
     }
-    BatchFn fn = b->staged ? pick_any<true>(precision, layout, ntmax)
-                           : pick_any<false>(precision, layout, ntmax);
-    const int threads = b->staged ? contract_shape(kTileS, ntmax, kPfS).threads : kThreadsB;
-    DeviceInfo dev;
-    if ((s = current_device_info(&dev)) != LPX_OK) { free_batch(b); return s; }
-    if (b->lds > 64 * 1024) {
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds);
-        if (e != hipSuccess) { free_batch(b); return hip_err(e, "batch LDS attribute"); }
+    for (int32_t i = 0; i < n; ++i)
+        if (darr_off[i] >= 0) b->host_items[i].Darr = b->darr + darr_off[i];
+    // the run, work-group and arrangement tables never change: copied once
+    if ((e = hipMemcpy(b->dev_runs, runs.data(), sizeof(kern::Run) * runs.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(b->dev_wg, wg_first.data(), sizeof(int32_t) * wg_first.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
+        (!idx.empty() && (e = hipMemcpy(b->dev_idx, idx.data(), sizeof(int32_t) * idx.size(),
+                                        hipMemcpyHostToDevice)) != hipSuccess)) {
+        free_batch(b);
+        return hip_err(e, "batch tables");
     }
-    int nb = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(fn),
-                                                     threads, (size_t)b->lds);
-    if (e != hipSuccess) { free_batch(b); return hip_err(e, "batch occupancy"); }
-    if (nb <= 0) { free_batch(b); return set_error(LPX_ERR_UNSUPPORTED, "batch kernel cannot be resident"); }
-    int64_t grid = (int64_t)nb * dev.num_cu;
-    const int64_t need = b->staged ? b->total_tiles : ceil_div(b->total_tiles, kChunk);
-    b->grid = (int)std::max<int64_t>(1, std::min(grid, need));
 
-    for (int32_t slot = 0; slot < n; ++slot) b->host_items[slot].a.Darr = b->darr + b->darr_off[slot];
-
-    // Capture the launches once: the D arrangement, then the direct kernel
-    // after its counter reset or the staged kernel.
-    BatchArgs args{b->dev_items, b->counter, b->total_tiles, n, b->ldu, b->ldo};
+    // Capture once: the arrangements, then one launch per group.
     e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        const dim3 ag(kern::kArrangeBlocks, (unsigned)std::min(n, 65535)), ab(kern::kArrangeThreads);
-        if (precision == LPX_FP32)
-            hipLaunchKernelGGL(arrange_all<LPX_FP32>, ag, ab, 0, b->cap_stream, b->dev_items, n);
-        else if (precision == LPX_BF16)
-            hipLaunchKernelGGL(arrange_all<LPX_BF16>, ag, ab, 0, b->cap_stream, b->dev_items, n);
-        else
-            hipLaunchKernelGGL(arrange_all<LPX_BF16X3>, ag, ab, 0, b->cap_stream, b->dev_items, n);
-        if (!b->staged)
-            hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, b->cap_stream, b->counter);
-        void* kargs[] = {&args};
-        hipError_t le = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3(b->grid),
-                                        dim3(threads), kargs, (size_t)b->lds, b->cap_stream);
+        hipError_t le = hipSuccess;
+        for (int p = 0; p < 3; ++p) {
+            const int m = (int)b->arr_cnt[p];
+            if (m == 0) continue;
+            const dim3 ag(kern::kArrangeBlocks, (unsigned)std::min(m, 65535)),
+                ab(kern::kArrangeThreads);
+            const int32_t* list = b->dev_idx + b->arr_off[p];
+            if (p == 0)
+                hipLaunchKernelGGL(arrange_list<LPX_FP32>, ag, ab, 0, b->cap_stream, b->dev_items,
+                                   list, m);
+            else if (p == 1)
+                hipLaunchKernelGGL(arrange_list<LPX_BF16>, ag, ab, 0, b->cap_stream, b->dev_items,
+                                   list, m);
+            else
+                hipLaunchKernelGGL(arrange_list<LPX_BF16X3>, ag, ab, 0, b->cap_stream,
+                                   b->dev_items, list, m);
+            if (le == hipSuccess) le = hipGetLastError();
+        }
+        for (const Group& G : b->groups) {
+            kern::RunArgs ra{b->dev_items, b->dev_runs + G.run_off, b->dev_wg + G.wg_off};
+            void* kargs[] = {&ra};
+            const hipError_t ge =
+                hipLaunchKernel(reinterpret_cast<const void*>(G.fn), dim3((unsigned)G.grid),
+                                dim3(G.threads), kargs, (size_t)G.lds, b->cap_stream);
+            if (le == hipSuccess) le = ge;
+        }
         e = hipStreamEndCapture(b->cap_stream, &b->graph);
         if (e == hipSuccess && le != hipSuccess) e = le;
     }
@@ -471,7 +338,7 @@ lpx_status create(const lpx_contract_desc* items, const lpx_record* recs, int32_
 
 lpx_status replay(lpx_batch* b, void* stream) {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    hipError_t e = hipMemcpyAsync(b->dev_items, b->host_items, sizeof(Item) * b->n,
+    hipError_t e = hipMemcpyAsync(b->dev_items, b->host_items, sizeof(kern::ContractArgs) * b->n,
                                   hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipEventRecord(b->copied, st);
     if (e == hipSuccess) e = hipGraphLaunch(b->exec, st);
@@ -513,11 +380,10 @@ lpx_status lpx_batch_submit(const lpx_contract_desc* items, const lpx_record* re
             return set_error(LPX_ERR_INVALID_ARG, "update needs the batch's %d descriptors", b->n);
         for (int32_t i = 0; i < n; ++i) {
             if (items[i].K != b->K[i] || items[i].Np != b->Np[i] || items[i].E != b->E[i] ||
-                items[i].layout != b->layout)
+                items[i].layout != b->layout[i])
                 return set_error(LPX_ERR_INVALID_ARG, "instance %d changed shape; create a new batch", i);
-            lpx_record r = default_record(b->precision);
             ContractGeom g;
-            lpx_status s = validate_contract(&items[i], &r, &g);
+            lpx_status s = validate_contract(&items[i], &b->rec[i], &g);
             if (s != LPX_OK) {
                 std::string why = last_error_text();
                 return set_error(s, "instance %d: %s", i, why.c_str());
@@ -526,11 +392,10 @@ lpx_status lpx_batch_submit(const lpx_contract_desc* items, const lpx_record* re
         // The previous table copy must have finished before it is rewritten.
         hipError_t e = hipEventSynchronize(b->copied);
         if (e != hipSuccess) return hip_err(e, "batch update");
-        for (int32_t slot = 0; slot < b->n; ++slot) {
-            const lpx_contract_desc& c = items[b->order[slot]];
-            b->host_items[slot].a.D = c.D;
-            b->host_items[slot].a.u = c.u;
-            b->host_items[slot].a.out = c.out;
+        for (int32_t i = 0; i < n; ++i) {
+            b->host_items[i].D = items[i].D;
+            b->host_items[i].u = items[i].u;
+            b->host_items[i].out = items[i].out;
         }
         return replay(b, stream);
     } catch (...) {
@@ -538,14 +403,14 @@ lpx_status lpx_batch_submit(const lpx_contract_desc* items, const lpx_record* re
     }
 }
 
-lpx_status lpx_batch_info(const lpx_batch* b, int64_t* total_tiles, int32_t* tile_e,
+lpx_status lpx_batch_info(const lpx_batch* b, int64_t* total_tiles, int32_t* kernels,
                           int32_t* grid, int64_t* lds_bytes) {
     clear_error();
     if (!b) return set_error(LPX_ERR_INVALID_ARG, "batch is NULL");
     if (total_tiles) *total_tiles = b->total_tiles;
-    if (tile_e) *tile_e = b->tile_e;
-    if (grid) *grid = b->grid;
-    if (lds_bytes) *lds_bytes = b->lds;
+    if (kernels) *kernels = (int32_t)b->groups.size();
+    if (grid) *grid = b->grid_total;
+    if (lds_bytes) *lds_bytes = b->lds_max;
     return LPX_OK;
 }
 

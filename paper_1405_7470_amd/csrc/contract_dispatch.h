@@ -7,50 +7,63 @@
 namespace lpx {
 
 using ContractFn = void (*)(kern::ContractArgs);
+using RunsFn = void (*)(kern::RunArgs);
 
 namespace dispatch {
 
-template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PF, int UN>
-ContractFn fn() {
-    return &kern::contract_kernel<PREC, LAYOUT, NTMAX, TILE_E, PF, UN>;
-}
+// The two kernels built for every record: one contraction, and the runs of
+// a ragged batch.
+struct Single {
+    using Fn = ContractFn;
+    template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PF, int UN>
+    static Fn get() {
+        return &kern::contract_kernel<PREC, LAYOUT, NTMAX, TILE_E, PF, UN>;
+    }
+};
+struct Runs {
+    using Fn = RunsFn;
+    template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PF, int UN>
+    static Fn get() {
+        return &kern::contract_runs_kernel<PREC, LAYOUT, NTMAX, TILE_E, PF, UN>;
+    }
+};
 
-template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PF>
-ContractFn by_unroll(int un) {
+template <class M, int PREC, int LAYOUT, int NTMAX, int TILE_E, int PF>
+typename M::Fn by_unroll(int un) {
     switch (un) {
-        case 1: return fn<PREC, LAYOUT, NTMAX, TILE_E, PF, 1>();
-        case 2: return fn<PREC, LAYOUT, NTMAX, TILE_E, PF, 2>();
-        default: return fn<PREC, LAYOUT, NTMAX, TILE_E, PF, 4>();
+        case 1: return M::template get<PREC, LAYOUT, NTMAX, TILE_E, PF, 1>();
+        case 2: return M::template get<PREC, LAYOUT, NTMAX, TILE_E, PF, 2>();
+        default: return M::template get<PREC, LAYOUT, NTMAX, TILE_E, PF, 4>();
     }
 }
 
-template <int PREC, int LAYOUT, int NTMAX, int TILE_E>
-ContractFn by_prefetch(int pf, int un) {
+template <class M, int PREC, int LAYOUT, int NTMAX, int TILE_E>
+typename M::Fn by_prefetch(int pf, int un) {
     switch (pf) {
-        case 0: return by_unroll<PREC, LAYOUT, NTMAX, TILE_E, 0>(un);
-        case 1: return by_unroll<PREC, LAYOUT, NTMAX, TILE_E, 1>(un);
-        case 2: return by_unroll<PREC, LAYOUT, NTMAX, TILE_E, 2>(un);
-        case 3: return by_unroll<PREC, LAYOUT, NTMAX, TILE_E, 3>(un);
-        case 10: return by_unroll<PREC, LAYOUT, NTMAX, TILE_E, 10>(un);
-        case 11: return by_unroll<PREC, LAYOUT, NTMAX, TILE_E, 11>(un);
+        case 0: return by_unroll<M, PREC, LAYOUT, NTMAX, TILE_E, 0>(un);
+        case 1: return by_unroll<M, PREC, LAYOUT, NTMAX, TILE_E, 1>(un);
+        case 2: return by_unroll<M, PREC, LAYOUT, NTMAX, TILE_E, 2>(un);
+        case 3: return by_unroll<M, PREC, LAYOUT, NTMAX, TILE_E, 3>(un);
+        case 10: return by_unroll<M, PREC, LAYOUT, NTMAX, TILE_E, 10>(un);
+        case 11: return by_unroll<M, PREC, LAYOUT, NTMAX, TILE_E, 11>(un);
         default: break;
     }
     // D in registers: built only where the fragments fit (Np <= 64); the
     // unroll knob does not apply (fully unrolled).
     if constexpr (NTMAX <= 4) {
-        if (pf == 4) return fn<PREC, LAYOUT, NTMAX, TILE_E, 4, 1>();
-        if (pf == 6) return fn<PREC, LAYOUT, NTMAX, TILE_E, 6, 1>();
-        if (pf == 14) return fn<PREC, LAYOUT, NTMAX, TILE_E, 14, 1>();
+        if (pf == 4) return M::template get<PREC, LAYOUT, NTMAX, TILE_E, 4, 1>();
+        if (pf == 6) return M::template get<PREC, LAYOUT, NTMAX, TILE_E, 6, 1>();
+        if (pf == 14) return M::template get<PREC, LAYOUT, NTMAX, TILE_E, 14, 1>();
     }
     return nullptr;
 }
 
-template <int PREC, int LAYOUT, int NTMAX>
-ContractFn by_tile(int tile, int pf, int un) {
+template <class M, int PREC, int LAYOUT, int NTMAX>
+typename M::Fn by_tile(int tile, int pf, int un) {
     switch (tile) {
-        case 16: return by_prefetch<PREC, LAYOUT, NTMAX, 16>(pf, un);
-        case 32: return by_prefetch<PREC, LAYOUT, NTMAX, 32>(pf, un);
-        default: return by_prefetch<PREC, LAYOUT, NTMAX, 64>(pf, un);
+        case 16: return by_prefetch<M, PREC, LAYOUT, NTMAX, 16>(pf, un);
+        case 32: return by_prefetch<M, PREC, LAYOUT, NTMAX, 32>(pf, un);
+        default: return by_prefetch<M, PREC, LAYOUT, NTMAX, 64>(pf, un);
     }
 }
 
@@ -92,7 +105,14 @@ ContractFn dg_by_tile(int tile, int pf, int un) {
 // parallel; everywhere else these are extern.
 template <int PREC, int LAYOUT, int NTMAX>
 ContractFn contract_instances(int tile, int pf, int un) {
-    return dispatch::by_tile<PREC, LAYOUT, NTMAX>(tile, pf, un);
+    return dispatch::by_tile<dispatch::Single, PREC, LAYOUT, NTMAX>(tile, pf, un);
+}
+
+// The batch-run instances, compiled the same way by the units
+// contract_runs_<precision>_<layout>.hip.
+template <int PREC, int LAYOUT, int NTMAX>
+RunsFn runs_instances(int tile, int pf, int un) {
+    return dispatch::by_tile<dispatch::Runs, PREC, LAYOUT, NTMAX>(tile, pf, un);
 }
 
 // The dG volume instances, compiled the same way by the units
@@ -108,7 +128,10 @@ ContractFn dg_instances(int tile, int pf, int un) {
     extern template ContractFn contract_instances<P, L, 8>(int, int, int);    \
     extern template ContractFn dg_instances<P, L, 2>(int, int, int);          \
     extern template ContractFn dg_instances<P, L, 4>(int, int, int);          \
-    extern template ContractFn dg_instances<P, L, 8>(int, int, int);
+    extern template ContractFn dg_instances<P, L, 8>(int, int, int);          \
+    extern template RunsFn runs_instances<P, L, 2>(int, int, int);            \
+    extern template RunsFn runs_instances<P, L, 4>(int, int, int);            \
+    extern template RunsFn runs_instances<P, L, 8>(int, int, int);
 LPX_EXTERN_INSTANCES(LPX_FP32, LPX_ELEMENT_MAJOR)
 LPX_EXTERN_INSTANCES(LPX_FP32, LPX_DOF_MAJOR)
 LPX_EXTERN_INSTANCES(LPX_BF16, LPX_ELEMENT_MAJOR)
@@ -133,5 +156,23 @@ ContractFn contract_instance(int ntmax, int tile, int pf, int un, bool dg = fals
         default: return contract_instances<PREC, LAYOUT, 8>(tile, pf, un);
     }
 }
+
+// Batch-run instance of a record for a run-time bound.
+template <int PREC, int LAYOUT>
+RunsFn runs_instance(int ntmax, int tile, int pf, int un) {
+    switch (ntmax) {
+        case 2: return runs_instances<PREC, LAYOUT, 2>(tile, pf, un);
+        case 4: return runs_instances<PREC, LAYOUT, 4>(tile, pf, un);
+        default: return runs_instances<PREC, LAYOUT, 8>(tile, pf, un);
+    }
+}
+
+// Kernel arguments of one validated contraction (Darr and G left NULL).
+kern::ContractArgs contract_args(const lpx_contract_desc& c, const ContractGeom& g);
+
+// Resident work-groups per CU of kernel `fn` with `threads` threads and
+// `lds` bytes of dynamic LDS on `device` (cached; sets the kernel's LDS
+// limit attribute when above 64 KiB).
+lpx_status blocks_per_cu(const void* fn, int threads, int64_t lds, int device, int* out);
 
 }  // namespace lpx

@@ -1265,11 +1265,14 @@ struct Shape {
                          NSW = CS.nsw, THREADS = CS.threads;
 };
 
+// The work of one work-group on tiles t0 + n * g, n < nmine, of the
+// contraction `a`: the whole kernel (contract_kernel) or one run of a
+// batch (contract_runs_kernel).
 // EPI = 1: the dG volume term (needs PREFETCH bit 3): the tile's geometric
 // factors travel with its staged output and the store waves apply them.
-template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PREFETCH, int UNROLL, int EPI = 0>
-__global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void contract_kernel(
-    ContractArgs a) {
+template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PREFETCH, int UNROLL, int EPI>
+__device__ __forceinline__ void contract_tiles(const ContractArgs& a, int64_t t0, int64_t g,
+                                               int64_t nmine) {
     static_assert(EPI == 0 || (PREFETCH & 8), "the dG epilogue runs in the store waves");
     extern __shared__ __align__(16) unsigned char lds[];
     using S = Shape<TILE_E, NTMAX, PREFETCH>;
@@ -1300,16 +1303,16 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
         if constexpr (D_REG) {
             DRegs<PREC, NTMAX, S::WPE> d;
             load_dregs<PREC, NTMAX, S::WPE>(a, part, lane, d);
-            for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-                const int64_t e0 = tile * TILE_E;
+            for (int64_t n = 0; n < nmine; ++n) {
+                const int64_t e0 = (t0 + n * g) * TILE_E;
                 if (e0 + 16 * eblk >= a.E) continue;
                 block_compute_dreg<PREC, LAYOUT, NTMAX, false, TILE_E, S::WPE>(
                     a, d, nullptr, 0, e0 + 16 * eblk, part, lane);
             }
         } else {
             with_pmax<pmax_cap<NTMAX, S::WPE>(), S::WPE, pmax_mode<PREC, NTMAX>()>(a.nrb, [&](auto pm) {
-                for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-                    const int64_t e0 = tile * TILE_E;
+                for (int64_t n = 0; n < nmine; ++n) {
+                    const int64_t e0 = (t0 + n * g) * TILE_E;
                     if (e0 + 16 * eblk >= a.E) continue;  // uniform per wave; no barrier below
                     // D from LDS, or from its arrangement in global memory
                     block_compute<PREC, LAYOUT, NTMAX, true, false, TILE_E, S::WPE, UNROLL, false,
@@ -1319,7 +1322,7 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
             });
         }
     } else {
-        // The work-group's n-th tile is blockIdx.x + n * gridDim.x, n < nmine.
+        // The work-group's n-th tile is t0 + n * g, n < nmine.
         // Every wave runs `niter` iterations of one barrier each (one more
         // than nmine when store waves trail the compute waves by a tile):
         //   iteration n: loaders start tile n+3 into u slot (n+3)&3 and wait
@@ -1328,8 +1331,6 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
         //   slot (n-1)&1 to global memory.
         // Each slot is rewritten only in an iteration after the one that
         // read it, so the barrier ending each iteration orders every access.
-        const int64_t t0 = blockIdx.x, g = gridDim.x;
-        const int64_t nmine = t0 < a.ntiles ? (a.ntiles - 1 - t0) / g + 1 : 0;
         const int64_t niter = PF_O ? nmine + 1 : nmine;
         auto nvalid_of = [&](int64_t tile) {
             const int64_t rest = a.E - tile * TILE_E;
@@ -1475,6 +1476,46 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
                 });
             }
         }
+    }
+}
+
+// One contraction: work-group b takes tiles b, b + G, b + 2G, ... (G the
+// persistent grid).
+template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PREFETCH, int UNROLL, int EPI = 0>
+__global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void contract_kernel(
+    ContractArgs a) {
+    const int64_t t0 = blockIdx.x, g = gridDim.x;
+    const int64_t nmine = t0 < a.ntiles ? (a.ntiles - 1 - t0) / g + 1 : 0;
+    contract_tiles<PREC, LAYOUT, NTMAX, TILE_E, PREFETCH, UNROLL, EPI>(a, t0, g, nmine);
+}
+
+// A ragged batch: runs of consecutive tiles of one instance each, listed
+// per work-group (runs wg_first[b] .. wg_first[b + 1] - 1 for work-group b).
+struct Run {
+    int64_t first;  // first tile of the run
+    int32_t inst;   // index into `items`
+    int32_t count;  // tiles in the run
+};
+struct RunArgs {
+    const ContractArgs* __restrict__ items;
+    const Run* __restrict__ runs;
+    const int32_t* __restrict__ wg_first;
+};
+
+// Every instance of a launch runs the same record's code as a separate
+// contraction (its D staged or loaded again at the start of each run), so
+// its outputs are those of lpx_contract with that record.
+template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PREFETCH, int UNROLL>
+__global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void contract_runs_kernel(
+    RunArgs r) {
+    const int q0 = r.wg_first[blockIdx.x], q1 = r.wg_first[blockIdx.x + 1];
+    for (int q = q0; q < q1; ++q) {
+        // every wave is past its last LDS access of the previous run
+        if (q > q0) __syncthreads();
+        const Run run = r.runs[q];
+        const ContractArgs a = r.items[run.inst];
+        contract_tiles<PREC, LAYOUT, NTMAX, TILE_E, PREFETCH, UNROLL, 0>(a, run.first, 1,
+                                                                          run.count);
     }
 }
 

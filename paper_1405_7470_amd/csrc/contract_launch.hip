@@ -27,7 +27,8 @@ ContractFn select(const ContractGeom& g) {
     }
 }
 
-// Resident work-groups per CU for (kernel, dynamic LDS), cached per device.
+}  // namespace
+
 lpx_status blocks_per_cu(const void* fn, int threads, int64_t lds, int device, int* out) {
     static std::mutex mu;
     static std::map<std::pair<std::pair<const void*, int64_t>, int>, int> cache;
@@ -55,6 +56,8 @@ lpx_status blocks_per_cu(const void* fn, int threads, int64_t lds, int device, i
     *out = nb;
     return LPX_OK;
 }
+
+namespace {
 
 // Device scratch for lpx_contract_noalloc: D's MFMA-order arrangement of
 // records that read D from memory goes here instead of into a workspace
@@ -95,6 +98,30 @@ int64_t darr_bytes(const ContractGeom& g) {
     return g.nfrag * frag_bytes;
 }
 
+kern::ContractArgs contract_args(const lpx_contract_desc& c, const ContractGeom& g) {
+    kern::ContractArgs a;
+    a.D = c.D;
+    a.Darr = nullptr;
+    a.u = c.u;
+    a.out = c.out;
+    a.E = c.E;
+    a.ntiles = g.ntiles;
+    a.K = c.K;
+    a.Np = c.Np;
+    a.nt = g.nt;
+    a.nrb = g.nrb;
+    a.np_div = make_divider(c.Np);
+    a.nsteps = g.nsteps;
+    a.ldu = g.ldu;
+    a.ldo = g.ldo;
+    a.G = nullptr;
+    a.ldo_g = g.ldo_g;
+    a.np_vec = (c.Np % 4) == 0;
+    a.e_vec = (c.E % 4) == 0;
+    a.stream_out = (int64_t)c.K * c.E * c.Np * 4 >= ((int64_t)32 << 20);
+    return a;
+}
+
 lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g, void* stream,
                            bool noalloc, const float* G) {
     DeviceInfo dev;
@@ -114,26 +141,8 @@ lpx_status launch_contract(const lpx_contract_desc& c, const ContractGeom& g, vo
     int64_t grid = (int64_t)nb * dev.num_cu;
     if (grid > g.ntiles) grid = g.ntiles;
 
-    kern::ContractArgs a;
-    a.D = c.D;
-    a.Darr = nullptr;
-    a.u = c.u;
-    a.out = c.out;
-    a.E = c.E;
-    a.ntiles = g.ntiles;
-    a.K = c.K;
-    a.Np = c.Np;
-    a.nt = g.nt;
-    a.nrb = g.nrb;
-    a.np_div = make_divider(c.Np);
-    a.nsteps = g.nsteps;
-    a.ldu = g.ldu;
-    a.ldo = g.ldo;
+    kern::ContractArgs a = contract_args(c, g);
     a.G = G;
-    a.ldo_g = g.ldo_g;
-    a.np_vec = (c.Np % 4) == 0;
-    a.e_vec = (c.E % 4) == 0;
-    a.stream_out = (int64_t)c.K * c.E * c.Np * 4 >= ((int64_t)32 << 20);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     // Kernels that read D from memory read its MFMA-order arrangement,
     // written by a pre-pass into a stream-ordered workspace.

@@ -557,11 +557,12 @@ def gemm_validate(desc, rec=None) -> int:
 
 # ------------------------------------------------------------ ragged batch
 class Batch:
-    """A ragged batch of contractions replayed as one persistent graph launch.
+    """A ragged batch of contractions replayed as one graph: one persistent
+    launch per kernel the instances' records select.
 
     items: list of (D, u, out, layout) CUDA tensors; records: list of Record
-    (one precision) or None (tuning cache / default).  submit() replays,
-    optionally with new tensors of the same shapes."""
+    (one per item, each honoured) or None (tuning cache / default).
+    submit() replays, optionally with new tensors of the same shapes."""
 
     def __init__(self, items, records=None, stream=None):
         self.handle = ctypes.c_void_p(None)
@@ -590,7 +591,7 @@ class Batch:
         t, te, g, l = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
         _check(lib().lpx_batch_info(self.handle, ctypes.byref(t), ctypes.byref(te), ctypes.byref(g),
                                     ctypes.byref(l)))
-        return {"tiles": t.value, "tile_e": te.value, "grid": g.value, "lds_bytes": l.value}
+        return {"tiles": t.value, "kernels": te.value, "grid": g.value, "lds_bytes": l.value}
 
     def destroy(self):
         if self.handle:

@@ -1,6 +1,10 @@
-"""Ragged batch in one persistent graph launch: bit-identical to separate
-lpx_contract calls, within tolerance of the oracle, replayable with new
-buffers; plus sampled instances of the 512-instance workload."""
+"""Ragged batch as one graph of persistent launches (one per kernel the
+records select): bit-identical to separate lpx_contract calls with the same
+records, within tolerance of the oracle, replayable with new buffers; mixed
+precisions and layouts, runs that split a large instance over many
+work-groups, instances smaller than a tile, records rejected like
+lpx_contract rejects them; plus sampled instances of the 512-instance
+workload."""
 import numpy as np
 import pytest
 import torch
@@ -22,41 +26,90 @@ def make_items(shapes, seed, layout="em", K=3):
     return host, items
 
 
+def valid_records(items, rng, precisions, prefetches=(0, 1, 2, 3, 4, 6, 10, 11, 14)):
+    """A random record per item; where its storage does not fit the
+    instance, the same record with prefetch 0 (always valid)."""
+    recs = []
+    for (D, u, out, lay) in items:
+        K, Np = D.shape[0], D.shape[1]
+        E = u.shape[0] if lay == "em" else u.shape[1]
+        rec = lpx.record(str(rng.choice(precisions)), int(rng.choice([16, 32, 64])),
+                         int(rng.choice(prefetches)), int(rng.choice([1, 2, 4])))
+        if lpx.lds_bytes(K, Np, E, lay, rec)[0] != lpx.OK:
+            rec = lpx.record(lpx.describe(rec).split()[0], rec.tile_e, 0, rec.unroll)
+        recs.append(rec)
+    return recs
+
+
+def check_batch(items, recs, host, precisions):
+    for (D, u, out, lay), rec, (Dh, uh) in zip(items, recs, host):
+        ref = lpx.contract(D, u, layout=lay, record=rec)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), lpx.describe(rec)
+        uu = uh if lay == "em" else np.ascontiguousarray(uh.T)
+        check_against_oracle(Dh, uu, as_em(out, lay), lay, precisions[lpx.describe(rec).split()[0]])
+
+
 @pytest.mark.parametrize("precision", ("fp32", "bf16x3", "bf16"))
 @pytest.mark.parametrize("layout", ("em", "dm"))
 def test_batch_bitwise_equals_separate_calls(precision, layout):
     shapes = inputs.ragged_shapes(n=40, seed=7, lo=1, hi=3000)
     host, items = make_items(shapes, seed=3, layout=layout)
-    rng = np.random.default_rng(1)
-    recs = [lpx.record(precision, int(rng.choice([16, 32, 64])), int(rng.choice([0, 1, 2, 3, 4, 6])),
-                       int(rng.choice([1, 2, 4]))) for _ in shapes]
+    recs = valid_records(items, np.random.default_rng(1), [precision])
     print(f"case: batch {precision} {layout} n={len(shapes)}", flush=True)
     b = lpx.Batch(items, recs)
     torch.cuda.synchronize()
-    for (D, u, out, lay), rec, (Dh, uh) in zip(items, recs, host):
-        K, Np = D.shape[0], D.shape[1]
-        E = u.shape[0] if lay == "em" else u.shape[1]
-        if lpx.lds_bytes(K, Np, E, lay, rec)[0] != lpx.OK:
-            # this storage choice does not exist for the shape; any record
-            # of the same precision sums in the same order
-            rec = lpx.record(precision, rec.tile_e, 0, rec.unroll)
-        ref = lpx.contract(D, u, layout=lay, record=rec)
-        torch.cuda.synchronize()
-        assert torch.equal(out, ref), lpx.describe(rec)
-        uu = uh if lay == "em" else np.ascontiguousarray(uh.T)
-        check_against_oracle(Dh, uu, as_em(out, lay), lay, precision)
+    assert b.info()["tiles"] == sum(
+        (E + r.tile_e - 1) // r.tile_e for (_, E), r in zip(shapes, recs))
+    check_batch(items, recs, host, {precision: precision})
     b.destroy()
+
+
+def test_batch_mixed_precisions_layouts_and_records():
+    """One batch whose instances differ in precision, layout and record:
+    every instance runs its own record's kernel."""
+    shapes = inputs.ragged_shapes(n=36, seed=21, lo=1, hi=5000)
+    host_e, items_e = make_items(shapes[:18], seed=8, layout="em")
+    host_d, items_d = make_items(shapes[18:], seed=9, layout="dm")
+    host, items = host_e + host_d, items_e + items_d
+    precs = ["fp32", "bf16", "bf16x3"]
+    recs = valid_records(items, np.random.default_rng(5), precs)
+    print(f"case: batch mixed n={len(items)}", flush=True)
+    b = lpx.Batch(items, recs)
+    torch.cuda.synchronize()
+    assert b.info()["kernels"] > 3
+    check_batch(items, recs, host, {p: p for p in precs})
+    b.destroy()
+
+
+def test_batch_runs_split_large_and_tiny_instances():
+    """A large instance cut into many runs over the work-groups, beside
+    instances smaller than one tile."""
+    shapes = [(56, 300000), (20, 5), (120, 3), (35, 70001), (84, 17)]
+    host, items = make_items(shapes, seed=12)
+    for rec in (lpx.record("fp32", 64, 14, 1), lpx.record("fp32", 32, 10, 2),
+                lpx.record("bf16x3", 64, 6, 1), lpx.record("fp32", 16, 0, 4)):
+        recs = valid_records(items, np.random.default_rng(0), ["fp32"], prefetches=(0,))
+        recs[0] = rec  # the large instance (Np = 56) takes the record under test
+        print(f"case: batch runs {lpx.describe(rec)}", flush=True)
+        for (_, _, out, _) in items:
+            out.fill_(float("nan"))
+        b = lpx.Batch(items, recs)
+        torch.cuda.synchronize()
+        check_batch(items, recs, host, {"fp32": "fp32", "bf16x3": "bf16x3"})
+        b.destroy()
 
 
 def test_batch_replay_with_new_buffers_and_sentinel():
     shapes = inputs.ragged_shapes(n=25, seed=11, lo=10, hi=2000)
     host, items = make_items(shapes, seed=5)
-    b = lpx.Batch(items, None)
+    recs = [lpx.record("fp32", 32, 10, 1)] * len(shapes)
+    b = lpx.Batch(items, recs)
     torch.cuda.synchronize()
     info = b.info()
-    te = info["tile_e"]
-    assert te == 32  # element-major, K = 3, Np <= 120: the staged rings fit
-    assert info["tiles"] == sum((E + te - 1) // te for _, E in shapes)
+    # one record: one kernel per i-block bound present (Np up to 32, 64, 128)
+    assert info["kernels"] == len({2 if Np <= 32 else 4 if Np <= 64 else 8 for Np, _ in shapes})
+    assert info["tiles"] == sum((E + 31) // 32 for _, E in shapes)
     # new inputs and NaN-filled outputs, same shapes: replay the graph
     host2, items2 = make_items(shapes, seed=6)
     for (_, _, out, _) in items2:
@@ -71,12 +124,16 @@ def test_batch_replay_with_new_buffers_and_sentinel():
     b.destroy()
 
 
-def test_batch_rejects_mixed_precision_and_changed_shapes():
+def test_batch_rejects_unfit_records_and_changed_shapes():
+    # D of K = 6, Np = 120 (345,600 bytes) cannot be staged in LDS: rejected,
+    # as lpx_contract rejects it
+    _, items6 = make_items([(120, 100), (20, 50)], seed=1, K=6)
+    with pytest.raises(lpx.LpxError) as ei:
+        lpx.Batch(items6, [lpx.record("fp32", 16, 1, 1), lpx.record("fp32")])
+    assert ei.value.status == lpx.ERR_UNSUPPORTED
+    assert "instance 0" in str(ei.value)
     shapes = [(20, 100), (56, 50)]
     _, items = make_items(shapes, seed=1)
-    with pytest.raises(lpx.LpxError) as ei:
-        lpx.Batch(items, [lpx.record("fp32"), lpx.record("bf16")])
-    assert ei.value.status == lpx.ERR_UNSUPPORTED
     b = lpx.Batch(items, None)
     _, items_bad = make_items([(20, 100), (56, 51)], seed=1)
     with pytest.raises(lpx.LpxError) as ei:
@@ -105,21 +162,13 @@ def test_batch_512_instances_sampled():
     b.destroy()
 
 
-def test_direct_kernel_when_staged_rings_do_not_fit():
-    """K = 6 at Np = 120 needs 2 x 6 x 32 x 120 floats of output ring, more
-    than LDS holds with the u ring: the batch falls back to 16-element tiles
-    pulled from a counter, still bit-identical to separate calls."""
+def test_batch_six_operators():
+    """K = 6 (stacked rows up to 720 at Np = 120): every record that fits
+    each instance, bit-identical to separate calls."""
     shapes = [(120, 700), (56, 333), (10, 1500), (84, 65)]
     host, items = make_items(shapes, seed=9, K=6)
-    recs = [lpx.record("fp32", 32, 1, 2)] * len(shapes)
+    recs = valid_records(items, np.random.default_rng(3), ["fp32"])
     b = lpx.Batch(items, recs)
     torch.cuda.synchronize()
-    info = b.info()
-    assert info["tile_e"] == 16
-    assert info["tiles"] == sum((E + 15) // 16 for _, E in shapes)
-    for (D, u, out, lay), rec, (Dh, uh) in zip(items, recs, host):
-        ref = lpx.contract(D, u, layout=lay, record=lpx.record("fp32", 16, 0, 1))
-        torch.cuda.synchronize()
-        assert torch.equal(out, ref)
-        check_against_oracle(Dh, uh, as_em(out, lay), lay, "fp32")
+    check_batch(items, recs, host, {"fp32": "fp32"})
     b.destroy()
