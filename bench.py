@@ -252,6 +252,24 @@ def extras(stream, learned_picker=None):
         del graph
     except Exception as exc:  # a side measurement never hides the rest
         same = repr(exc)
+    # records tuned for the batch itself (lpx_batch_tune: each (K, Np)
+    # group timed as a batch with every candidate record)
+    t0 = time.perf_counter()
+    trecs = lpx.batch_tune(items, "fp32", warmup=1, reps=3, stream=stream)
+    tune_s = time.perf_counter() - t0
+    bt = lpx.Batch(items, trecs, stream=stream)
+    t_tuned = _event_time(lambda: bt.submit(stream=stream), 5, stream)
+    torch.cuda.synchronize()
+    tinfo = bt.info()
+    tuned_same = all(torch.equal(o, b) for (_, _, o, _), b in zip(items[:8], batch_out))
+    bt.destroy()
+    chosen = {}
+    for (D, _, _, _), r in zip(items, trecs):
+        chosen[str(D.shape[1])] = lpx.describe(r)
+    res["batch_tuned"] = {"graph_us": t_tuned * 1e6, "graph_tflops": flop / t_tuned / 1e12,
+                          "graph_pct_roof": 100 * roof / t_tuned, "tune_s": tune_s,
+                          "graph_kernels": tinfo["kernels"], "records_by_Np": chosen,
+                          "equals_learned_batch": tuned_same}
     res["batch"] = {"instances": len(shapes), "records": how, "gflop": flop / 1e9,
                     "gbytes": nbytes / 1e9,
                     "graph_us": t_graph * 1e6, "separate_us": t_sep * 1e6,

@@ -450,6 +450,20 @@ typedef struct lpx_batch lpx_batch;
 lpx_status lpx_batch_submit(const lpx_contract_desc* items, const lpx_record* recs,
                             int32_t n, lpx_batch** h, void* stream);
 
+/* Batch autotuner: the instances are grouped by (K, Np, layout); for each
+ * group every candidate record of `precision` (lpx_record_enumerate order)
+ * that fits all of the group's instances is timed on the group alone, as a
+ * batch built with that record for each of them -- `warmup` untimed
+ * replays, then `reps` replays bracketed by HIP events on `stream`, median
+ * kept -- and recs_out[i] (host array of n) receives the fastest record of
+ * instance i's group (ties: lowest index).  The records a batch needs
+ * differ from the ones separate calls need: in a batch the other instances
+ * fill the GPU, so a small instance no longer wants small tiles.  Blocks
+ * the calling thread; overwrites every out buffer; allocates and frees
+ * device memory per candidate. */
+lpx_status lpx_batch_tune(const lpx_contract_desc* items, int32_t n, int32_t precision,
+                          int32_t warmup, int32_t reps, void* stream, lpx_record* recs_out);
+
 /* Element tiles in the batch (each instance cut by its record's tile_e),
  * kernels launched (one per group), work-groups over all launches and the
  * largest dynamic LDS of a launch (any output pointer may be NULL). */

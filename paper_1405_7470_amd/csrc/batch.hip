@@ -19,11 +19,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <functional>
 #include <map>
 #include <queue>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -398,6 +400,96 @@ lpx_status lpx_batch_submit(const lpx_contract_desc* items, const lpx_record* re
             b->host_items[i].out = items[i].out;
         }
         return replay(b, stream);
+    } catch (...) {
+        return set_error(LPX_ERR_INTERNAL, "unexpected C++ exception");
+    }
+}
+
+lpx_status lpx_batch_tune(const lpx_contract_desc* items, int32_t n, int32_t precision,
+                          int32_t warmup, int32_t reps, void* stream, lpx_record* recs_out) {
+    clear_error();
+    try {
+        if (!items || n <= 0 || !recs_out)
+            return set_error(LPX_ERR_INVALID_ARG, "need n > 0 descriptors and an output array");
+        if (warmup < 0 || reps < 1) return set_error(LPX_ERR_INVALID_ARG, "bad warmup/reps");
+        if (precision < LPX_FP32 || precision > LPX_BF16X3)
+            return set_error(LPX_ERR_INVALID_ARG, "unknown precision %d", precision);
+        // groups of instances that share (K, Np, layout)
+        std::map<std::tuple<int, int, int>, std::vector<int32_t>> groups;
+        for (int32_t i = 0; i < n; ++i) {
+            if (items[i].K == 0 || items[i].Np == 0 || items[i].E == 0)
+                return set_error(LPX_ERR_INVALID_ARG, "instance %d has a zero size", i);
+            lpx_record def = default_record(precision);
+            ContractGeom g;
+            lpx_status s = validate_contract(&items[i], &def, &g);
+            if (s != LPX_OK) {
+                std::string why = last_error_text();
+                return set_error(s, "instance %d: %s", i, why.c_str());
+            }
+            groups[std::make_tuple(items[i].K, items[i].Np, items[i].layout)].push_back(i);
+        }
+        hipEvent_t ea = nullptr, eb = nullptr;
+        hipError_t e = hipEventCreate(&ea);
+        if (e == hipSuccess) e = hipEventCreate(&eb);
+        if (e != hipSuccess) {
+            if (ea) (void)hipEventDestroy(ea);
+            return hip_err(e, "hipEventCreate");
+        }
+        hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+        lpx_status status = LPX_OK;
+        std::vector<float> t(reps);
+        for (auto& kv : groups) {
+            const std::vector<int32_t>& idx = kv.second;
+            std::vector<lpx_contract_desc> sub;
+            for (int32_t i : idx) sub.push_back(items[i]);
+            lpx_problem p{items[idx[0]].K, items[idx[0]].Np, items[idx[0]].E,
+                          items[idx[0]].layout, precision};
+            lpx_record cand[LPX_MAX_RECORDS];
+            int32_t ncand = 0;
+            if ((status = lpx_record_enumerate(&p, cand, LPX_MAX_RECORDS, &ncand)) != LPX_OK) break;
+            float best_t = INFINITY;
+            lpx_record best = default_record(precision);
+            for (int32_t c = 0; c < ncand && status == LPX_OK; ++c) {
+                std::vector<lpx_record> rv(sub.size(), cand[c]);
+                bool fits = true;
+                for (const lpx_contract_desc& d : sub) {
+                    ContractGeom g;
+                    if (validate_contract(&d, &cand[c], &g) != LPX_OK) fits = false;
+                }
+                clear_error();
+                if (!fits) continue;
+                lpx_batch* b = nullptr;
+                if (create(sub.data(), rv.data(), (int32_t)sub.size(), &b) != LPX_OK) {
+                    clear_error();  // e.g. a kernel that cannot be resident
+                    continue;
+                }
+                for (int32_t w = 0; w < warmup && status == LPX_OK; ++w) status = replay(b, stream);
+                for (int32_t q = 0; q < reps && status == LPX_OK; ++q) {
+                    float ms = 0.f;
+                    if ((e = hipEventRecord(ea, st)) == hipSuccess &&
+                        (status = replay(b, stream)) == LPX_OK &&
+                        (e = hipEventRecord(eb, st)) == hipSuccess &&
+                        (e = hipEventSynchronize(eb)) == hipSuccess &&
+                        (e = hipEventElapsedTime(&ms, ea, eb)) == hipSuccess)
+                        t[q] = ms * 1000.f;
+                    if (e != hipSuccess && status == LPX_OK) status = hip_err(e, "batch timing");
+                }
+                if (status == LPX_OK && (e = hipStreamSynchronize(st)) != hipSuccess)
+                    status = hip_err(e, "batch timing");
+                free_batch(b);
+                if (status != LPX_OK) break;
+                std::sort(t.begin(), t.end());
+                if (t[reps / 2] < best_t) {
+                    best_t = t[reps / 2];
+                    best = cand[c];
+                }
+            }
+            if (status != LPX_OK) break;
+            for (int32_t i : idx) recs_out[i] = best;
+        }
+        (void)hipEventDestroy(ea);
+        (void)hipEventDestroy(eb);
+        return status;
     } catch (...) {
         return set_error(LPX_ERR_INTERNAL, "unexpected C++ exception");
     }

@@ -618,8 +618,8 @@ __global__ __launch_bounds__(kArrangeThreads) void arrange_d_kernel(ContractArgs
 // through without being kept in the caches).  Used where every store
 // instruction writes whole contiguous runs (the store waves' copy-out, 1 KiB
 // per instruction) and for the DOF-major direct stores; measured on MI355X at
-// K=3, Np=56, E=2^20: bf16x3 staged-output kernels 187 -> 148 us
-// (element-major) and 191 -> 152 us (DOF-major).  Element-major direct
+// K=3, Np=56, E=2^20, one launch timed alone: bf16x3 staged-output kernels
+// 187 -> 142-148 us (element-major) and 191 -> 152 us (DOF-major).  Element-major direct
 // stores (64-byte pieces of each element's run, completed in L2 by other
 // row blocks) stay ordinary stores: streaming them doubled the time.
 // The hint is applied only to outputs of at least 32 MiB (stream_out, set
@@ -719,9 +719,19 @@ __device__ __forceinline__ void stage_pairs(const ContractArgs& a, const f4 (&ac
 // Store wave sw (of NSW) copies the staged tile at element e0 (nvalid
 // valid elements) from slot `os` to `out`.  Store waves issue no global
 // loads, so nothing ever waits for their stores.
-template <int LAYOUT, int TILE_E, int NSW>
-__device__ __forceinline__ void store_tile(const ContractArgs& a, const float* os, int64_t e0,
-                                           int nvalid, int sw, int lane) {
+// 16-byte store, streaming (non-temporal) when NT: the store waves' loops
+// are compiled once per kind, so no store carries a branch on stream_out.
+template <bool NT>
+__device__ __forceinline__ void store_f4(float* p, const f4& v) {
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, reinterpret_cast<f4*>(p));
+    else
+        *reinterpret_cast<f4*>(p) = v;
+}
+
+template <int LAYOUT, int TILE_E, int NSW, bool NT>
+__device__ __forceinline__ void store_tile_as(const ContractArgs& a, const float* os, int64_t e0,
+                                              int nvalid, int sw, int lane) {
     constexpr int U = 4;  // chunks read from LDS before their stores
     constexpr int STRIDE = 64 * NSW;
     if constexpr (LAYOUT == LPX_ELEMENT_MAJOR) {
@@ -741,7 +751,7 @@ __device__ __forceinline__ void store_tile(const ContractArgs& a, const float* o
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
                         const int c = c0 + STRIDE * u;
-                        if (c < nch) store_stream(a, g + 4 * c, v[u]);
+                        if (c < nch) store_f4<NT>(g + 4 * c, v[u]);
                     }
                 }
             } else {
@@ -771,8 +781,7 @@ __device__ __forceinline__ void store_tile(const ContractArgs& a, const float* o
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    if (row + RSTEP * u < rows && colok)
-                        store_stream(a, dst + u * dstep, v[u]);
+                    if (row + RSTEP * u < rows && colok) store_f4<NT>(dst + u * dstep, v[u]);
                 }
                 dst += U * dstep;
             }
@@ -786,15 +795,25 @@ __device__ __forceinline__ void store_tile(const ContractArgs& a, const float* o
     }
 }
 
+// Copy-out of one staged output tile by the store waves.
+template <int LAYOUT, int TILE_E, int NSW>
+__device__ __forceinline__ void store_tile(const ContractArgs& a, const float* os, int64_t e0,
+                                           int nvalid, int sw, int lane) {
+    if (a.stream_out)  // uniform
+        store_tile_as<LAYOUT, TILE_E, NSW, true>(a, os, e0, nvalid, sw, lane);
+    else
+        store_tile_as<LAYOUT, TILE_E, NSW, false>(a, os, e0, nvalid, sw, lane);
+}
+
 // dG volume term, write-back of a staged tile: the slot holds the K
 // reference derivatives (layout of stage_pairs) and the tile's geometric
 // factors at gs (element-major: gs[r*K*K + d*K + k] for element e0 + r;
 // DOF-major: gs[(d*K + k)*TILE_E + r]); store wave sw writes
 // out[d] = sum_k G(e,d,k) * slot[k] (FP32, k increasing) for d < K.
-template <int LAYOUT, int TILE_E, int NSW>
-__device__ __forceinline__ void store_tile_dg(const ContractArgs& a, const float* os,
-                                              const float* gs, int64_t e0, int nvalid, int sw,
-                                              int lane) {
+template <int LAYOUT, int TILE_E, int NSW, bool NT>
+__device__ __forceinline__ void store_tile_dg_as(const ContractArgs& a, const float* os,
+                                                 const float* gs, int64_t e0, int nvalid, int sw,
+                                                 int lane) {
     constexpr int STRIDE = 64 * NSW;
     constexpr int KM = LPX_DG_MAX_K;
     const int K = a.K, KK = a.K * a.K;
@@ -839,7 +858,7 @@ __device__ __forceinline__ void store_tile_dg(const ContractArgs& a, const float
                                 for (int t = 0; t < 4; ++t)
                                     acc[t] = fmaf(gk[u][d][k], v[u][k][t], acc[t]);
                             }
-                        store_stream(a, a.out + ((int64_t)d * a.E + e0) * a.Np + 4 * c, acc);
+                        store_f4<NT>(a.out + ((int64_t)d * a.E + e0) * a.Np + 4 * c, acc);
                     }
                 }
             }
@@ -890,7 +909,7 @@ __device__ __forceinline__ void store_tile_dg(const ContractArgs& a, const float
                             for (int t = 0; t < 4; ++t) acc[t] = fmaf(gk[d][k][t], v[k][t], acc[t]);
                         }
                     if (colok)
-                        store_stream(a, a.out + (int64_t)(d * a.Np + i) * a.E + e0 + col, acc);
+                        store_f4<NT>(a.out + (int64_t)(d * a.Np + i) * a.E + e0 + col, acc);
                 }
             }
         } else {
@@ -908,6 +927,16 @@ __device__ __forceinline__ void store_tile_dg(const ContractArgs& a, const float
             }
         }
     }
+}
+
+template <int LAYOUT, int TILE_E, int NSW>
+__device__ __forceinline__ void store_tile_dg(const ContractArgs& a, const float* os,
+                                              const float* gs, int64_t e0, int nvalid, int sw,
+                                              int lane) {
+    if (a.stream_out)  // uniform
+        store_tile_dg_as<LAYOUT, TILE_E, NSW, true>(a, os, gs, e0, nvalid, sw, lane);
+    else
+        store_tile_dg_as<LAYOUT, TILE_E, NSW, false>(a, os, gs, e0, nvalid, sw, lane);
 }
 
 // dG volume term: the compute waves copy a tile's geometric factors into its

@@ -181,6 +181,9 @@ def lib():
         L.lpx_batch_submit.argtypes = [ctypes.POINTER(ContractDesc), ctypes.POINTER(Record),
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), vp]
         L.lpx_batch_submit.restype = st
+        L.lpx_batch_tune.argtypes = [ctypes.POINTER(ContractDesc), ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_int32, vp, ctypes.POINTER(Record)]
+        L.lpx_batch_tune.restype = st
         L.lpx_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
@@ -604,6 +607,19 @@ class Batch:
             self.destroy()
         except Exception:
             pass
+
+
+def batch_tune(items, precision="fp32", warmup=1, reps=5, stream=None):
+    """Records for a batch of (D, u, out, layout) items from timing each
+    (K, Np, layout) group as a batch (lpx_batch_tune); one Record per item.
+    Overwrites every out tensor."""
+    arr = (ContractDesc * len(items))()
+    for i, (D, u, out, layout) in enumerate(items):
+        arr[i] = make_desc(D, u, out, layout)
+    recs = (Record * len(items))()
+    _check(lib().lpx_batch_tune(arr, len(items), PRECISION[precision], warmup, reps,
+                                _stream_handle(stream), recs))
+    return list(recs)
 
 
 # ------------------------------------------------------------ cost model

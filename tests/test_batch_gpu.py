@@ -172,3 +172,18 @@ def test_batch_six_operators():
     torch.cuda.synchronize()
     check_batch(items, recs, host, {"fp32": "fp32"})
     b.destroy()
+
+
+def test_batch_tune_groups_and_bitwise():
+    """lpx_batch_tune: one record per (K, Np, layout) group, each valid for
+    all of its instances; the batch built with them matches separate calls."""
+    shapes = [(20, 900), (20, 3000), (56, 1200), (56, 40), (120, 700), (120, 2500)]
+    host, items = make_items(shapes, seed=4)
+    recs = lpx.batch_tune(items, "fp32", warmup=1, reps=3)
+    assert len(recs) == len(items)
+    for a, b in ((0, 1), (2, 3), (4, 5)):
+        assert lpx.describe(recs[a]) == lpx.describe(recs[b])
+    b = lpx.Batch(items, recs)
+    torch.cuda.synchronize()
+    check_batch(items, recs, host, {"fp32": "fp32"})
+    b.destroy()
