@@ -439,10 +439,14 @@ typedef struct lpx_batch lpx_batch;
  *     into runs of similar length, and the runs are dealt largest first to
  *     the least-loaded work-group.  Records that read D from memory get its
  *     MFMA-order arrangement from the graph's first nodes (into device
- *     memory the batch owns).  The nodes are captured once into a HIP graph.
- *   *h != NULL: items must have the batch's n and per-item K, Np, E and
- *     layout (pointers may change); copies the updated descriptor table and
- *     replays the graph on `stream`.
+ *     memory the batch owns).  The nodes are captured once into a HIP graph,
+ *     the group launches on two parallel branches.
+ *   *h != NULL, items != NULL: items must have the batch's n and per-item
+ *     K, Np, E and layout (pointers may change); copies the updated
+ *     descriptor table and replays the graph on `stream`.
+ *   *h != NULL, items == NULL: replays the graph on `stream` with the
+ *     table of the last submit (no host-side work, no copy; recs and n are
+ *     not read).
  * Outputs are bit-identical to lpx_contract with the same records (and to
  * any record of the same precision: every record of a precision sums each
  * output in the same order).  The caller keeps all buffers alive until
@@ -479,9 +483,10 @@ lpx_status lpx_batch_destroy(lpx_batch* b);
  * (lpx_record_enumerate order) on the caller's buffers -- `warmup` untimed
  * launches, then `reps` launches each bracketed by HIP events on `stream`,
  * median kept -- and returns the fastest in *best (ties: lowest index).
- * If flush (device, flush_bytes, a multiple of 16) is not NULL it is
- * overwritten before every timed launch, outside the events, so that the
- * caches do not hold the problem's data (needed for small problems).
+ * If flush (device, flush_bytes, a multiple of 16) is not NULL it is read
+ * in full before every timed launch, outside the events, so that the caches
+ * hold none of the problem's data and no dirty lines (needed for problems
+ * that fit the last-level cache); its contents are left unchanged.
  * Blocks the calling thread until the timing launches finish.  Overwrites
  * c->out.  Candidates that lpx_contract_validate rejects (e.g. LDS budget)
  * are skipped and reported as +infinity.  Writes min(cap, count) median

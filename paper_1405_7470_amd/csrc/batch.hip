@@ -12,10 +12,10 @@
 // -- only between runs.  Records that read D from memory get its MFMA-order
 // arrangement from the first graph nodes, into a buffer the batch owns.
 //
-// The nodes (arrangements, then one launch per group) are captured once
-// into a HIP graph on a library-owned stream; lpx_batch_submit replays it
-// on the caller's stream after copying the (possibly updated) descriptor
-// table.
+// The nodes (arrangements, then one launch per group on two parallel
+// branches) are captured once into a HIP graph on library-owned streams;
+// lpx_batch_submit replays it on the caller's stream after copying the
+// (possibly updated) descriptor table.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -102,6 +102,7 @@ struct lpx_batch {
     int64_t total_tiles = 0, lds_max = 0;
     int grid_total = 0;
     hipStream_t cap_stream = nullptr;
+    hipStream_t side_stream = nullptr;  // the graph's second branch during capture
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t copied = nullptr;     // the table copy of the last submit is done
@@ -119,6 +120,7 @@ void free_batch(lpx_batch* b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->side_stream) (void)hipStreamDestroy(b->side_stream);
     if (b->copied) (void)hipEventDestroy(b->copied);
     if (b->dev_items) (void)hipFree(b->dev_items);
     if (b->dev_runs) (void)hipFree(b->dev_runs);
@@ -283,7 +285,8 @@ lpx_status create(const lpx_contract_desc* items, const lpx_record* recs, int32_
          (e = hipMalloc((void**)&b->dev_idx, sizeof(int32_t) * idx.size())) != hipSuccess) ||
         (darr_total > 0 && (e = hipMalloc((void**)&b->darr, (size_t)darr_total)) != hipSuccess) ||
         (e = hipEventCreateWithFlags(&b->copied, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
+        (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&b->side_stream, hipStreamNonBlocking)) != hipSuccess) {
         free_batch(b);
         return hip_err(e, "batch allocation");
     }
@@ -321,16 +324,40 @@ lpx_status create(const lpx_contract_desc* items, const lpx_record* recs, int32_
                                    b->dev_items, list, m);
             if (le == hipSuccess) le = hipGetLastError();
         }
-        for (const Group& G : b->groups) {
+        // The group launches on two branches of the graph (largest groups
+        // first, each to the branch with less work), so that one group's
+        // tail overlaps work of the other branch.
+        hipEvent_t fork = nullptr, join = nullptr;
+        if (le == hipSuccess) le = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        if (le == hipSuccess) le = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+        if (le == hipSuccess) le = hipEventRecord(fork, b->cap_stream);
+        if (le == hipSuccess) le = hipStreamWaitEvent(b->side_stream, fork, 0);
+        std::vector<std::pair<double, int>> order;  // (-work, group)
+        for (int gi = 0; gi < (int)b->groups.size(); ++gi) {
+            double w = 0;
+            for (int32_t i : b->groups[gi].inst)
+                w += (double)geo[i].ntiles * geo[i].tile_e * geo[i].nrb * geo[i].nsteps;
+            order.push_back({-w, gi});
+        }
+        std::sort(order.begin(), order.end());
+        double load[2] = {0.0, 0.0};
+        for (const auto& o : order) {
+            const Group& G = b->groups[o.second];
+            const int br = load[0] <= load[1] ? 0 : 1;
+            load[br] -= o.first;
             kern::RunArgs ra{b->dev_items, b->dev_runs + G.run_off, b->dev_wg + G.wg_off};
             void* kargs[] = {&ra};
-            const hipError_t ge =
-                hipLaunchKernel(reinterpret_cast<const void*>(G.fn), dim3((unsigned)G.grid),
-                                dim3(G.threads), kargs, (size_t)G.lds, b->cap_stream);
+            const hipError_t ge = hipLaunchKernel(
+                reinterpret_cast<const void*>(G.fn), dim3((unsigned)G.grid), dim3(G.threads),
+                kargs, (size_t)G.lds, br == 0 ? b->cap_stream : b->side_stream);
             if (le == hipSuccess) le = ge;
         }
+        if (le == hipSuccess) le = hipEventRecord(join, b->side_stream);
+        if (le == hipSuccess) le = hipStreamWaitEvent(b->cap_stream, join, 0);
         e = hipStreamEndCapture(b->cap_stream, &b->graph);
         if (e == hipSuccess && le != hipSuccess) e = le;
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) { free_batch(b); return hip_err(e, "batch graph capture"); }
@@ -378,7 +405,15 @@ lpx_status lpx_batch_submit(const lpx_contract_desc* items, const lpx_record* re
             return LPX_OK;
         }
         lpx_batch* b = *h;
-        if (!items || n != b->n)
+        if (!items) {
+            // replay with the table as it is: after its last copy, no host work
+            hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+            hipError_t e = hipStreamWaitEvent(st, b->copied, 0);
+            if (e == hipSuccess) e = hipGraphLaunch(b->exec, st);
+            if (e != hipSuccess) return hip_err(e, "batch replay");
+            return LPX_OK;
+        }
+        if (n != b->n)
             return set_error(LPX_ERR_INVALID_ARG, "update needs the batch's %d descriptors", b->n);
         for (int32_t i = 0; i < n; ++i) {
             if (items[i].K != b->K[i] || items[i].Np != b->Np[i] || items[i].E != b->E[i] ||

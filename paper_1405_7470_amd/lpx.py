@@ -498,7 +498,7 @@ def autotune(D, u, out=None, layout="em", precision="fp32", warmup=2, reps=7, st
              flush=None):
     """Exhaustive tuning on the given buffers; returns (best Record, list of
     median microseconds per candidate in enumeration order; inf = skipped).
-    flush: optional CUDA tensor overwritten before every timed launch."""
+    flush: optional CUDA tensor read in full before every timed launch (left unchanged)."""
     K, Np, E = contract_shapes(D, u, layout)
     if out is None:
         out = torch.empty(out_shape(K, Np, E, layout), dtype=torch.float32, device=u.device)
@@ -588,7 +588,13 @@ class Batch:
         self._keep = items  # the caller's tensors stay referenced until the next submit
 
     def submit(self, items=None, stream=None):
-        self._submit(items if items is not None else self._keep, None, stream)
+        """Replays the graph; with items, first points it at new tensors of
+        the same shapes."""
+        if items is None:
+            _check(lib().lpx_batch_submit(None, None, self.n, ctypes.byref(self.handle),
+                                          _stream_handle(stream)))
+            return
+        self._submit(items, None, stream)
 
     def info(self):
         t, te, g, l = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()

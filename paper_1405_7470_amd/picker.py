@@ -1,8 +1,9 @@
 """Training and evaluation of the learned variant picker.
 
 1. collect(): for random problem shapes, the exhaustive autotuner
-   (lpx_autotune, with a cache-flush buffer overwritten before every timed
-   launch) times every candidate record; each (shape, record) becomes one
+   (lpx_autotune, with a cache-flush buffer read before every timed launch;
+   the shipped model was trained when the flush wrote the buffer instead)
+   times every candidate record; each (shape, record) becomes one
    row: its 12 features (lpx_features) and the median time.
 2. train(): the 12-64-64-1 cost model learns log time from those rows.
    Every step runs the library's kernels: lpx_mlp_forward -> lpx_mlp_loss ->

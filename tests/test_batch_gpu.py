@@ -121,6 +121,14 @@ def test_batch_replay_with_new_buffers_and_sentinel():
         for (D, u, out, lay), (Dh, uh) in zip(items2, host2):
             assert not torch.isnan(out).any()
             check_against_oracle(Dh, uh, as_em(out, lay), lay, "fp32")
+    # a replay without descriptors reuses the last table (items2)
+    ref = [out.clone() for (_, _, out, _) in items2]
+    for (_, _, out, _) in items2:
+        out.fill_(float("nan"))
+    b.submit()
+    torch.cuda.synchronize()
+    for (_, _, out, _), r in zip(items2, ref):
+        assert torch.equal(out, r)
     b.destroy()
 
 
