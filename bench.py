@@ -125,14 +125,15 @@ def hbm_copy(stream):
 
 def sweep_table(key, times):
     """The autotuner's timing of every record of one problem (enumeration
-    order): [tile_e, prefetch, unroll, median us, GB/s, % of roofline]."""
+    order): [tile_e, prefetch, unroll, order, median us, GB/s, % of roofline]."""
     recs = lpx.enumerate_records(K, NP, E, key[0], key[1])
     rows = []
     for r, t in zip(recs, times):
         if not math.isfinite(t):
             continue
         s = t * 1e-6
-        rows.append([r.tile_e, r.prefetch, r.unroll, round(t, 2), round(BYTES / s / 1e9, 1),
+        rows.append([r.tile_e, r.prefetch, r.unroll, r.order, round(t, 2),
+                     round(BYTES / s / 1e9, 1),
                      round(100.0 * FLOP / s / 1e12 / roof_tflops(key[1]), 2)])
     return rows
 
@@ -573,7 +574,8 @@ def main():
                    "selection": "learned" if results["learned"] else "autotuned"},
         "roofline": roofline,
         "variants": results,
-        "sweep": {"columns": ["tile_e", "prefetch", "unroll", "us", "GBps", "pct_roof"],
+        "sweep": {"columns": ["tile_e", "prefetch", "unroll", "order", "us", "GBps",
+                              "pct_roof"],
                   "note": "autotuner medians (5 reps, a 512 MiB cache flush before each) "
                           "of every supported record",
                   "problems": sweeps},

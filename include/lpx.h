@@ -124,6 +124,14 @@ typedef int32_t lpx_status;
  *   assume_tile_divides: 1 asserts E % tile_e == 0 (an assumption in the
  *              sense of sec. 2.1); a call whose E violates it fails with
  *              LPX_ERR_ASSUMPTION instead of computing.
+ *   order    : how the outer loop of the split element loop (the tiles)
+ *              is laid over the G persistent work-groups (loop order,
+ *              sec. 2.3; split_iname, sec. 2.4.1): 0 = cyclic, work-group b
+ *              takes tiles b, b + G, b + 2G, ... (neighbouring work-groups
+ *              stream neighbouring tiles); 1 = blocked, work-group b takes
+ *              the consecutive tiles b*c .. b*c + c - 1, c = ceil(ntiles /
+ *              G) (each work-group streams one contiguous range).  The
+ *              ragged batch lays out its own runs and ignores this field.
  *   gemm_tm, gemm_tn, gemm_tk: GEMM macro tile (rows of C, columns of C,
  *              reduction depth staged per step); 0 = library default.
  * Records are plain values (the paper's kernels are immutable, sec. 2.4):
@@ -135,7 +143,8 @@ typedef struct lpx_record {
     uint8_t prefetch;
     uint8_t unroll;
     uint8_t assume_tile_divides;
-    uint8_t reserved0[3];
+    uint8_t order;
+    uint8_t reserved0[2];
     uint16_t gemm_tm;
     uint16_t gemm_tn;
     uint16_t gemm_tk;
@@ -273,11 +282,12 @@ lpx_status lpx_record_validate(const lpx_record* rec);
 lpx_status lpx_record_describe(const lpx_record* rec, char* buf, size_t len);
 
 /* The candidate records of a problem in canonical order: precision fixed to
- * p->precision, then tile_e in {16,32,64} (outer), prefetch in
- * {0,1,2,3,4,6,10,11,14}, unroll in {1,2,4} (inner): LPX_MAX_RECORDS = 81
- * records (some may be unsupported for a given shape).  Writes
- * min(cap, 81) records to the host array `recs` and the total count to *n. */
-#define LPX_MAX_RECORDS 81
+ * p->precision, then order in {0,1} (outermost), tile_e in {16,32,64},
+ * prefetch in {0,1,2,3,4,6,10,11,14}, unroll in {1,2,4} (inner):
+ * LPX_MAX_RECORDS = 162 records (some may be unsupported for a given
+ * shape; the first 81 are the cyclic-order ones).  Writes min(cap, 162)
+ * records to the host array `recs` and the total count to *n. */
+#define LPX_MAX_RECORDS 162
 lpx_status lpx_record_enumerate(const lpx_problem* p, lpx_record* recs,
                                 int32_t cap, int32_t* n);
 
@@ -506,26 +516,27 @@ lpx_status lpx_tune_cache_insert(const lpx_problem* p, const lpx_record* rec);
 lpx_status lpx_tune_cache_clear(void);
 
 /* --------------------------------------------------- learned picker */
-/* Cost model: a perceptron 12 -> 64 -> 64 -> 1 with ReLU hidden units that
+/* Cost model: a perceptron 13 -> 64 -> 64 -> 1 with ReLU hidden units that
  * predicts the log run time of one (problem, record) pair.  Parameters are
- * one flat FP32 vector: W1[64][12], b1[64], W2[64][64], b2[64], w3[64], b3.
+ * one flat FP32 vector: W1[64][13], b1[64], W2[64][64], b2[64], w3[64], b3.
  * Every kernel below sums in a fixed order (deterministic results). */
-#define LPX_MLP_FEATURES 12
+#define LPX_MLP_FEATURES 13
 #define LPX_MLP_HIDDEN 64
-#define LPX_MLP_PARAMS 5057
+#define LPX_MLP_PARAMS 5121
 
-/* The 12 features of (problem, record), into the host array out[12]:
+/* The 13 features of (problem, record), into the host array out[13]:
  * log2 Np, log2 E, K, layout, log2 tile_e, D storage, staging (0 none,
  * 1 u tile, 2 u and output tiles), log2 unroll, precision code, MFMA row
  * padding of the stacked operator rows (16*ceil(K*Np/16) - K*Np) /
  * (16*ceil(K*Np/16)), alignment class 2*(Np % 4 == 0) + (E % 4 == 0)
  * (vector or scalar row and element accesses), dynamic LDS bytes per
- * work-group / 160 KiB.  The D-prefetch feature is the storage of D:
+ * work-group / 160 KiB, tile order (0 cyclic, 1 blocked).  The
+ * D-prefetch feature is the storage of D:
  * 0 global, 1 LDS, 2 registers.  Needs 0 < K, 0 < Np <= 128, 0 < E. */
 lpx_status lpx_features(const lpx_problem* p, const lpx_record* r, float* out);
 
 /* Forward pass of n rows.  params: device, LPX_MLP_PARAMS floats; X: device
- * n x 12; act: device n x 128 (per row z1[64] then z2[64], kept for the
+ * n x 13; act: device n x 128 (per row z1[64] then z2[64], kept for the
  * backward pass) or NULL; y: device n predictions. */
 lpx_status lpx_mlp_forward(const float* params, const float* X, int32_t n, float* act,
                            float* y, void* stream);
@@ -558,7 +569,7 @@ lpx_status lpx_mlp_pick(const float* params, const float* feats, int32_t ncand,
 
 /* A trained picker: weights plus feature standardisation, loaded from a
  * model file (magic "LPXPICK1", version, dimensions, mean[12], std[12],
- * params[5057], FNV-1a checksum; little-endian).  Opaque. */
+ * params[5121], FNV-1a checksum; little-endian).  Opaque. */
 typedef struct lpx_picker lpx_picker;
 
 /* Writes a model file from host arrays. */

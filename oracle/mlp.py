@@ -1,7 +1,7 @@
 """FP64 reference of the variant picker's cost model (test infrastructure).
 
-A multilayer perceptron 12 -> 64 -> 64 -> 1 with ReLU hidden units predicts
-the log run time of one (problem, record) pair from its 12 features; it is
+A multilayer perceptron 13 -> 64 -> 64 -> 1 with ReLU hidden units predicts
+the log run time of one (problem, record) pair from its 13 features; it is
 trained by mean squared error with Adam, and the pick is the candidate with
 the smallest prediction (ties: lowest index).  The paper leaves every choice
 of transformation to the user (its sec. 1: instructions, loop bounds and
@@ -9,15 +9,15 @@ transformations fix the code); this model is how the build chooses records
 for shapes it has not timed.
 
 Parameters are one flat vector in this order (the layout the GPU kernels
-use): W1[64][12], b1[64], W2[64][64], b2[64], w3[64], b3.
+use): W1[64][13], b1[64], W2[64][64], b2[64], w3[64], b3.
 
 Only tests and the benchmark's CPU leg import this module.
 """
 import numpy as np
 
-NF, NH = 12, 64
+NF, NH = 13, 64
 SIZES = (("W1", NH * NF), ("b1", NH), ("W2", NH * NH), ("b2", NH), ("w3", NH), ("b3", 1))
-NPARAMS = sum(n for _, n in SIZES)  # 5057
+NPARAMS = sum(n for _, n in SIZES)  # 5121
 
 
 def unpack(p):

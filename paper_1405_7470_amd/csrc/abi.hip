@@ -65,6 +65,7 @@ lpx_status check_record(const lpx_record* rec) {
     if (rec->assume_tile_divides > 1)
         return set_error(LPX_ERR_INVALID_ARG, "assume_tile_divides %u not in {0,1}",
                          rec->assume_tile_divides);
+    if (rec->order > 1) return set_error(LPX_ERR_INVALID_ARG, "order %u not in {0,1}", rec->order);
     for (uint8_t b : rec->reserved0)
         if (b) return set_error(LPX_ERR_INVALID_ARG, "reserved record bytes must be 0");
     if (rec->reserved1) return set_error(LPX_ERR_INVALID_ARG, "reserved record bytes must be 0");
@@ -79,6 +80,7 @@ lpx_status contract_geometry(int K, int Np, int64_t E, int layout,
     g->tile_e = r.tile_e;
     g->prefetch = r.prefetch;
     g->unroll = r.unroll;
+    g->order = r.order;
     g->kstep = (r.precision == LPX_FP32) ? 4 : 32;
     g->nt = (int)ceil_div(Np, 16);
     g->ntmax = g->nt <= 2 ? 2 : (g->nt <= 4 ? 4 : 8);
@@ -355,8 +357,9 @@ lpx_status lpx_record_describe(const lpx_record* rec, char* buf, size_t len) {
         return s;
     }
     static const char* prec[] = {"fp32", "bf16", "bf16x3"};
-    snprintf(buf, len, "%s tile_e=%u prefetch=%u unroll=%u%s gemm=%ux%ux%u",
+    snprintf(buf, len, "%s tile_e=%u prefetch=%u unroll=%u%s%s gemm=%ux%ux%u",
              prec[rec->precision], rec->tile_e, rec->prefetch, rec->unroll,
+             rec->order ? " order=blocked" : "",
              rec->assume_tile_divides ? " assume(E%tile_e==0)" : "", rec->gemm_tm,
              rec->gemm_tn, rec->gemm_tk);
     return LPX_OK;
@@ -373,18 +376,20 @@ lpx_status lpx_record_enumerate(const lpx_problem* p, lpx_record* recs, int32_t 
     static const uint8_t tiles[] = {16, 32, 64};
     static const uint8_t unrolls[] = {1, 2, 4};
     int32_t count = 0;
-    for (uint8_t t : tiles)
-        for (uint8_t pf : kPrefetchSets)
-            for (uint8_t un : unrolls) {
-                if (count < cap) {
-                    lpx_record r = default_record(p->precision);
-                    r.tile_e = t;
-                    r.prefetch = pf;
-                    r.unroll = un;
-                    recs[count] = r;
+    for (uint8_t ord = 0; ord < 2; ++ord)
+        for (uint8_t t : tiles)
+            for (uint8_t pf : kPrefetchSets)
+                for (uint8_t un : unrolls) {
+                    if (count < cap) {
+                        lpx_record r = default_record(p->precision);
+                        r.tile_e = t;
+                        r.prefetch = pf;
+                        r.unroll = un;
+                        r.order = ord;
+                        recs[count] = r;
+                    }
+                    ++count;
                 }
-                ++count;
-            }
     *n = count;
     return LPX_OK;
 }

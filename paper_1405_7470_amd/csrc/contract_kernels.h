@@ -82,6 +82,7 @@ struct ContractArgs {
     int np_vec;  // Np % 4 == 0: 16-byte row accesses are aligned
     int e_vec;   // E % 4 == 0
     int stream_out;  // large outputs: streaming (non-temporal) stores, see store_stream
+    int blocked;     // record order 1: work-group b takes one contiguous range of tiles
 };
 
 // Operator index of stacked row R (0 <= R < 2^31).
@@ -1508,14 +1509,21 @@ __device__ __forceinline__ void contract_tiles(const ContractArgs& a, int64_t t0
     }
 }
 
-// One contraction: work-group b takes tiles b, b + G, b + 2G, ... (G the
-// persistent grid).
+// One contraction over the persistent grid of G work-groups: work-group b
+// takes tiles b, b + G, b + 2G, ... (cyclic order), or the consecutive
+// tiles b*c .. b*c + c - 1, c = ceil(ntiles / G) (blocked order).
 template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PREFETCH, int UNROLL, int EPI = 0>
 __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void contract_kernel(
     ContractArgs a) {
-    const int64_t t0 = blockIdx.x, g = gridDim.x;
-    const int64_t nmine = t0 < a.ntiles ? (a.ntiles - 1 - t0) / g + 1 : 0;
-    contract_tiles<PREC, LAYOUT, NTMAX, TILE_E, PREFETCH, UNROLL, EPI>(a, t0, g, nmine);
+    const int64_t b = blockIdx.x, G = gridDim.x;
+    int64_t t0 = b, step = G, nmine = b < a.ntiles ? (a.ntiles - 1 - b) / G + 1 : 0;
+    if (a.blocked) {  // uniform
+        const int64_t c = (a.ntiles + G - 1) / G, rest = a.ntiles - b * c;
+        t0 = b * c;
+        step = 1;
+        nmine = rest < 0 ? 0 : (rest < c ? rest : c);
+    }
+    contract_tiles<PREC, LAYOUT, NTMAX, TILE_E, PREFETCH, UNROLL, EPI>(a, t0, step, nmine);
 }
 
 // A ragged batch: runs of consecutive tiles of one instance each, listed

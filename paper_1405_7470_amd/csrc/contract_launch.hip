@@ -119,6 +119,7 @@ kern::ContractArgs contract_args(const lpx_contract_desc& c, const ContractGeom&
     a.np_vec = (c.Np % 4) == 0;
     a.e_vec = (c.E % 4) == 0;
     a.stream_out = (int64_t)c.K * c.E * c.Np * 4 >= ((int64_t)32 << 20);
+    a.blocked = g.order;
     return a;
 }
 

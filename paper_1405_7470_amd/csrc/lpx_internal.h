@@ -83,6 +83,7 @@ inline Divider make_divider(int d) {
 struct ContractGeom {
     int prec = 0, layout = 0;
     int tile_e = 16, prefetch = 0, unroll = 1;
+    int order = 0;     // element tiles over the grid: 0 cyclic, 1 blocked
     int threads = 256;  // work-group size: 4 wave64s per 16 elements of the tile
     int kstep = 4;     // reduction length of one MFMA (4 fp32, 32 bf16)
     int nt = 0;        // i-blocks of 16 rows: ceil(Np / 16)

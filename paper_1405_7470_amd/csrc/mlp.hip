@@ -1,9 +1,9 @@
-// Cost model of the variant picker: a 12 -> 64 -> 64 -> 1 ReLU perceptron
+// Cost model of the variant picker: a 13 -> 64 -> 64 -> 1 ReLU perceptron
 // predicting log run time, with its forward, loss, backward, Adam and pick
 // kernels.  The paper has the user choose every transformation (sec. 1); the
 // model picks records for shapes the exhaustive tuner has not timed.
 //
-// Flat parameter layout: W1[64][12], b1[64], W2[64][64], b2[64], w3[64], b3.
+// Flat parameter layout: W1[64][13], b1[64], W2[64][64], b2[64], w3[64], b3.
 // All sums run in a fixed order, so results are deterministic.
 #include <hip/hip_runtime.h>
 
@@ -14,7 +14,7 @@
 namespace lpx {
 namespace mlpk {
 
-constexpr int NF = 12, NH = 64;
+constexpr int NF = LPX_MLP_FEATURES, NH = LPX_MLP_HIDDEN;
 constexpr int OW1 = 0, OB1 = OW1 + NH * NF, OW2 = OB1 + NH, OB2 = OW2 + NH * NH,
               OW3 = OB2 + NH, OB3 = OW3 + NH, NP = OB3 + 1;
 static_assert(NP == LPX_MLP_PARAMS, "parameter count");

@@ -58,6 +58,7 @@ lpx_status features(const lpx_problem& p, const lpx_record& r, float* f) {
     // accesses, which log2 Np and log2 E cannot express
     f[10] = (float)(2 * (p.Np % 4 == 0) + (p.E % 4 == 0));
     f[11] = (float)((double)g.lds_bytes / (double)kMaxLdsPerWorkgroup);
+    f[12] = (float)r.order;  // element tiles over the grid: cyclic or blocked
     return LPX_OK;
 }
 

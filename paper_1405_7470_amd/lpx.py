@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liblpx.so")
 
 # status codes (include/lpx.h)
 OK = 0
-MAX_RECORDS = 81  # LPX_MAX_RECORDS
+MAX_RECORDS = 162  # LPX_MAX_RECORDS
 ERR_INVALID_ARG = 1
 ERR_UNSUPPORTED = 2
 ERR_ASSUMPTION = 3
@@ -49,7 +49,8 @@ class Record(ctypes.Structure):
         ("prefetch", ctypes.c_uint8),
         ("unroll", ctypes.c_uint8),
         ("assume_tile_divides", ctypes.c_uint8),
-        ("reserved0", ctypes.c_uint8 * 3),
+        ("order", ctypes.c_uint8),
+        ("reserved0", ctypes.c_uint8 * 2),
         ("gemm_tm", ctypes.c_uint16),
         ("gemm_tn", ctypes.c_uint16),
         ("gemm_tk", ctypes.c_uint16),
@@ -58,7 +59,7 @@ class Record(ctypes.Structure):
 
     def key(self):
         return (self.precision, self.tile_e, self.prefetch, self.unroll,
-                self.assume_tile_divides, self.gemm_tm, self.gemm_tn, self.gemm_tk)
+                self.assume_tile_divides, self.order, self.gemm_tm, self.gemm_tn, self.gemm_tk)
 
     def __eq__(self, other):
         return isinstance(other, Record) and self.key() == other.key()
@@ -72,7 +73,7 @@ class Record(ctypes.Structure):
     def as_dict(self):
         return {"precision": PRECISION_NAME[self.precision], "tile_e": self.tile_e,
                 "prefetch": self.prefetch, "unroll": self.unroll,
-                "assume_tile_divides": self.assume_tile_divides,
+                "assume_tile_divides": self.assume_tile_divides, "order": self.order,
                 "gemm": [self.gemm_tm, self.gemm_tn, self.gemm_tk]}
 
 
@@ -231,10 +232,11 @@ def default_record(precision="fp32") -> Record:
 
 
 def record(precision="fp32", tile_e=16, prefetch=0, unroll=1, assume_tile_divides=0,
-           gemm=(0, 0, 0)) -> Record:
+           gemm=(0, 0, 0), order=0) -> Record:
     r = default_record(precision)
     r.tile_e, r.prefetch, r.unroll = tile_e, prefetch, unroll
     r.assume_tile_divides = assume_tile_divides
+    r.order = order
     r.gemm_tm, r.gemm_tn, r.gemm_tk = gemm
     return r
 
@@ -629,7 +631,7 @@ def batch_tune(items, precision="fp32", warmup=1, reps=5, stream=None):
 
 
 # ------------------------------------------------------------ cost model
-MLP_FEATURES, MLP_HIDDEN, MLP_PARAMS = 12, 64, 5057
+MLP_FEATURES, MLP_HIDDEN, MLP_PARAMS = 13, 64, 5121
 PICK_UNTUNED, PICK_EXHAUSTIVE, PICK_LEARNED = 0, 1, 2
 
 

@@ -4,7 +4,7 @@
    (lpx_autotune, with a cache-flush buffer read before every timed launch;
    the shipped model was trained when the flush wrote the buffer instead)
    times every candidate record; each (shape, record) becomes one
-   row: its 12 features (lpx_features) and the median time.
+   row: its 13 features (lpx_features) and the median time.
 2. train(): the 12-64-64-1 cost model learns log time from those rows.
    Every step runs the library's kernels: lpx_mlp_forward -> lpx_mlp_loss ->
    lpx_mlp_backward -> lpx_adam_step (torch only gathers minibatches).
@@ -223,6 +223,8 @@ def main():
                     help="evaluate the existing model on the held-out shapes only")
     ap.add_argument("--summary", default=None,
                     help="also write a text summary of the evaluation to this file")
+    ap.add_argument("--command", default=None,
+                    help="with --summary-from: the command that wrote the eval.json")
     ap.add_argument("--summary-from", default=None,
                     help="write --summary from the eval.json of an earlier evaluation "
                          "(no GPU work)")
@@ -280,10 +282,9 @@ def write_summary(path, summary, res, args):
     lines = [
         "# Learned picker: regret on held-out shapes",
         "",
-        f"Command: `python -m paper_1405_7470_amd.picker --eval-only --eval-shapes "
-        f"{args.eval_shapes} --out {args.out}` (model `{os.path.relpath(args.model)}`), "
-        f"then `python -m paper_1405_7470_amd.picker --summary-from "
-        f"{os.path.join(args.out, 'eval.json')} --summary {path}`.",
+        f"Command: `{args.command or ('python -m paper_1405_7470_amd.picker --eval-only --eval-shapes %d --out %s' % (args.eval_shapes, args.out))}` "
+        f"(model `{os.path.relpath(args.model)}`), then `python -m paper_1405_7470_amd.picker "
+        f"--summary-from {os.path.join(args.out, 'eval.json')} --summary {path}`.",
         "",
         f"Held-out shapes: {summary['shapes']} (seed 2: Np uniform in [8, 128], "
         "E = floor(2^U(10, 21)), layout and precision uniform, K = 3), each tuned "

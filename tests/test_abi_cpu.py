@@ -51,27 +51,29 @@ def test_default_record_is_the_untuned_variant():
 
 def test_enumeration_canonical_order_and_truncation():
     recs = lpx.enumerate_records(3, 56, 1 << 20, "em", "bf16x3")
-    assert len(recs) == 81 == lpx.MAX_RECORDS
-    keys = [(r.tile_e, r.prefetch, r.unroll) for r in recs]
-    assert keys == [(t, p, u) for t in (16, 32, 64) for p in (0, 1, 2, 3, 4, 6, 10, 11, 14)
-                    for u in (1, 2, 4)]
+    assert len(recs) == 162 == lpx.MAX_RECORDS
+    keys = [(r.order, r.tile_e, r.prefetch, r.unroll) for r in recs]
+    assert keys == [(o, t, p, u) for o in (0, 1) for t in (16, 32, 64)
+                    for p in (0, 1, 2, 3, 4, 6, 10, 11, 14) for u in (1, 2, 4)]
     assert all(lpx.PRECISION_NAME[r.precision] == "bf16x3" for r in recs)
     p = lpx.problem(3, 56, 1 << 20, "em", "fp32")
     arr = (lpx.Record * 4)()
     n = ctypes.c_int32()
     assert lpx.lib().lpx_record_enumerate(ctypes.byref(p), arr, 4, ctypes.byref(n)) == 0
-    assert n.value == 81 and arr[3].unroll == 1 and arr[3].prefetch == 1
+    assert n.value == 162 and arr[3].unroll == 1 and arr[3].prefetch == 1
 
 
 def test_describe():
     r = lpx.record("bf16", 64, 1, 4)
     assert lpx.describe(r) == "bf16 tile_e=64 prefetch=1 unroll=4 gemm=0x0x0"
+    r = lpx.record("fp32", 32, 14, 1, order=1)
+    assert lpx.describe(r) == "fp32 tile_e=32 prefetch=14 unroll=1 order=blocked gemm=0x0x0"
 
 
 @pytest.mark.parametrize("field,value", [
     ("version", 2), ("precision", 3), ("tile_e", 8), ("tile_e", 128), ("prefetch", 5),
     ("prefetch", 7), ("prefetch", 8), ("prefetch", 9), ("prefetch", 12), ("prefetch", 15),
-    ("unroll", 3), ("assume_tile_divides", 2), ("reserved1", 1)])
+    ("unroll", 3), ("assume_tile_divides", 2), ("order", 2), ("reserved1", 1)])
 def test_malformed_records_rejected(field, value):
     r = lpx.default_record()
     setattr(r, field, value)

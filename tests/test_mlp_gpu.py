@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 def setup(n, seed):
     rng = np.random.default_rng(seed)
     p = rng.normal(0, 0.25, mlp.NPARAMS).astype(np.float32)
-    X = rng.normal(0, 1, (n, 12)).astype(np.float32)
+    X = rng.normal(0, 1, (n, lpx.MLP_FEATURES)).astype(np.float32)
     t = rng.normal(0, 1, n).astype(np.float32)
     return p, X, t
 
@@ -59,9 +59,9 @@ def test_pick_kernel_matches_oracle():
     for trial in range(20):
         p = rng.normal(0, 0.3, mlp.NPARAMS).astype(np.float32)
         nc = int(rng.integers(1, 65))
-        F = rng.normal(0, 2, (nc, 12)).astype(np.float32)
-        mean = rng.normal(0, 1, 12).astype(np.float32)
-        std = np.abs(rng.normal(1, 0.5, 12)).astype(np.float32)
+        F = rng.normal(0, 2, (nc, lpx.MLP_FEATURES)).astype(np.float32)
+        mean = rng.normal(0, 1, lpx.MLP_FEATURES).astype(np.float32)
+        std = np.abs(rng.normal(1, 0.5, lpx.MLP_FEATURES)).astype(np.float32)
         std[trial % 12] = 0.0
         pred = torch.empty(nc, device="cuda")
         best = lpx.mlp_pick(to_dev(p), to_dev(F), to_dev(mean), to_dev(std), pred=pred)
@@ -77,7 +77,7 @@ def test_pick_kernel_matches_oracle():
 def test_training_reduces_loss():
     """A few hundred Adam steps on a smooth synthetic target."""
     rng = np.random.default_rng(6)
-    X = rng.normal(0, 1, (2048, 12)).astype(np.float32)
+    X = rng.normal(0, 1, (2048, lpx.MLP_FEATURES)).astype(np.float32)
     t = (np.sin(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2]).astype(np.float32)
     p = (rng.normal(0, 1, mlp.NPARAMS) * 0.1).astype(np.float32)
     P, Xd, Td = to_dev(p), to_dev(X), to_dev(t)

@@ -11,18 +11,18 @@ def rand_params(seed, scale=0.3):
 
 
 def test_parameter_count_and_layout():
-    assert mlp.NPARAMS == 5057
+    assert mlp.NPARAMS == 5121
     p = np.arange(mlp.NPARAMS, dtype=np.float64)
     W1, b1, W2, b2, w3, b3 = mlp.unpack(p)
-    assert W1.shape == (64, 12) and W1[0, 1] == 1 and W1[1, 0] == 12
-    assert b1[0] == 768 and W2[0, 0] == 832 and W2[1, 0] == 896
-    assert b2[0] == 4928 and w3[0] == 4992 and b3[0] == 5056
+    assert W1.shape == (64, 13) and W1[0, 1] == 1 and W1[1, 0] == 13
+    assert b1[0] == 832 and W2[0, 0] == 896 and W2[1, 0] == 960
+    assert b2[0] == 4992 and w3[0] == 5056 and b3[0] == 5120
 
 
 def test_gradient_matches_central_differences():
     rng = np.random.default_rng(0)
     p = rand_params(1)
-    X = rng.normal(0, 1, (9, 12))
+    X = rng.normal(0, 1, (9, 13))
     t = rng.normal(0, 1, 9)
 
     def loss(q):
@@ -33,8 +33,8 @@ def test_gradient_matches_central_differences():
     _, dy = mlp.mse(y, t)
     g = mlp.backward(p, cache, dy)
     h = 1e-6
-    idx = list(range(0, 768, 37)) + list(range(768, 832, 7)) + list(range(832, 4928, 211)) + \
-        list(range(4928, 5057, 5)) + [5056]
+    idx = list(range(0, 832, 37)) + list(range(832, 896, 7)) + list(range(896, 4992, 211)) + \
+        list(range(4992, 5121, 5)) + [5120]
     for i in idx:
         e = np.zeros_like(p)
         e[i] = h
@@ -45,7 +45,7 @@ def test_gradient_matches_central_differences():
 def test_zero_weights_closed_form():
     p = np.zeros(mlp.NPARAMS)
     p[-1] = 0.75                         # b3
-    X = np.random.default_rng(2).normal(0, 1, (5, 12))
+    X = np.random.default_rng(2).normal(0, 1, (5, 13))
     t = np.arange(5.0)
     y, cache = mlp.forward(p, X)
     assert np.all(y == 0.75)
@@ -61,7 +61,7 @@ def test_linear_region_matches_least_squares_gradient():
     least-squares residual sum and wrt w3 is h2^T dy."""
     rng = np.random.default_rng(3)
     p = np.abs(rand_params(4, 0.1))       # positive weights and inputs
-    X = np.abs(rng.normal(0, 1, (7, 12)))
+    X = np.abs(rng.normal(0, 1, (7, 13)))
     W1, b1, W2, b2, w3, b3 = mlp.unpack(p)
     c = W1.T @ W2.T @ w3
     d = w3 @ (W2 @ b1 + b2) + b3[0]
@@ -72,19 +72,19 @@ def test_linear_region_matches_least_squares_gradient():
     g = mlp.backward(p, cache, dy)
     assert g[-1] == pytest.approx(2 * np.mean(y - t))
     h2 = cache[4]
-    assert np.allclose(g[4992:5056], h2.T @ dy)
+    assert np.allclose(g[5056:5120], h2.T @ dy)
 
 
 def test_tiny_network_by_hand():
     """One active path: x0 -> unit 0 -> unit 0 -> output, everything else 0."""
     p = np.zeros(mlp.NPARAMS)
     p[0] = 2.0          # W1[0][0]
-    p[768] = -1.0       # b1[0]
-    p[832] = 3.0        # W2[0][0]
-    p[4928] = 0.5       # b2[0]
-    p[4992] = -2.0      # w3[0]
-    p[5056] = 1.0       # b3
-    X = np.zeros((2, 12))
+    p[832] = -1.0       # b1[0]
+    p[896] = 3.0        # W2[0][0]
+    p[4992] = 0.5       # b2[0]
+    p[5056] = -2.0      # w3[0]
+    p[5120] = 1.0       # b3
+    X = np.zeros((2, 13))
     X[0, 0] = 1.5       # z1 = 2, h1 = 2, z2 = 6.5, y = -13 + 1 = -12
     X[1, 0] = 0.25      # z1 = -0.5 -> dead, z2 = 0.5, y = -1 + 1 = 0
     y, cache = mlp.forward(p, X)
@@ -93,8 +93,8 @@ def test_tiny_network_by_hand():
     # d y0 / d W1[0][0] = w3[0] * W2[0][0] * x0 = -2 * 3 * 1.5 = -9 (row 1 dead)
     assert g[0] == pytest.approx(-9.0)
     # d(y0 + y1)/d w3[0] = h2_0 + h2_1 = 6.5 + 0.5
-    assert g[4992] == pytest.approx(7.0)
-    assert g[5056] == pytest.approx(2.0)
+    assert g[5056] == pytest.approx(7.0)
+    assert g[5120] == pytest.approx(2.0)
 
 
 def test_adam_first_step_is_signed_lr():
@@ -108,12 +108,12 @@ def test_adam_first_step_is_signed_lr():
 
 def test_pick_rule_and_ties():
     p = np.zeros(mlp.NPARAMS)
-    p[4992] = 1.0                  # y = h2_0 (unit 0 of layer 2)
-    p[832] = 1.0                   # z2_0 = h1_0
+    p[5056] = 1.0                  # y = h2_0 (unit 0 of layer 2)
+    p[896] = 1.0                   # z2_0 = h1_0
     p[0] = 1.0                     # z1_0 = x_0 standardised
-    feats = np.array([[5.0] + [0] * 11, [2.0] + [0] * 11, [2.0] + [0] * 11, [9.0] + [0] * 11])
-    mean = np.zeros(12)
-    std = np.zeros(12)             # std 0 counts as 1
+    feats = np.array([[5.0] + [0] * 12, [2.0] + [0] * 12, [2.0] + [0] * 12, [9.0] + [0] * 12])
+    mean = np.zeros(13)
+    std = np.zeros(13)             # std 0 counts as 1
     assert mlp.pick(p, feats, mean, std) == 1   # 2.0 twice: lowest index
     std[0] = 2.0
     mean[0] = 3.0                  # (x-3)/2 -> ReLU: 1, 0, 0, 3 -> min 0 at index 1

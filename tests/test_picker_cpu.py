@@ -1,5 +1,5 @@
 """Picker host logic on the CPU: model file round trip and rejection of
-damaged files, the 12 features, and the pick modes that need no GPU."""
+damaged files, the 13 features, and the pick modes that need no GPU."""
 import ctypes
 import math
 import struct
@@ -13,8 +13,8 @@ from paper_1405_7470_amd import lpx
 def write_model(path, seed=0):
     rng = np.random.default_rng(seed)
     p = rng.normal(0, 0.1, lpx.MLP_PARAMS).astype(np.float32)
-    m = rng.normal(0, 1, 12).astype(np.float32)
-    s = np.abs(rng.normal(1, 0.1, 12)).astype(np.float32)
+    m = rng.normal(0, 1, lpx.MLP_FEATURES).astype(np.float32)
+    s = np.abs(rng.normal(1, 0.1, lpx.MLP_FEATURES)).astype(np.float32)
     lpx.picker_save(path, p, m, s)
     return p, m, s
 
@@ -26,7 +26,7 @@ def test_round_trip(tmp_path):
     p2, m2, s2 = pk.params()
     assert np.array_equal(p, p2) and np.array_equal(m, m2) and np.array_equal(s, s2)
     pk.close()
-    assert f.stat().st_size == 8 + 16 + 4 * (24 + 5057) + 4
+    assert f.stat().st_size == 8 + 16 + 4 * (2 * lpx.MLP_FEATURES + lpx.MLP_PARAMS) + 4
 
 
 def damaged(tmp_path, how):
@@ -73,7 +73,7 @@ def test_features_by_hand():
     # the 3 operators stacked are 168 rows: 11 row blocks of 16, 8 rows padding
     lds = 11 * 2 * 64 * 32 + 4 * (32 * 64 + 32) * 4
     expect = [math.log2(56), 20.0, 3.0, 1.0, 5.0, 1.0, 1.0, 2.0, 2.0, 8 / 176,
-              3.0, lds / (160 * 1024)]
+              3.0, lds / (160 * 1024), 0.0]
     assert np.allclose(f, expect, rtol=1e-6)
     f = lpx.features(3, 56, 1000, "em", lpx.record("fp32", 16, 6, 1))
     assert f[5] == 2.0 and f[6] == 1.0               # D in registers, u staged
@@ -82,7 +82,10 @@ def test_features_by_hand():
     f = lpx.features(3, 10, 1000, "em", lpx.default_record("fp32"))
     # Np = 10 rows are not 16-byte multiples, E = 1000 runs are
     assert f[9] == pytest.approx(2 / 32) and f[10] == 1.0
-    assert f[5] == 0 and f[6] == 0 and f[11] == 0
+    assert f[5] == 0 and f[6] == 0 and f[11] == 0 and f[12] == 0
+    r = lpx.default_record("fp32")
+    r.order = 1
+    assert lpx.features(3, 10, 1000, "em", r)[12] == 1.0  # blocked tile order
 
 
 def test_pick_modes_without_gpu():
