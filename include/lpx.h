@@ -493,10 +493,11 @@ lpx_status lpx_batch_destroy(lpx_batch* b);
  * (lpx_record_enumerate order) on the caller's buffers -- `warmup` untimed
  * launches, then `reps` launches each bracketed by HIP events on `stream`,
  * median kept -- and returns the fastest in *best (ties: lowest index).
- * If flush (device, flush_bytes, a multiple of 16) is not NULL it is read
- * in full before every timed launch, outside the events, so that the caches
- * hold none of the problem's data and no dirty lines (needed for problems
- * that fit the last-level cache); its contents are left unchanged.
+ * If flush (device, flush_bytes, a multiple of 16) is not NULL it is
+ * overwritten before every timed launch, outside the events, so that the
+ * caches hold none of the problem's data, only dirty lines of the flush
+ * buffer (as after other work; needed for problems that fit the
+ * last-level cache).
  * Blocks the calling thread until the timing launches finish.  Overwrites
  * c->out.  Candidates that lpx_contract_validate rejects (e.g. LDS budget)
  * are skipped and reported as +infinity.  Writes min(cap, count) median
@@ -568,7 +569,7 @@ lpx_status lpx_mlp_pick(const float* params, const float* feats, int32_t ncand,
                         void* stream);
 
 /* A trained picker: weights plus feature standardisation, loaded from a
- * model file (magic "LPXPICK1", version, dimensions, mean[12], std[12],
+ * model file (magic "LPXPICK1", version, dimensions, mean[13], std[13],
  * params[5121], FNV-1a checksum; little-endian).  Opaque. */
 typedef struct lpx_picker lpx_picker;
 

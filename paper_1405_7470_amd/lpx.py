@@ -500,7 +500,7 @@ def autotune(D, u, out=None, layout="em", precision="fp32", warmup=2, reps=7, st
              flush=None):
     """Exhaustive tuning on the given buffers; returns (best Record, list of
     median microseconds per candidate in enumeration order; inf = skipped).
-    flush: optional CUDA tensor read in full before every timed launch (left unchanged)."""
+    flush: optional CUDA tensor overwritten before every timed launch."""
     K, Np, E = contract_shapes(D, u, layout)
     if out is None:
         out = torch.empty(out_shape(K, Np, E, layout), dtype=torch.float32, device=u.device)

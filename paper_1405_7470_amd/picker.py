@@ -1,9 +1,8 @@
 """Training and evaluation of the learned variant picker.
 
 1. collect(): for random problem shapes, the exhaustive autotuner
-   (lpx_autotune, with a cache-flush buffer read before every timed launch;
-   the shipped model was trained when the flush wrote the buffer instead)
-   times every candidate record; each (shape, record) becomes one
+   (lpx_autotune, with a cache-flush buffer overwritten before every timed
+   launch) times every candidate record; each (shape, record) becomes one
    row: its 13 features (lpx_features) and the median time.
 2. train(): the 12-64-64-1 cost model learns log time from those rows.
    Every step runs the library's kernels: lpx_mlp_forward -> lpx_mlp_loss ->
@@ -223,12 +222,23 @@ def main():
                     help="evaluate the existing model on the held-out shapes only")
     ap.add_argument("--summary", default=None,
                     help="also write a text summary of the evaluation to this file")
+    ap.add_argument("--timings", default=None,
+                    help="train from the rows of an earlier collection (timings.jsonl, "
+                         "or .gz) instead of timing the training shapes again")
+    ap.add_argument("--widen-from", default=None,
+                    help="write --model from a model file of the 12-feature cost model "
+                         "(no tile-order feature): its weights with a zero weight for the "
+                         "order feature, so its picks are unchanged (ties go to the cyclic "
+                         "order, listed first)")
     ap.add_argument("--command", default=None,
                     help="with --summary-from: the command that wrote the eval.json")
     ap.add_argument("--summary-from", default=None,
                     help="write --summary from the eval.json of an earlier evaluation "
                          "(no GPU work)")
     args = ap.parse_args()
+    if args.widen_from:
+        widen_model(args.widen_from, args.model)
+        return
     if args.summary_from:
         d = json.load(open(args.summary_from))
         args.out = os.path.dirname(args.summary_from)
@@ -245,11 +255,18 @@ def main():
         print(json.dumps(summary), flush=True)
         return
     os.makedirs(os.path.dirname(args.model), exist_ok=True)
-    train_shapes = inputs.picker_shapes(args.train_shapes, seed=1)
-    db = os.path.join(args.out, "timings.jsonl")
-    if os.path.exists(db):
-        os.remove(db)
-    rows = collect(train_shapes, db_path=db)
+    if args.timings:
+        import gzip
+        opener = gzip.open if args.timings.endswith(".gz") else open
+        with opener(args.timings, "rt") as fh:
+            rows = [json.loads(line) for line in fh if line.strip()]
+        print(f"loaded {len(rows)} timings from {args.timings}", flush=True)
+    else:
+        train_shapes = inputs.picker_shapes(args.train_shapes, seed=1)
+        db = os.path.join(args.out, "timings.jsonl")
+        if os.path.exists(db):
+            os.remove(db)
+        rows = collect(train_shapes, db_path=db)
     best = None
     for seed in range(args.seeds):
         params, mean, std, hist = train(rows, epochs=args.epochs, seed=seed)
@@ -268,6 +285,24 @@ def main():
     if args.summary:
         write_summary(args.summary, summary, res, args)
     print(json.dumps(summary), flush=True)
+
+
+def widen_model(old_path, new_path, old_nf=12):
+    """A 12-feature model file (magic, version and dimensions, mean[12],
+    std[12], params, checksum) as a 13-feature one: W1 gains a zero column
+    for the order feature, whose standardisation is (0, 1)."""
+    raw = open(old_path, "rb").read()
+    nh = lpx.MLP_HIDDEN
+    nparams = nh * old_nf + nh + nh * nh + nh + nh + 1
+    if len(raw) != 8 + 16 + 4 * (2 * old_nf + nparams) + 4:
+        raise ValueError(f"{old_path} is not a {old_nf}-feature model file")
+    v = np.frombuffer(raw[24:-4], dtype="<f4")
+    mean, std, p = v[:old_nf], v[old_nf:2 * old_nf], v[2 * old_nf:]
+    W1 = p[:nh * old_nf].reshape(nh, old_nf)
+    W1n = np.concatenate([W1, np.zeros((nh, 1), np.float32)], axis=1)
+    pn = np.concatenate([W1n.ravel(), p[nh * old_nf:]]).astype(np.float32)
+    assert pn.size == lpx.MLP_PARAMS
+    lpx.picker_save(new_path, pn, np.append(mean, 0.0), np.append(std, 1.0))
 
 
 def write_summary(path, summary, res, args):

@@ -97,3 +97,26 @@ def test_pick_modes_without_gpu():
     with pytest.raises(lpx.LpxError) as ei:
         lpx.pick_variant(3, 56, 1000, "em", "fp32", mode=7, stream=0)
     assert ei.value.status == lpx.ERR_INVALID_ARG
+
+
+def test_widen_twelve_feature_model(tmp_path):
+    """A 12-feature model file becomes a 13-feature one whose order weights
+    are zero and whose other weights are unchanged (same predictions)."""
+    from paper_1405_7470_amd import picker
+    nh, nf = lpx.MLP_HIDDEN, 12
+    n12 = nh * nf + nh + nh * nh + nh + nh + 1
+    rng = np.random.default_rng(5)
+    mean = rng.normal(0, 1, nf).astype("<f4")
+    std = np.abs(rng.normal(1, 0.1, nf)).astype("<f4")
+    p = rng.normal(0, 0.1, n12).astype("<f4")
+    old = tmp_path / "m12"
+    old.write_bytes(b"\0" * 24 + mean.tobytes() + std.tobytes() + p.tobytes() + b"\0" * 4)
+    new = tmp_path / "m13"
+    picker.widen_model(str(old), str(new))
+    q, m, s = lpx.Picker(new).params()
+    W1 = q[:nh * 13].reshape(nh, 13)
+    assert np.array_equal(W1[:, :12], p[:nh * 12].reshape(nh, 12)) and not W1[:, 12].any()
+    assert np.array_equal(q[nh * 13:], p[nh * 12:])
+    assert np.array_equal(m, np.append(mean, 0)) and np.array_equal(s, np.append(std, 1))
+    with pytest.raises(ValueError):
+        picker.widen_model(str(new), str(tmp_path / "x"))
