@@ -1515,18 +1515,15 @@ __device__ __forceinline__ void contract_tiles(const ContractArgs& a, int64_t t0
 template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PREFETCH, int UNROLL, int EPI = 0>
 __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void contract_kernel(
     ContractArgs a) {
-    // Two call sites: each order's tile indices are then computed from
-    // values the compiler can reload (block and grid size, kernel
-    // arguments) instead of being held in registers the whole kernel.
     const int64_t b = blockIdx.x, G = gridDim.x;
+    int64_t t0 = b, step = G, nmine = b < a.ntiles ? (a.ntiles - 1 - b) / G + 1 : 0;
     if (a.blocked) {  // uniform
         const int64_t c = (a.ntiles + G - 1) / G, rest = a.ntiles - b * c;
-        contract_tiles<PREC, LAYOUT, NTMAX, TILE_E, PREFETCH, UNROLL, EPI>(
-            a, b * c, 1, rest < 0 ? 0 : (rest < c ? rest : c));
-    } else {
-        contract_tiles<PREC, LAYOUT, NTMAX, TILE_E, PREFETCH, UNROLL, EPI>(
-            a, b, G, b < a.ntiles ? (a.ntiles - 1 - b) / G + 1 : 0);
+        t0 = b * c;
+        step = 1;
+        nmine = rest < 0 ? 0 : (rest < c ? rest : c);
     }
+    contract_tiles<PREC, LAYOUT, NTMAX, TILE_E, PREFETCH, UNROLL, EPI>(a, t0, step, nmine);
 }
 
 // A ragged batch: runs of consecutive tiles of one instance each, listed
