@@ -1302,7 +1302,7 @@ struct Shape {
 // factors travel with its staged output and the store waves apply them.
 template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PREFETCH, int UNROLL, int EPI>
 __device__ __forceinline__ void contract_tiles(const ContractArgs& a, int64_t t0, int64_t g,
-                                               int64_t nmine) {
+                                               int64_t nmine, int tid) {
     static_assert(EPI == 0 || (PREFETCH & 8), "the dG epilogue runs in the store waves");
     extern __shared__ __align__(16) unsigned char lds[];
     using S = Shape<TILE_E, NTMAX, PREFETCH>;
@@ -1311,7 +1311,6 @@ __device__ __forceinline__ void contract_tiles(const ContractArgs& a, int64_t t0
     constexpr bool D_REG = (PREFETCH & 4) != 0;
     constexpr bool PF_O = (PREFETCH & 8) != 0;
 
-    const int tid = threadIdx.x;
     const int lane = tid & 63;
     // the same in every lane of a wave: scalar, so role branches and
     // per-wave LDS addresses stay in scalar registers
@@ -1509,6 +1508,28 @@ __device__ __forceinline__ void contract_tiles(const ContractArgs& a, int64_t t0
     }
 }
 
+// A structure read at an address that is the same in every lane, copied
+// word by word to scalar registers.
+template <class T>
+__device__ __forceinline__ T scalar_copy(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
+    constexpr int W = sizeof(T) / 4;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(p);
+    uint32_t w[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) w[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    T v;
+    __builtin_memcpy(&v, w, sizeof(T));
+    return v;
+}
+
+// A 64-bit value known to be the same in every lane, as a scalar.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // One contraction over the persistent grid of G work-groups: work-group b
 // takes tiles b, b + G, b + 2G, ... (cyclic order), or the consecutive
 // tiles b*c .. b*c + c - 1, c = ceil(ntiles / G) (blocked order).
@@ -1523,7 +1544,15 @@ __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void con
         step = 1;
         nmine = rest < 0 ? 0 : (rest < c ? rest : c);
     }
-    contract_tiles<PREC, LAYOUT, NTMAX, TILE_E, PREFETCH, UNROLL, EPI>(a, t0, step, nmine);
+    // The three values are the same in every lane; without the explicit
+    // broadcast the compiler keeps the selected values in vector registers,
+    // which made the element-major register-D kernels spill (bf16x3 tile 32:
+    // 108 -> 128 VGPRs and 76 bytes of scratch per lane).
+    t0 = uniform64(t0);
+    step = uniform64(step);
+    nmine = uniform64(nmine);
+    contract_tiles<PREC, LAYOUT, NTMAX, TILE_E, PREFETCH, UNROLL, EPI>(a, t0, step, nmine,
+                                                                       threadIdx.x);
 }
 
 // A ragged batch: runs of consecutive tiles of one instance each, listed
@@ -1545,14 +1574,24 @@ struct RunArgs {
 template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PREFETCH, int UNROLL>
 __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void contract_runs_kernel(
     RunArgs r) {
-    const int q0 = r.wg_first[blockIdx.x], q1 = r.wg_first[blockIdx.x + 1];
+    // The tables are read at addresses that are the same in every lane, but
+    // the loads are vector loads: without the copies to scalar registers the
+    // compiler keeps the run's arguments in vector registers (the kernels
+    // then need up to 40 more VGPRs than lpx_contract's and spill).
+    const int q0 = __builtin_amdgcn_readfirstlane(r.wg_first[blockIdx.x]);
+    const int q1 = __builtin_amdgcn_readfirstlane(r.wg_first[blockIdx.x + 1]);
     for (int q = q0; q < q1; ++q) {
         // every wave is past its last LDS access of the previous run
         if (q > q0) __syncthreads();
-        const Run run = r.runs[q];
-        const ContractArgs a = r.items[run.inst];
+        const Run run = scalar_copy(r.runs + q);
+        const ContractArgs a = scalar_copy(r.items + run.inst);
+        // The thread index passes through an empty asm statement, so nothing
+        // derived from it is computed once before the loop and kept live
+        // across every run (that raised the staged kernels to the VGPR cap).
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
         contract_tiles<PREC, LAYOUT, NTMAX, TILE_E, PREFETCH, UNROLL, 0>(a, run.first, 1,
-                                                                          run.count);
+                                                                          run.count, tid);
     }
 }
 
