@@ -436,21 +436,22 @@ def cpu_leg(seconds, data, gpu_chunks, small, extra_samples):
     parity["small_workload/fp32"] = oracle.rel_err(out, oracle.contract(D, u, "em", "fp32"))
     for entry in (extra_samples or {}).get("gemm", []):
         M, N, Kd = entry["shape"]
-        # timing sample: 48 rows of A (the three sampled rows repeated; the
-        # oracle's time does not depend on the values)
-        At = np.tile(entry["A"], (16, 1))
-        gflop = 2.0 * At.shape[0] * N * Kd
+        # timing sample: 192 rows of A (the three sampled rows repeated; the
+        # oracle's time does not depend on the values), 16 on one thread
+        At = np.tile(entry["A"], (64, 1))
+        gflop = 2.0 * N * Kd
         t_all = _timed(lambda: oracle.gemm(At, entry["B"], "fp32"))
         oracle.set_threads(1)
         try:
-            t_one = _timed(lambda: oracle.gemm(At[:8], entry["B"], "fp32"))
+            t_one = _timed(lambda: oracle.gemm(At[:16], entry["B"], "fp32"))
         finally:
             oracle.set_threads(nthreads)
         base.setdefault("gemm", []).append({
             "shape": [M, N, Kd], "unit": "TFLOP/s",
-            "value": gflop / t_all / 1e12, "single_thread": gflop / 6 / t_one / 1e12,
+            "value": gflop * At.shape[0] / t_all / 1e12,
+            "single_thread": gflop * 16 / t_one / 1e12,
             "sample": f"{At.shape[0]} rows of C, fp64 accumulation, {t_all:.2f} s on "
-                      f"{nthreads} threads; 8 rows, {t_one:.2f} s on one thread"})
+                      f"{nthreads} threads; 16 rows, {t_one:.2f} s on one thread"})
         for prec, C in entry["C"].items():
             ref = oracle.gemm(entry["A"], entry["B"], "fp32")
             parity[f"gemm {M}x{N}x{Kd}/{prec}"] = oracle.rel_err(C, ref)
