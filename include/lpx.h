@@ -465,8 +465,10 @@ lpx_status lpx_batch_submit(const lpx_contract_desc* items, const lpx_record* re
                             int32_t n, lpx_batch** h, void* stream);
 
 /* Batch autotuner: the instances are grouped by (K, Np, layout); for each
- * group every candidate record of `precision` (lpx_record_enumerate order)
- * that fits all of the group's instances is timed on the group alone, as a
+ * group every cyclic-order candidate record of `precision`
+ * (lpx_record_enumerate order; the batch ignores the tile order, so the
+ * blocked-order copies are not timed) that fits all of the group's
+ * instances is timed on the group alone, as a
  * batch built with that record for each of them -- `warmup` untimed
  * replays, then `reps` replays bracketed by HIP events on `stream`, median
  * kept -- and recs_out[i] (host array of n) receives the fastest record of

@@ -191,6 +191,8 @@ def test_batch_tune_groups_and_bitwise():
     assert len(recs) == len(items)
     for a, b in ((0, 1), (2, 3), (4, 5)):
         assert lpx.describe(recs[a]) == lpx.describe(recs[b])
+    # the batch ignores the tile order: only cyclic-order records are timed
+    assert all(r.order == 0 for r in recs)
     b = lpx.Batch(items, recs)
     torch.cuda.synchronize()
     check_batch(items, recs, host, {"fp32": "fp32"})
