@@ -39,8 +39,14 @@ namespace batchk {
 template <int PREC>
 __global__ __launch_bounds__(kern::kArrangeThreads) void arrange_list(
     const kern::ContractArgs* __restrict__ items, const int32_t* __restrict__ idx, int m) {
+    // constant-address-space reads: scalar loads, and the descriptors'
+    // pointers are known to point to global memory (see contract_runs_kernel)
+    typedef __attribute__((address_space(4))) const kern::ContractArgs CItem;
+    typedef __attribute__((address_space(4))) const int32_t CInt;
+    const CItem* citems = (const CItem*)items;
+    const CInt* cidx = (const CInt*)idx;
     for (int i = blockIdx.y; i < m; i += gridDim.y) {
-        const kern::ContractArgs a = items[idx[i]];
+        const kern::ContractArgs a = kern::load_args(citems + cidx[i]);
         kern::stage_d<PREC, kern::kArrangeThreads * kern::kArrangeBlocks>(
             a, const_cast<unsigned char*>(a.Darr),
             blockIdx.x * kern::kArrangeThreads + threadIdx.x);

@@ -311,22 +311,40 @@ struct Lds {
     static constexpr int UELEM_BYTES = PREC == LPX_FP32 ? 4 : 2;
 };
 
-template <int PREC>
-__device__ __forceinline__ Frag<PREC> d_frag_lds(const unsigned char* lds, int64_t nfrag,
-                                                 int idx) {
-    if constexpr (PREC == LPX_FP32) {
-        return {reinterpret_cast<const float*>(lds)[idx]};
-    } else if constexpr (PREC == LPX_BF16) {
-        return {reinterpret_cast<const bf16x8*>(lds)[idx]};
+// Element idx of an array of T at `base`: in LDS, or (GLOBAL) in global
+// memory.  The global case reads through a global-address-space pointer, so
+// the load is a global load even where the compiler cannot trace the
+// pointer to a kernel argument (the batch reads it from its descriptor
+// table; a generic pointer there gives flat loads, which also count against
+// the LDS wait counter).
+template <class T, bool GLOBAL>
+__device__ __forceinline__ T load_elem(const unsigned char* base, int64_t idx) {
+    if constexpr (GLOBAL) {
+        typedef __attribute__((address_space(1))) const T GT;
+        return ((GT*)base)[idx];
     } else {
-        const bf16x8* p = reinterpret_cast<const bf16x8*>(lds);
-        return {p[idx], p[nfrag + idx]};
+        return reinterpret_cast<const T*>(base)[idx];
     }
 }
 
+// D fragments in MFMA operand order: staged in LDS, or (GLOBAL) the same
+// arrangement in global memory.
+template <int PREC, bool GLOBAL = false>
+__device__ __forceinline__ Frag<PREC> d_frag_lds(const unsigned char* lds, int64_t nfrag,
+                                                 int idx) {
+    if constexpr (PREC == LPX_FP32) {
+        return {load_elem<float, GLOBAL>(lds, idx)};
+    } else if constexpr (PREC == LPX_BF16) {
+        return {load_elem<bf16x8, GLOBAL>(lds, idx)};
+    } else {
+        return {load_elem<bf16x8, GLOBAL>(lds, idx), load_elem<bf16x8, GLOBAL>(lds, nfrag + idx)};
+    }
+}
+
+template <bool GLOBAL = false>
 __device__ __forceinline__ f4 d_quad_lds(const unsigned char* lds, int p, int Q, int nsteps,
                                          int lane) {
-    return reinterpret_cast<const f4*>(lds)[(p * nsteps + 4 * Q) * 16 + lane];
+    return load_elem<f4, GLOBAL>(lds, (p * nsteps + 4 * Q) * 16 + lane);
 }
 
 template <int PREC>
@@ -1030,7 +1048,8 @@ constexpr int pmax_mode() {
 }
 
 template <int PREC, int LAYOUT, int NTMAX, bool PF_D, bool PF_U, int TILE_E, int WPE, int UNROLL,
-          bool PF_O = false, bool MASK = true, int PM = pmax_cap<NTMAX, WPE>()>
+          bool PF_O = false, bool MASK = true, int PM = pmax_cap<NTMAX, WPE>(),
+          bool DGLOBAL = false>
 __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsigned char* lds,
                                               const float* ut, int row0, int64_t eb0, int part,
                                               int lane, float* os = nullptr) {
@@ -1059,7 +1078,7 @@ __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsig
             for (int q = 0; q < PMAX; ++q) {
                 Frag<PREC> df;
                 if constexpr (PF_D)
-                    df = d_frag_lds<PREC>(lds, nfrag, (pp[q] * a.nsteps + s) * 64 + lane);
+                    df = d_frag_lds<PREC, DGLOBAL>(lds, nfrag, (pp[q] * a.nsteps + s) * 64 + lane);
                 else
                     df = d_frag_global<PREC>(a, pp[q], s, lane);
                 if constexpr (LAYOUT == LPX_ELEMENT_MAJOR)
@@ -1082,7 +1101,7 @@ __device__ __forceinline__ void block_compute(const ContractArgs& a, const unsig
 #pragma unroll
                 for (int q = 0; q < PMAX; ++q) {
                     if constexpr (PF_D)
-                        dq[q] = d_quad_lds(lds, pp[q], Q, a.nsteps, lane);
+                        dq[q] = d_quad_lds<DGLOBAL>(lds, pp[q], Q, a.nsteps, lane);
                     else
                         dq[q] = d_quad_global(a, pp[q], Q, lane);
                 }
@@ -1345,8 +1364,8 @@ __device__ __forceinline__ void contract_tiles(const ContractArgs& a, int64_t t0
                     if (e0 + 16 * eblk >= a.E) continue;  // uniform per wave; no barrier below
                     // D from LDS, or from its arrangement in global memory
                     block_compute<PREC, LAYOUT, NTMAX, true, false, TILE_E, S::WPE, UNROLL, false,
-                                  true, decltype(pm)::value>(a, PF_D ? lds : a.Darr, nullptr, 0,
-                                                             e0 + 16 * eblk, part, lane);
+                                  true, decltype(pm)::value, !PF_D>(
+                        a, PF_D ? lds : a.Darr, nullptr, 0, e0 + 16 * eblk, part, lane);
                 }
             });
         }
@@ -1488,7 +1507,7 @@ __device__ __forceinline__ void contract_tiles(const ContractArgs& a, int64_t t0
                         auto run = [&](auto mask) {
                             // D from LDS, or from its arrangement in global memory
                             block_compute<PREC, LAYOUT, NTMAX, true, true, TILE_E, S::WPE, UNROLL,
-                                          PF_O, decltype(mask)::value, decltype(pm)::value>(
+                                          PF_O, decltype(mask)::value, decltype(pm)::value, !PF_D>(
                                 a, PF_D ? lds : a.Darr, ring + (n & 3) * a.ldu, row0,
                                 tile * TILE_E + row0, part, lane, oring + (n & 1) * a.ldo);
                         };
@@ -1508,19 +1527,36 @@ __device__ __forceinline__ void contract_tiles(const ContractArgs& a, int64_t t0
     }
 }
 
-// A structure read at an address that is the same in every lane, copied
-// word by word to scalar registers.
-template <class T>
-__device__ __forceinline__ T scalar_copy(const T* p) {
-    static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
-    constexpr int W = sizeof(T) / 4;
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(p);
-    uint32_t w[W];
-#pragma unroll
-    for (int i = 0; i < W; ++i) w[i] = __builtin_amdgcn_readfirstlane(src[i]);
-    T v;
-    __builtin_memcpy(&v, w, sizeof(T));
-    return v;
+// The arguments of one contraction read from a table in the constant
+// address space, field by field (a class object in another address space
+// cannot be copied whole): scalar loads, and the pointers read are taken
+// to point to global memory.
+template <class CItem>
+__device__ __forceinline__ ContractArgs load_args(const CItem* p) {
+    static_assert(sizeof(ContractArgs) == 120, "load_args copies every field");
+    ContractArgs a;
+    a.D = p->D;
+    a.u = p->u;
+    a.out = p->out;
+    a.Darr = p->Darr;
+    a.E = p->E;
+    a.ntiles = p->ntiles;
+    a.K = p->K;
+    a.Np = p->Np;
+    a.nt = p->nt;
+    a.nsteps = p->nsteps;
+    a.ldu = p->ldu;
+    a.nrb = p->nrb;
+    a.np_div.m = p->np_div.m;
+    a.np_div.sh = p->np_div.sh;
+    a.ldo = p->ldo;
+    a.G = p->G;
+    a.ldo_g = p->ldo_g;
+    a.np_vec = p->np_vec;
+    a.e_vec = p->e_vec;
+    a.stream_out = p->stream_out;
+    a.blocked = p->blocked;
+    return a;
 }
 
 // A 64-bit value known to be the same in every lane, as a scalar.
@@ -1574,24 +1610,31 @@ struct RunArgs {
 template <int PREC, int LAYOUT, int NTMAX, int TILE_E, int PREFETCH, int UNROLL>
 __global__ __launch_bounds__((Shape<TILE_E, NTMAX, PREFETCH>::THREADS)) void contract_runs_kernel(
     RunArgs r) {
-    // The tables are read at addresses that are the same in every lane, but
-    // the loads are vector loads: without the copies to scalar registers the
-    // compiler keeps the run's arguments in vector registers (the kernels
-    // then need up to 40 more VGPRs than lpx_contract's and spill).
-    const int q0 = __builtin_amdgcn_readfirstlane(r.wg_first[blockIdx.x]);
-    const int q1 = __builtin_amdgcn_readfirstlane(r.wg_first[blockIdx.x + 1]);
+    // The tables are read through constant-address-space pointers: they do
+    // not change during the launch, so the compiler loads them with scalar
+    // loads into scalar registers, and it takes the pointers read from the
+    // descriptors to point to global memory (global loads and stores; as
+    // generic pointers they gave flat accesses, which also count against the
+    // LDS wait counter, and vector copies of every argument).
+    typedef __attribute__((address_space(4))) const ContractArgs CItem;
+    typedef __attribute__((address_space(4))) const Run CRun;
+    typedef __attribute__((address_space(4))) const int32_t CInt;
+    const CItem* items = (const CItem*)r.items;
+    const CRun* runs = (const CRun*)r.runs;
+    const CInt* wg_first = (const CInt*)r.wg_first;
+    const int q0 = wg_first[blockIdx.x], q1 = wg_first[blockIdx.x + 1];
     for (int q = q0; q < q1; ++q) {
         // every wave is past its last LDS access of the previous run
         if (q > q0) __syncthreads();
-        const Run run = scalar_copy(r.runs + q);
-        const ContractArgs a = scalar_copy(r.items + run.inst);
+        const int64_t first = runs[q].first;
+        const int32_t inst = runs[q].inst, count = runs[q].count;
+        const ContractArgs a = load_args(items + inst);
         // The thread index passes through an empty asm statement, so nothing
         // derived from it is computed once before the loop and kept live
         // across every run (that raised the staged kernels to the VGPR cap).
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
-        contract_tiles<PREC, LAYOUT, NTMAX, TILE_E, PREFETCH, UNROLL, 0>(a, run.first, 1,
-                                                                          run.count, tid);
+        contract_tiles<PREC, LAYOUT, NTMAX, TILE_E, PREFETCH, UNROLL, 0>(a, first, 1, count, tid);
     }
 }
 
