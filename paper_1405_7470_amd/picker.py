@@ -211,7 +211,7 @@ def evaluate(shapes, model_path, flush_mb=512, reps=5, log=print):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default="gpurun_out/picker")
+    ap.add_argument("--out", default="picker_out")
     ap.add_argument("--train-shapes", type=int, default=560)
     ap.add_argument("--eval-shapes", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=300)
