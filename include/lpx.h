@@ -450,7 +450,7 @@ typedef struct lpx_batch lpx_batch;
  *     the least-loaded work-group.  Records that read D from memory get its
  *     MFMA-order arrangement from the graph's first nodes (into device
  *     memory the batch owns).  The nodes are captured once into a HIP graph,
- *     the group launches on two parallel branches.
+ *     the group launches on four parallel branches.
  *   *h != NULL, items != NULL: items must have the batch's n and per-item
  *     K, Np, E and layout (pointers may change); copies the updated
  *     descriptor table and replays the graph on `stream`.

@@ -12,7 +12,7 @@
 // -- only between runs.  Records that read D from memory get its MFMA-order
 // arrangement from the first graph nodes, into a buffer the batch owns.
 //
-// The nodes (arrangements, then one launch per group on two parallel
+// The nodes (arrangements, then one launch per group on kBranches parallel
 // branches) are captured once into a HIP graph on library-owned streams;
 // lpx_batch_submit replays it on the caller's stream after copying the
 // (possibly updated) descriptor table.
@@ -85,6 +85,11 @@ struct Group {
 // few enough that a run is long against its start-up (pipeline fill, D).
 constexpr int kRunsPerWg = 3;
 constexpr int64_t kMinRunTiles = 4;
+// Parallel branches of the graph the group launches are spread over
+// (512-instance batch, per-instance learned records, 24 groups: 2 branches
+// 4.61 ms, 3 4.04, 4 3.98, 6 4.02, 8 3.94; batch-tuned records, 5 groups:
+// 3.54, 3.60, 3.43, 3.55, 3.56 ms).
+constexpr int kBranches = 4;
 
 }  // namespace batchk
 }  // namespace lpx
@@ -108,7 +113,7 @@ struct lpx_batch {
     int64_t total_tiles = 0, lds_max = 0;
     int grid_total = 0;
     hipStream_t cap_stream = nullptr;
-    hipStream_t side_stream = nullptr;  // the graph's second branch during capture
+    hipStream_t side[kBranches - 1] = {};  // the graph's other branches during capture
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t copied = nullptr;     // the table copy of the last submit is done
@@ -126,7 +131,8 @@ void free_batch(lpx_batch* b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-    if (b->side_stream) (void)hipStreamDestroy(b->side_stream);
+    for (hipStream_t s : b->side)
+        if (s) (void)hipStreamDestroy(s);
     if (b->copied) (void)hipEventDestroy(b->copied);
     if (b->dev_items) (void)hipFree(b->dev_items);
     if (b->dev_runs) (void)hipFree(b->dev_runs);
@@ -291,11 +297,15 @@ lpx_status create(const lpx_contract_desc* items, const lpx_record* recs, int32_
          (e = hipMalloc((void**)&b->dev_idx, sizeof(int32_t) * idx.size())) != hipSuccess) ||
         (darr_total > 0 && (e = hipMalloc((void**)&b->darr, (size_t)darr_total)) != hipSuccess) ||
         (e = hipEventCreateWithFlags(&b->copied, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipStreamCreateWithFlags(&b->side_stream, hipStreamNonBlocking)) != hipSuccess) {
+        (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
         free_batch(b);
         return hip_err(e, "batch allocation");
     }
+    for (hipStream_t& s : b->side)
+        if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) {
+            free_batch(b);
+            return hip_err(e, "batch allocation");
+        }
     for (int32_t i = 0; i < n; ++i)
         if (darr_off[i] >= 0) b->host_items[i].Darr = b->darr + darr_off[i];
     // the run, work-group and arrangement tables never change: copied once
@@ -330,14 +340,19 @@ lpx_status create(const lpx_contract_desc* items, const lpx_record* recs, int32_
                                    b->dev_items, list, m);
             if (le == hipSuccess) le = hipGetLastError();
         }
-        // The group launches on two branches of the graph (largest groups
-        // first, each to the branch with less work), so that one group's
-        // tail overlaps work of the other branch.
-        hipEvent_t fork = nullptr, join = nullptr;
+        // The group launches on kBranches branches of the graph (largest
+        // groups first, each to the branch with the least work), so that one
+        // group's tail overlaps work of the other branches.
+        hipStream_t br_stream[kBranches];
+        br_stream[0] = b->cap_stream;
+        for (int k = 1; k < kBranches; ++k) br_stream[k] = b->side[k - 1];
+        hipEvent_t fork = nullptr, join[kBranches] = {};
         if (le == hipSuccess) le = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-        if (le == hipSuccess) le = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+        for (int k = 1; k < kBranches; ++k)
+            if (le == hipSuccess) le = hipEventCreateWithFlags(&join[k], hipEventDisableTiming);
         if (le == hipSuccess) le = hipEventRecord(fork, b->cap_stream);
-        if (le == hipSuccess) le = hipStreamWaitEvent(b->side_stream, fork, 0);
+        for (int k = 1; k < kBranches; ++k)
+            if (le == hipSuccess) le = hipStreamWaitEvent(br_stream[k], fork, 0);
         std::vector<std::pair<double, int>> order;  // (-work, group)
         for (int gi = 0; gi < (int)b->groups.size(); ++gi) {
             double w = 0;
@@ -346,24 +361,29 @@ lpx_status create(const lpx_contract_desc* items, const lpx_record* recs, int32_
             order.push_back({-w, gi});
         }
         std::sort(order.begin(), order.end());
-        double load[2] = {0.0, 0.0};
+        double load[kBranches] = {};
         for (const auto& o : order) {
             const Group& G = b->groups[o.second];
-            const int br = load[0] <= load[1] ? 0 : 1;
+            int br = 0;
+            for (int k = 1; k < kBranches; ++k)
+                if (load[k] < load[br]) br = k;
             load[br] -= o.first;
             kern::RunArgs ra{b->dev_items, b->dev_runs + G.run_off, b->dev_wg + G.wg_off};
             void* kargs[] = {&ra};
             const hipError_t ge = hipLaunchKernel(
                 reinterpret_cast<const void*>(G.fn), dim3((unsigned)G.grid), dim3(G.threads),
-                kargs, (size_t)G.lds, br == 0 ? b->cap_stream : b->side_stream);
+                kargs, (size_t)G.lds, br_stream[br]);
             if (le == hipSuccess) le = ge;
         }
-        if (le == hipSuccess) le = hipEventRecord(join, b->side_stream);
-        if (le == hipSuccess) le = hipStreamWaitEvent(b->cap_stream, join, 0);
+        for (int k = 1; k < kBranches; ++k) {
+            if (le == hipSuccess) le = hipEventRecord(join[k], br_stream[k]);
+            if (le == hipSuccess) le = hipStreamWaitEvent(b->cap_stream, join[k], 0);
+        }
         e = hipStreamEndCapture(b->cap_stream, &b->graph);
         if (e == hipSuccess && le != hipSuccess) e = le;
         if (fork) (void)hipEventDestroy(fork);
-        if (join) (void)hipEventDestroy(join);
+        for (hipEvent_t j : join)
+            if (j) (void)hipEventDestroy(j);
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) { free_batch(b); return hip_err(e, "batch graph capture"); }
